@@ -1,0 +1,26 @@
+"""FP64 CPU oracle for the sparsified thin-wire MoM method (TEST INFRASTRUCTURE).
+
+This package is the independent reference that every GPU result is judged
+against.  It is test infrastructure only: the product path never imports it;
+only the tests, the package smoke check and the benchmark's CPU-baseline leg
+may call it.  It shares no code with the HIP path (no kernels, headers,
+tables or helpers); both sides take their inputs from the seeded generator
+in ``paper_2410_03060_amd.workloads``, which holds none of the method's
+arithmetic.
+
+Everything is plain NumPy/SciPy in complex128:
+
+* ``mom``     -- segmentation, Galerkin impedance blocks (eqs. 5-8 with the
+                 free-space Green's function of Sec. II-A), the S-NFC near set
+                 and block-sparse matrix (eq. 9), excitation (eq. 4) and the
+                 far-field / RCS functional;
+* ``solve``   -- dense LU ("entire coupling"), sparse direct and FP64 GMRES;
+* ``mlp``     -- reference forward/backward of the learned initial guess.
+
+Pins (tests/test_oracle_pins.py) tie each function to something outside the
+oracle itself: the resonant half-wave dipole RCS, Galerkin symmetry,
+reciprocity, the optical theorem, segment-refinement convergence, the
+orientation-averaged dipole RCS quoted in Sec. III-B, closed-form integrals
+checked by adaptive quadrature, and brute force on tiny inputs.
+"""
+from . import mom, solve  # noqa: F401
