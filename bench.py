@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the S-NFC thin-wire MoM hot path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input:
+neighbour search (chaff_build_cloud), impedance fill (chaff_fill_Z),
+excitation + preconditioned GMRES with FP64 refinement (chaff_solve) and
+monostatic RCS (chaff_rcs), with the inputs already resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--config c5] [--gpus 1]
+
+Prints ONE JSON line.  `value` = solved (cloud, incidence) systems per
+second over the K timed steps; a system counts as solved when its FP64 true
+relative residual is <= tol (1e-6).  `roofline` is the dominant kernel of the
+timed region: its algorithmic work (bytes or flops, computed by the library
+from the exact sizes of each launch) over its HIP-event time measured on the
+launch stream.  `cpu_baseline` is the FP64 oracle timed on a bounded sample
+of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed) peak, TFLOP/s
+
+CONFIGS = {
+    # name: (workload factory kwargs, prec, restart, description)
+    "c1": dict(prec="c128", restart=60, desc="64 half-wave wires, 10-wavelength cube, d_c=2 lambda, "
+                                              "1 incidence, complex128"),
+    "c2": dict(prec="c64", restart=30, desc="2,000 wires, Gaussian sigma=15 lambda, d_c=1.5 lambda, "
+                                             "1 incidence, complex64 + FP64 refinement"),
+    "c3": dict(prec="c64", restart=20, desc="20,000-wire Gaussian cloud + 16 side clouds (500-5,000 wires), "
+                                             "d_c=2 lambda, 360 azimuth incidences, one launch per stage"),
+    "c4_eval": dict(prec="c64", restart=20, desc="100,000 wires, uniform sphere R=40 lambda, d_c=1.5 lambda, "
+                                                  "8 incidences"),
+    "c5": dict(prec="c64", restart=10, desc="1,000,000 wires (7M unknowns), uniform sphere R=50 lambda, "
+                                             "d_c=1 lambda, 64 azimuth incidences, complex64 + FP64 refinement"),
+}
+
+
+def make_workload(name):
+    from paper_2410_03060_amd import workloads as W
+    if name == "c1":
+        return W.c1()
+    if name == "c2":
+        return W.c2()
+    if name == "c3":
+        return W.c3()
+    if name == "c4_eval":
+        return W.c4_eval()
+    if name == "c5":
+        return W.c5()
+    raise SystemExit(f"unknown config {name}")
+
+
+def sub_sphere(cloud, n_keep):
+    """The n_keep wires closest to the centroid of cloud 0 (same density)."""
+    import numpy as np
+
+    from paper_2410_03060_amd import workloads as W
+    lo, hi = int(cloud.cloud_off[0]), int(cloud.cloud_off[1])
+    c = cloud.center[lo:hi]
+    d = np.linalg.norm(c - c.mean(axis=0), axis=1)
+    idx = np.sort(np.argsort(d)[:n_keep]) + lo
+    return W.single_cloud(cloud.center[idx], cloud.tangent[idx], cloud.length[idx], cloud.wavelength,
+                          cloud.d_c, cloud.radius[idx])
+
+
+def cpu_baseline(wl, n_sample: int = 4000, r_sample: int = 8):
+    """Oracle (FP64 CPU) on a bounded sample, scaled to the full workload.
+
+    Sample: the n_sample wires of the first cloud nearest its centroid (same
+    density) and the first r_sample incidences.  The oracle's setup (near
+    set, Galerkin fill, SuperLU factorisation) and its per-incidence work
+    (triangular solves + RCS) are timed separately and each is scaled by the
+    wire ratio; the full workload then costs setup + R * per-incidence.
+    """
+    from oracle import mom, solve as osolve
+    import scipy.sparse.linalg as spla
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    cloud = wl.cloud
+    n_full = cloud.n
+    R = wl.inc.k_hat.shape[0]
+    n_s = int(min(cloud.cloud_off[1] - cloud.cloud_off[0], n_sample))
+    sample = sub_sphere(cloud, n_s) if n_s < cloud.n else cloud
+    r_s = min(R, r_sample)
+    kh, eh = wl.inc.k_hat[:r_s], wl.inc.e_hat[:r_s]
+    t0 = time.perf_counter()
+    Zs, _ = mom.snfc_matrix(sample)
+    lu = spla.splu(Zs.tocsc())
+    t1 = time.perf_counter()
+    u = mom.excitation(sample, kh, eh)
+    x = lu.solve(u)
+    mom.monostatic_rcs(sample, x, kh, eh)
+    t2 = time.perf_counter()
+    scale = n_full / sample.n
+    t_full = (t1 - t0) * scale + (t2 - t1) / r_s * R * scale
+    systems = cloud.n_clouds * R
+    return {"value": systems / t_full, "unit": "solved angles/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{sample.n} of {n_full} wires (first cloud, nearest its centroid) and {r_s} of {R} "
+                      f"incidences: setup {t1 - t0:.2f} s + {r_s} incidences {t2 - t1:.2f} s, each scaled "
+                      f"by the wire ratio {scale:.1f}; full workload estimated at {t_full:.1f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c5", choices=sorted(CONFIGS))
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--restart", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); this build has no multi-GPU "
+              "path. Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2410_03060_amd import binding as B
+
+    torch.cuda.set_device(0)
+    cfg = CONFIGS[a.config]
+    prec = B.C64 if cfg["prec"] == "c64" else B.C128
+    restart = a.restart or cfg["restart"]
+    wl = make_workload(a.config)
+    geom = B.upload(wl.cloud)
+    kh = torch.as_tensor(wl.inc.k_hat, device="cuda")
+    eh = torch.as_tensor(wl.inc.e_hat, device="cuda")
+    R = kh.shape[0]
+    opts = B.solve_opts(tol=a.tol, restart=restart, max_cycles=60, prec=prec)
+    torch.cuda.synchronize()
+
+    def step():
+        cl = B.build_cloud(geom)
+        Z, P = B.fill_Z(cl, prec)
+        X, info = B.solve(cl, Z, P, kh, eh, opts)
+        sig = B.rcs(cl, X, -kh, eh, monostatic=True)
+        return cl, X, info, sig
+
+    print(f"[bench] config={a.config} N={wl.cloud.n} clouds={wl.cloud.n_clouds} R={R} warmup={a.warmup} "
+          f"steps={a.steps}", file=sys.stderr, flush=True)
+    for w in range(a.warmup):
+        _, _, info, _ = step()
+        print(f"[bench] warmup {w}: cycles={info['cycles']} iters={info['iterations']} "
+              f"res={info['max_rel_residual']:.2e} solve={info['seconds']:.3f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    B.profile_enable(True)
+    t0 = time.perf_counter()
+    solved = 0
+    infos = []
+    for k in range(a.steps):
+        cl, X, info, sig = step()
+        infos.append(info)
+        solved += int((info["rel_res"] <= a.tol).sum())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.profile_enable(False)
+    prof = B.profile_read()
+    dt = t1 - t0
+    sig_np = sig.cpu().numpy()
+    assert np.all(np.isfinite(sig_np))
+
+    # dominant kernel of the timed region and its roofline
+    ranked = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])
+    name, k = ranked[0]
+    sec = k["total_ms"] / 1e3
+    if k["unit"] == "flop":
+        ach = k["work"] / sec / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_PEAK_TFLOPS, "traffic": None}
+    else:
+        ach = k["work"] / sec / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    roof.update({"kernel": name, "launches": k["launches"], "avg_ms": k["total_ms"] / k["launches"],
+                 "work_per_launch": k["work"] / k["launches"]})
+    kernels = {n: {"ms_total": round(v["total_ms"], 3), "launches": v["launches"],
+                   ("GB/s" if v["unit"] == "B" else "TFLOP/s"):
+                       (round(v["work"] / (v["total_ms"] / 1e3) / (1e9 if v["unit"] == "B" else 1e12), 2)
+                        if v["work"] > 0 and v["total_ms"] > 0 else None)}
+               for n, v in ranked[:12]}
+    if a.kernels:
+        for n, v in ranked:
+            print(f"  {n:28s} {v['launches']:7d} {v['total_ms']:10.3f} ms", file=sys.stderr)
+
+    out = {
+        "metric": "solved angles/sec at <=0.1 dB RCS error; fill GFLOP/s and SpMM GB/s vs peak",
+        "value": solved / dt,
+        "unit": "solved angles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if prec == B.C64 else "c128",
+        "data": "synthetic",
+        "config": {"workload": a.config, "description": cfg["desc"], "wires": int(wl.cloud.n),
+                   "clouds": int(wl.cloud.n_clouds), "rhs": int(R), "unknowns": int(wl.cloud.n * 7),
+                   "nnzb": int(cl.nnzb), "pairs": int(cl.n_pairs), "restart": restart, "tol": a.tol},
+        "solver": {"cycles": infos[-1]["cycles"], "iterations": infos[-1]["iterations"],
+                   "max_rel_residual": infos[-1]["max_rel_residual"],
+                   "systems_per_step": int(wl.cloud.n_clouds * R), "solved_total": solved},
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": None,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

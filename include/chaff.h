@@ -1,0 +1,226 @@
+/*
+ * chaff.h -- C ABI of the MI355X (gfx950) hot path of the sparsified thin-wire
+ * method of moments for chaff clouds (S-NFC: sparsification via neglecting
+ * far-field coupling).
+ *
+ * Problem statement (Sec. II-A): N thin perfectly conducting straight wires of
+ * arbitrary centre, orientation, length and radius are illuminated by plane
+ * waves.  Each wire is cut into 8 equal segments carrying 7 rooftop unknowns
+ * (eq. 2 and its footnote; the paper's own runs use 19 unknowns per wire).
+ * The Galerkin EFIE system Z x = u (eqs. 3-8) is kept only on wire pairs
+ * whose centroid distance is <= d_c (eq. 9) and solved iteratively with a
+ * block-diagonal preconditioner (Sec. II-B); the far-field functional then
+ * gives monostatic and bistatic radar cross sections (Sec. III).
+ *
+ * Conventions shared by every call
+ *  - Time convention exp(+j w t); G(R) = exp(-j k R)/(4 pi R) with the thin-wire
+ *    reduced distance R = sqrt(|r - r'|^2 + a^2) between wire axes
+ *    (a^2 = (a_p^2 + a_p'^2)/2 between wires of different radius).
+ *  - Units are metres; only the wavelength enters (k = 2 pi / wavelength).
+ *  - Unknown order is wire-major in the CALLER's wire order:
+ *    n = p*7 + q, q = 0..6 counted from the -L/2 end along the tangent.
+ *    Multi-RHS vectors are row-major [N*7][R] (element (n, r) at n*R + r).
+ *  - x is the solution of Z x = u with u the tested incident field
+ *    u_n = int L_n (t_n . e) exp(-j k k_hat . r) ds (eq. 4 without its
+ *    -(j/(w mu0)) factor).  The physical current is -(j/(w mu0)) x, and for a
+ *    unit-amplitude wave sigma = |w^T x|^2 / (4 pi), w the far-field weights.
+ *  - Complex numbers are interleaved (re, im): CHAFF_C64 = 2 x float,
+ *    CHAFF_C128 = 2 x double.
+ *  - Pointers are DEVICE pointers unless marked [host].  The library never
+ *    allocates device memory: data-dependent scratch is a caller workspace
+ *    whose size is queried first.  Every call is asynchronous on `stream`
+ *    (a hipStream_t) except where a host read-back is stated.
+ *  - Errors: every entry point returns a chaff_status; inputs are validated
+ *    on the host before any launch; no C++ exception crosses the ABI; the
+ *    text of the last error of the calling thread is chaff_last_error().
+ */
+#ifndef CHAFF_H
+#define CHAFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct ihipStream_t;                  /* hipStream_t is struct ihipStream_t* */
+typedef struct ihipStream_t* chaff_stream;
+
+typedef enum {
+    CHAFF_OK = 0,
+    CHAFF_EINVAL = -1,       /* bad argument (null pointer, size, non-unit tangent ...) */
+    CHAFF_EWORKSPACE = -2,   /* workspace too small / pattern capacity exceeded */
+    CHAFF_EHIP = -3,         /* a HIP runtime call failed */
+    CHAFF_ESINGULAR = -4,    /* a self block could not be inverted */
+    CHAFF_ENOCONV = -5       /* solver hit its iteration cap; X holds the last iterate */
+} chaff_status;
+
+typedef enum { CHAFF_C64 = 0, CHAFF_C128 = 1 } chaff_prec;
+
+typedef struct chaff_cloud_s* chaff_cloud;   /* opaque handle, host memory owned by the library */
+
+#define CHAFF_NSEG 8          /* segments per wire */
+#define CHAFF_NB 7            /* unknowns per wire */
+
+typedef struct {
+    int64_t n_wires;          /* total wires over all clouds, >= 1 */
+    int32_t n_clouds;         /* independent clouds, >= 1 (pairs never cross clouds) */
+    int32_t n_seg;            /* must be CHAFF_NSEG */
+    double  wavelength;       /* metres, > 0 */
+    double  d_c;              /* coupling threshold (eq. 9), metres, >= 0; INFINITY = dense */
+    int32_t quad_mutual;      /* Gauss-Legendre nodes per segment, different wires (1..8; 4) */
+    int32_t quad_self;        /* Gauss-Legendre nodes per segment, same wire (2..8; 8) */
+    int64_t max_nnzb;         /* capacity of the block pattern held in the build workspace */
+} chaff_params;
+
+/* ------------------------------------------------------------------ build
+ * Neighbour search (eq. 9): stored blocks are the diagonal plus every ordered
+ * pair (p, p') of one cloud with ((dx*dx + dy*dy) + dz*dz) <= d_c*d_c in
+ * IEEE double without fused multiply-add (dx = c_p'.x - c_p.x, ...).
+ * Wires are reordered internally along a Morton curve of a cell grid
+ * (cell side >= d_c); the block pattern (CSR of 7x7 blocks) is stored in that
+ * internal order and its permutation is returned by chaff_get_info.
+ *
+ * chaff_build_workspace_bytes: [host only] bytes the build workspace needs.
+ * chaff_build_cloud:
+ *   cloud_off  [host] [n_clouds+1] wire offsets of the clouds, cloud_off[0]=0,
+ *              non-decreasing, cloud_off[n_clouds] = n_wires.
+ *   center [N][3], tangent [N][3] (unit, |t|^2 within 1e-10 of 1),
+ *   length [N] (> 0), radius [N] (> 0, < length/8): double, device.
+ *   ws / ws_bytes: device workspace of at least chaff_build_workspace_bytes;
+ *              it holds the cloud's internal arrays and must stay allocated
+ *              and untouched until chaff_destroy.  The geometry arrays may be
+ *              freed after the call.
+ *   nnzb       [host out] number of stored blocks.  If it exceeds
+ *              p->max_nnzb the call returns CHAFF_EWORKSPACE with *nnzb set
+ *              and no handle; call again with a larger capacity.
+ *   out        [host out] the handle.
+ *   Synchronises `stream` twice (grid bounds and block count read-back).
+ */
+size_t chaff_build_workspace_bytes(int64_t n_wires, int32_t n_clouds, int64_t max_nnzb);
+chaff_status chaff_build_cloud(const chaff_params* p, const int64_t* cloud_off,
+                               const double* center, const double* tangent,
+                               const double* length, const double* radius,
+                               void* ws, size_t ws_bytes, int64_t* nnzb,
+                               chaff_stream stream, chaff_cloud* out);
+
+typedef struct {
+    int64_t n_wires, nnzb, n_pairs;      /* n_pairs = unique off-diagonal pairs (p < p') */
+    int32_t n_clouds, n_seg;
+    double  wavelength, d_c;
+    const int64_t* row_ptr;              /* [N+1] device, internal order */
+    const int32_t* col_idx;              /* [nnzb] device, internal wire indices, ascending per row */
+    const int32_t* perm;                 /* [N] device: internal wire i is caller wire perm[i] */
+    const int64_t* diag_pos;             /* [N] device: block index of (i, i) */
+} chaff_cloud_info;
+chaff_status chaff_get_info(chaff_cloud c, chaff_cloud_info* info /* [host out] */);
+
+/* ------------------------------------------------------------------ fill
+ * Galerkin impedance blocks (eqs. 5-8) on the stored pattern, with the
+ * rooftop assembly of Sec. II-A: tensor Gauss-Legendre per segment pair
+ * (quad_mutual nodes between wires, quad_self on one wire); on one wire the
+ * static part 1/(4 pi R) of touching and identical segments is integrated in
+ * closed form ("analytic singularity extraction").  Z = Z^T block-wise: each
+ * unique pair is computed once and stored twice.
+ *   Z    [nnzb][7][7] complex (prec), internal block order, row-major blocks.
+ *   Pinv [N][7][7] complex (prec) or NULL: inverse of every self block
+ *        (block-diagonal preconditioner of Sec. II-B), internal wire order.
+ * Returns CHAFF_ESINGULAR (after the stream completes) if a self block has a
+ * zero pivot.
+ */
+chaff_status chaff_fill_Z(chaff_cloud c, chaff_prec prec, void* Z, void* Pinv,
+                          chaff_stream stream);
+
+/* ------------------------------------------------------------------ solve
+ * Excitation (eq. 4) for R plane waves, then right block-Jacobi
+ * preconditioned restarted GMRES on the S-NFC system, one independent system
+ * per (cloud, RHS), all advanced in lockstep so each sparse product serves
+ * every right-hand side.  With prec = CHAFF_C64 the Krylov work is complex
+ * FP32 and every restart cycle is an iterative-refinement sweep against the
+ * FP64 true residual u - Z x (Z the stored matrix, FP64 accumulation).  With
+ * CHAFF_C128 everything is FP64.  Stops when every system has
+ * ||u - Z x||_2 <= tol * ||u||_2 over its cloud's rows.
+ */
+typedef struct {
+    double  tol;              /* relative FP64 residual target per system (1e-6) */
+    double  inner_tol;        /* relative reduction asked of one FP32 cycle (1e-4) */
+    int32_t restart;          /* GMRES(m) cycle length, 1..200 (30) */
+    int32_t max_cycles;       /* restart/refinement cycles (50) */
+    int32_t use_x0;           /* 1: X holds an initial guess on entry */
+    int32_t prec;             /* chaff_prec of Z, Pinv and the Krylov vectors */
+    int32_t spmm_variant;     /* -1: autotuned/heuristic choice; else a fixed kernel variant */
+    int32_t reserved;
+} chaff_solve_opts;
+
+typedef struct {
+    int32_t cycles;           /* refinement sweeps (= GMRES restart cycles) run */
+    int32_t iterations;       /* Arnoldi steps summed over cycles */
+    double  max_rel_residual; /* final max over systems of the FP64 relative residual */
+    double  seconds;          /* host wall time of the call */
+} chaff_solve_stats;
+
+size_t chaff_solve_workspace_bytes(chaff_cloud c, const chaff_solve_opts* o, int64_t n_rhs);
+/*   Z, Pinv  from chaff_fill_Z with the same prec.
+ *   k_hat, e_hat [R][3] double: propagation direction and polarisation (unit).
+ *   X        [N*7][R] complex double, caller order; input guess if use_x0.
+ *   ws       device workspace of chaff_solve_workspace_bytes.
+ *   rel_res  [host out, optional] [n_clouds*R] final relative residuals (cloud-major).
+ *   Host-synchronising: reads residual estimates once per Arnoldi step. */
+chaff_status chaff_solve(chaff_cloud c, const chaff_solve_opts* o, const void* Z,
+                         const void* Pinv, const double* k_hat, const double* e_hat,
+                         int64_t n_rhs, void* X, void* ws, size_t ws_bytes,
+                         chaff_solve_stats* st, double* rel_res, chaff_stream stream);
+
+/* Excitation alone: U [N*7][R] complex double (caller order), eq. (4) without
+ * its -(j/(w mu0)) factor, closed-form triangle transform. */
+chaff_status chaff_excitation(chaff_cloud c, const double* k_hat, const double* e_hat,
+                              int64_t n_rhs, void* U, chaff_stream stream);
+
+/* Block-sparse product Y = Z X on the internal order (the matvec of the
+ * Krylov solver, complexity O(b_mean N) of Sec. II-B).
+ *   X, Y [N*7][s] complex (prec), internal order, row-major.
+ *   variant -1 = the tuned/heuristic choice. */
+chaff_status chaff_spmm(chaff_cloud c, chaff_prec prec, const void* Z, const void* X,
+                        void* Y, int64_t s, int32_t variant, chaff_stream stream);
+
+/* ------------------------------------------------------------------ rcs
+ * Far field of the currents X (caller order, complex double [N*7][R]):
+ * S = sum_n w_n(r_hat, e) x_n with w_n = int L_n (t_n . e) exp(+j k r_hat . r) ds,
+ * sigma = |S|^2/(4 pi) [m^2], summed separately over each cloud.
+ *   monostatic = 1: M == R, observation m pairs with RHS m;
+ *                   sigma [n_clouds][R].
+ *   monostatic = 0: every (RHS, direction); sigma [n_clouds][R][M].
+ *   obs_dir, obs_pol [M][3] double (unit; pol transverse to dir).
+ *   ws: device workspace of chaff_rcs_workspace_bytes. */
+size_t chaff_rcs_workspace_bytes(chaff_cloud c, int64_t n_rhs, int64_t n_dirs, int32_t monostatic);
+chaff_status chaff_rcs(chaff_cloud c, const void* X, int64_t n_rhs, const double* obs_dir,
+                       const double* obs_pol, int64_t n_dirs, int32_t monostatic,
+                       double* sigma, void* ws, size_t ws_bytes, chaff_stream stream);
+
+/* ------------------------------------------------------------------ profiling
+ * Per-kernel timing of the library's own launches with HIP events recorded
+ * on the launch stream (used for roofline figures).  chaff_profile_enable(1)
+ * clears the record and starts; (0) stops.  chaff_profile_read waits for the
+ * recorded events and writes one aggregate per kernel name (at most max_out)
+ * into out [host]; returns the number written. */
+typedef struct {
+    char    name[48];
+    int64_t launches;
+    double  total_ms, min_ms, max_ms;
+    double  work;             /* algorithmic work summed over launches (see work_is_flops) */
+    int32_t work_is_flops;    /* 1: work counts flops; 0: HBM bytes */
+    int32_t reserved;
+} chaff_kernel_time;
+chaff_status chaff_profile_enable(int32_t on);
+int32_t chaff_profile_read(chaff_kernel_time* out, int32_t max_out);
+
+/* ------------------------------------------------------------------ misc */
+void chaff_destroy(chaff_cloud c);
+const char* chaff_last_error(void);
+const char* chaff_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHAFF_H */

@@ -1,0 +1,366 @@
+"""ctypes binding of libchaff (include/chaff.h): argument marshalling only.
+
+Every step of the hot path runs in the gfx950 kernels of libchaff.so; this
+module only allocates device memory with PyTorch, passes raw pointers and the
+current HIP stream, and turns status codes into exceptions.  There is no CPU
+fallback: if the library is missing the import of a binding function fails.
+
+Function names follow the C ABI: ``build_cloud``, ``fill_Z``, ``solve``,
+``rcs``, ``excitation``, ``spmm``, ``destroy``, ``last_error``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime libchaff binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchaff.so")
+
+OK, EINVAL, EWORKSPACE, EHIP, ESINGULAR, ENOCONV = 0, -1, -2, -3, -4, -5
+C64, C128 = 0, 1
+NB = 7
+NSEG = 8
+
+
+class ChaffError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"chaff status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("n_wires", C.c_int64), ("n_clouds", C.c_int32), ("n_seg", C.c_int32),
+                ("wavelength", C.c_double), ("d_c", C.c_double),
+                ("quad_mutual", C.c_int32), ("quad_self", C.c_int32), ("max_nnzb", C.c_int64)]
+
+
+class CloudInfo(C.Structure):
+    _fields_ = [("n_wires", C.c_int64), ("nnzb", C.c_int64), ("n_pairs", C.c_int64),
+                ("n_clouds", C.c_int32), ("n_seg", C.c_int32),
+                ("wavelength", C.c_double), ("d_c", C.c_double),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("perm", C.c_void_p),
+                ("diag_pos", C.c_void_p)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("restart", C.c_int32),
+                ("max_cycles", C.c_int32), ("use_x0", C.c_int32), ("prec", C.c_int32),
+                ("spmm_variant", C.c_int32), ("reserved", C.c_int32)]
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("min_ms", C.c_double), ("max_ms", C.c_double), ("work", C.c_double),
+                ("work_is_flops", C.c_int32), ("reserved", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("iterations", C.c_int32),
+                ("max_rel_residual", C.c_double), ("seconds", C.c_double)]
+
+
+_lib = None
+
+EXPORTS = {
+    "chaff_build_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int64]),
+    "chaff_build_cloud": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_int64), C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                    C.POINTER(C.c_int64), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "chaff_get_info": (C.c_int, [C.c_void_p, C.POINTER(CloudInfo)]),
+    "chaff_fill_Z": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chaff_solve_workspace_bytes": (C.c_size_t, [C.c_void_p, C.POINTER(SolveOpts), C.c_int64]),
+    "chaff_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t,
+                              C.POINTER(SolveStats), C.c_void_p, C.c_void_p]),
+    "chaff_excitation": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "chaff_spmm": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                             C.c_int32, C.c_void_p]),
+    "chaff_rcs_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int64, C.c_int64, C.c_int32]),
+    "chaff_rcs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                            C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "chaff_destroy": (None, [C.c_void_p]),
+    "chaff_profile_enable": (C.c_int, [C.c_int32]),
+    "chaff_profile_read": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "chaff_last_error": (C.c_char_p, []),
+    "chaff_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libchaff.so (built in-tree by paper_2410_03060_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2410_03060_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().chaff_last_error().decode()
+
+
+def _check(st: int):
+    if st != OK:
+        raise ChaffError(st, last_error())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_f64(a, device):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.array(a, dtype=np.float64, order="C", copy=True), device=device)
+
+
+def _2d(a):
+    if isinstance(a, torch.Tensor):
+        return a.reshape(-1, 3)
+    return np.atleast_2d(a)
+
+
+# --------------------------------------------------------------------------- handle
+
+@dataclass
+class Cloud:
+    handle: C.c_void_p
+    ws: torch.Tensor          # build workspace (holds the pattern; keep alive)
+    n: int
+    n_clouds: int
+    nnzb: int
+    n_pairs: int
+    wavelength: float
+    d_c: float
+    device: torch.device
+
+    def info(self) -> CloudInfo:
+        inf = CloudInfo()
+        _check(lib().chaff_get_info(self.handle, C.byref(inf)))
+        return inf
+
+    def pattern(self):
+        """(row_ptr, col_idx, perm, diag_pos) as host numpy arrays (internal order)."""
+        inf = self.info()
+
+        def grab(ptr, count, dtype):
+            t = torch.empty(count, dtype=dtype, device=self.device)
+            nbytes = count * t.element_size()
+            if nbytes:
+                _copy_ptr(t, ptr, nbytes)
+            return t.cpu().numpy()
+
+        return (grab(inf.row_ptr, self.n + 1, torch.int64), grab(inf.col_idx, self.nnzb, torch.int32),
+                grab(inf.perm, self.n, torch.int32), grab(inf.diag_pos, self.n, torch.int64))
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().chaff_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def _copy_ptr(dst: torch.Tensor, src_ptr: int, nbytes: int):
+    """Device-to-device copy from a raw library pointer into a tensor (HIP runtime)."""
+    hip = _hip()
+    st = torch.cuda.current_stream().cuda_stream
+    rc = hip.hipMemcpyAsync(C.c_void_p(dst.data_ptr()), C.c_void_p(src_ptr), C.c_size_t(nbytes),
+                            C.c_int(3), C.c_void_p(st))
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+
+
+_hiprt = None
+
+
+def _hip():
+    global _hiprt
+    if _hiprt is None:
+        _hiprt = C.CDLL("libamdhip64.so.7", mode=C.RTLD_GLOBAL)
+        _hiprt.hipMemcpyAsync.restype = C.c_int
+        _hiprt.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+    return _hiprt
+
+
+@dataclass
+class DeviceGeometry:
+    """Wire geometry already resident in device memory (float64 tensors)."""
+    center: torch.Tensor
+    tangent: torch.Tensor
+    length: torch.Tensor
+    radius: torch.Tensor
+    cloud_off: np.ndarray
+    wavelength: float
+    d_c: float
+
+    @property
+    def n(self) -> int:
+        return int(self.center.shape[0])
+
+    @property
+    def n_clouds(self) -> int:
+        return int(len(self.cloud_off) - 1)
+
+
+def upload(cloud, device="cuda") -> DeviceGeometry:
+    device = torch.device(device)
+    return DeviceGeometry(_dev_f64(cloud.center, device), _dev_f64(cloud.tangent, device),
+                          _dev_f64(cloud.length, device), _dev_f64(cloud.radius, device),
+                          np.asarray(cloud.cloud_off, dtype=np.int64), float(cloud.wavelength),
+                          float(cloud.d_c))
+
+
+def build_cloud(cloud, device="cuda", max_nnzb: int | None = None, quad_mutual: int = 4,
+                quad_self: int = 8) -> Cloud:
+    """Neighbour search and internal layout for a (multi-)cloud (chaff_build_cloud).
+
+    ``cloud`` is a host workload (numpy arrays, uploaded here) or a
+    DeviceGeometry already in device memory.
+    """
+    if not isinstance(cloud, DeviceGeometry):
+        cloud = upload(cloud, device)
+    device = cloud.center.device
+    n = cloud.n
+    nc = cloud.n_clouds
+    c, t, L, a = cloud.center, cloud.tangent, cloud.length, cloud.radius
+    off = (C.c_int64 * (nc + 1))(*[int(v) for v in cloud.cloud_off])
+    if max_nnzb is None:
+        max_nnzb = n * n if not math.isfinite(cloud.d_c) else min(n * n, 24 * n + 64)
+    for _ in range(2):
+        p = Params(n, nc, NSEG, float(cloud.wavelength), float(cloud.d_c), quad_mutual, quad_self,
+                   int(max_nnzb))
+        need = lib().chaff_build_workspace_bytes(n, nc, int(max_nnzb))
+        if need == 0:
+            raise ChaffError(EINVAL, "bad sizes for the build workspace")
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+        nnzb = C.c_int64(0)
+        h = C.c_void_p()
+        st = lib().chaff_build_cloud(C.byref(p), off, _ptr(c), _ptr(t), _ptr(L), _ptr(a), _ptr(ws),
+                                     need, C.byref(nnzb), _stream(), C.byref(h))
+        if st == EWORKSPACE and nnzb.value > max_nnzb:
+            max_nnzb = int(nnzb.value)
+            continue
+        _check(st)
+        out = Cloud(h, ws, n, nc, int(nnzb.value), 0, float(cloud.wavelength), float(cloud.d_c), device)
+        out.n_pairs = int(out.info().n_pairs)
+        return out
+    raise ChaffError(EWORKSPACE, last_error())
+
+
+def fill_Z(cl: Cloud, prec: int = C64, with_pinv: bool = True):
+    """Impedance blocks [nnzb,7,7] and inverse self blocks [N,7,7] (chaff_fill_Z)."""
+    dt = torch.complex64 if prec == C64 else torch.complex128
+    Z = torch.empty((cl.nnzb, NB, NB), dtype=dt, device=cl.device)
+    P = torch.empty((cl.n, NB, NB), dtype=dt, device=cl.device) if with_pinv else None
+    _check(lib().chaff_fill_Z(cl.handle, prec, _ptr(Z), _ptr(P), _stream()))
+    return Z, P
+
+
+def solve_opts(tol=1e-6, inner_tol=1e-4, restart=30, max_cycles=50, use_x0=False, prec=C64,
+               spmm_variant=-1) -> SolveOpts:
+    return SolveOpts(tol, inner_tol, restart, max_cycles, int(use_x0), prec, spmm_variant, 0)
+
+
+def solve(cl: Cloud, Z, Pinv, k_hat, e_hat, opts: SolveOpts | None = None, x0=None,
+          raise_on_noconv: bool = True):
+    """Excitation + preconditioned restarted GMRES (+ FP64 refinement) (chaff_solve).
+
+    Returns (X [N*7, R] complex128 in caller wire order, stats dict).
+    """
+    opts = opts or solve_opts()
+    kh = _dev_f64(_2d(k_hat), cl.device)
+    eh = _dev_f64(_2d(e_hat), cl.device)
+    R = kh.shape[0]
+    if x0 is not None:
+        X = x0.to(device=cl.device, dtype=torch.complex128).contiguous().clone()
+        opts.use_x0 = 1
+    else:
+        X = torch.empty((cl.n * NB, R), dtype=torch.complex128, device=cl.device)
+    need = lib().chaff_solve_workspace_bytes(cl.handle, C.byref(opts), R)
+    if need == 0:
+        raise ChaffError(EINVAL, last_error() or "bad solve options")
+    ws = torch.empty(need, dtype=torch.uint8, device=cl.device)
+    stats = SolveStats()
+    rel = np.zeros(cl.n_clouds * R, dtype=np.float64)
+    st = lib().chaff_solve(cl.handle, C.byref(opts), _ptr(Z), _ptr(Pinv), _ptr(kh), _ptr(eh), R,
+                           _ptr(X), _ptr(ws), need, C.byref(stats),
+                           rel.ctypes.data_as(C.c_void_p), _stream())
+    info = {"cycles": stats.cycles, "iterations": stats.iterations,
+            "max_rel_residual": stats.max_rel_residual, "seconds": stats.seconds,
+            "rel_res": rel.reshape(cl.n_clouds, R), "status": st}
+    if st != OK and not (st == ENOCONV and not raise_on_noconv):
+        _check(st)
+    return X, info
+
+
+def excitation(cl: Cloud, k_hat, e_hat):
+    kh = _dev_f64(_2d(k_hat), cl.device)
+    eh = _dev_f64(_2d(e_hat), cl.device)
+    U = torch.empty((cl.n * NB, kh.shape[0]), dtype=torch.complex128, device=cl.device)
+    _check(lib().chaff_excitation(cl.handle, _ptr(kh), _ptr(eh), kh.shape[0], _ptr(U), _stream()))
+    return U
+
+
+def spmm(cl: Cloud, Z, X, prec: int = C64, variant: int = -1, Y=None):
+    """Y = Z X on the internal order (chaff_spmm); X is [N*7, s]."""
+    if Y is None:
+        Y = torch.empty_like(X)
+    _check(lib().chaff_spmm(cl.handle, prec, _ptr(Z), _ptr(X), _ptr(Y), X.shape[1], variant, _stream()))
+    return Y
+
+
+def rcs(cl: Cloud, X, obs_dir, obs_pol, monostatic: bool):
+    """sigma per cloud (chaff_rcs): [n_clouds, R] monostatic or [n_clouds, R, M] bistatic."""
+    d = _dev_f64(_2d(obs_dir), cl.device)
+    p = _dev_f64(_2d(obs_pol), cl.device)
+    R = X.shape[1]
+    M = d.shape[0]
+    need = lib().chaff_rcs_workspace_bytes(cl.handle, R, M, int(monostatic))
+    ws = torch.empty(need, dtype=torch.uint8, device=cl.device)
+    shape = (cl.n_clouds, R) if monostatic else (cl.n_clouds, R, M)
+    sig = torch.empty(shape, dtype=torch.float64, device=cl.device)
+    _check(lib().chaff_rcs(cl.handle, _ptr(X), R, _ptr(d), _ptr(p), M, int(monostatic), _ptr(sig),
+                           _ptr(ws), need, _stream()))
+    return sig
+
+
+def destroy(cl: Cloud):
+    if cl.handle:
+        lib().chaff_destroy(cl.handle)
+        cl.handle = None
+
+
+def profile_enable(on: bool):
+    _check(lib().chaff_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{kernel: dict(launches, total_ms, min_ms, max_ms, work, unit)} of the tracked launches."""
+    buf = (KernelTime * 64)()
+    n = lib().chaff_profile_read(C.cast(buf, C.c_void_p), 64)
+    return {buf[i].name.decode(): dict(launches=int(buf[i].launches), total_ms=buf[i].total_ms,
+                                       min_ms=buf[i].min_ms, max_ms=buf[i].max_ms, work=buf[i].work,
+                                       unit="flop" if buf[i].work_is_flops else "B")
+            for i in range(n)}
+
+
+def version() -> str:
+    return lib().chaff_version().decode()

@@ -1,0 +1,254 @@
+// extern "C" entry points of libchaff: host-side validation, error text,
+// and dispatch to the gfx950 kernels.  Validation never touches the HIP
+// runtime, so argument errors are reported on machines without a GPU.
+#include <cmath>
+#include <cstdio>
+#include <exception>
+#include <new>
+
+#include "common.hpp"
+
+namespace chaff {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+chaff_status fail(chaff_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+// Gauss-Legendre on [0,1]: Newton iteration on P_q from the Chebyshev guesses.
+void gauss_legendre01(int q, double* x, double* w) {
+    for (int i = 0; i < MAXQ; ++i) x[i] = w[i] = 0.0;
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < q; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (q + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= q; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            double pq = q == 1 ? z : p1;
+            double pqm1 = q == 1 ? 1.0 : p0;
+            dp = q * (z * pq - pqm1) / (z * z - 1.0);
+            double dz = pq / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        // recompute derivative at the converged node
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= q; ++k) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        double pq = q == 1 ? z : p1, pqm1 = q == 1 ? 1.0 : p0;
+        dp = q * (z * pq - pqm1) / (z * z - 1.0);
+        // node on [-1,1] is z (descending); map to [0,1] ascending
+        x[i] = 0.5 * (z + 1.0);
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // 2/((1-z^2)P'^2) on [-1,1], halved
+    }
+    // ascending order
+    for (int i = 0; i < q; ++i)
+        for (int j = i + 1; j < q; ++j)
+            if (x[j] < x[i]) {
+                std::swap(x[i], x[j]);
+                std::swap(w[i], w[j]);
+            }
+}
+
+size_t build_workspace_bytes(int64_t n, int32_t n_clouds, int64_t max_nnzb);
+chaff_status build_cloud(const chaff_params* p, const int64_t* cloud_off, const double* center,
+                         const double* tangent, const double* length, const double* radius, void* ws,
+                         size_t ws_bytes, int64_t* nnzb_out, hipStream_t st, Cloud** out);
+chaff_status fill_Z(Cloud* c, chaff_prec prec, void* Z, void* Pinv, hipStream_t st);
+size_t solve_workspace_bytes(const Cloud* c, const chaff_solve_opts* o, int64_t s);
+chaff_status solve(Cloud* c, const chaff_solve_opts* o, const void* Z, const void* Pinv, const double* k_hat,
+                   const double* e_hat, int64_t s, void* X, void* ws, size_t ws_bytes, chaff_solve_stats* st_out,
+                   double* rel_res, hipStream_t st);
+chaff_status excitation(Cloud* c, const double* k_hat, const double* e_hat, int64_t s, void* U, hipStream_t st);
+chaff_status spmm_public(Cloud* c, chaff_prec prec, const void* Z, const void* X, void* Y, int64_t s, int variant,
+                         hipStream_t st);
+size_t rcs_workspace_bytes(const Cloud* c, int64_t R, int64_t M, int32_t mono);
+chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const double* pol, int64_t M, int32_t mono,
+                 double* sigma, void* ws, size_t ws_bytes, hipStream_t st);
+
+}  // namespace chaff
+
+using namespace chaff;
+
+struct chaff_cloud_s {
+    Cloud c;
+};
+
+#define CHAFF_GUARD_BEGIN try {
+#define CHAFF_GUARD_END                                                   \
+    }                                                                     \
+    catch (const std::bad_alloc&) {                                       \
+        return fail(CHAFF_EINVAL, "host allocation failed");              \
+    }                                                                     \
+    catch (const std::exception& ex) {                                    \
+        return fail(CHAFF_EINVAL, std::string("internal error: ") + ex.what()); \
+    }                                                                     \
+    catch (...) {                                                         \
+        return fail(CHAFF_EINVAL, "internal error");                      \
+    }
+
+static chaff_status check_params(const chaff_params* p, const int64_t* cloud_off) {
+    if (!p) return fail(CHAFF_EINVAL, "params is NULL");
+    if (p->n_wires < 1 || p->n_wires > (int64_t)INT32_MAX / 8)
+        return fail(CHAFF_EINVAL, "n_wires must be in [1, 2^28)");
+    if (p->n_clouds < 1 || p->n_clouds > 65535) return fail(CHAFF_EINVAL, "n_clouds must be in [1, 65535]");
+    if (p->n_seg != NSEG) return fail(CHAFF_EINVAL, "n_seg must be 8 (7 unknowns per wire)");
+    if (!(p->wavelength > 0) || !std::isfinite(p->wavelength)) return fail(CHAFF_EINVAL, "wavelength must be > 0");
+    if (!(p->d_c >= 0)) return fail(CHAFF_EINVAL, "d_c must be >= 0 (INFINITY for the dense matrix)");
+    if (p->quad_mutual < 1 || p->quad_mutual > MAXQ) return fail(CHAFF_EINVAL, "quad_mutual must be in [1, 8]");
+    if (p->quad_self < 2 || p->quad_self > MAXQ) return fail(CHAFF_EINVAL, "quad_self must be in [2, 8]");
+    if (p->max_nnzb < p->n_wires) return fail(CHAFF_EINVAL, "max_nnzb must be >= n_wires (diagonal blocks)");
+    if (!cloud_off) return fail(CHAFF_EINVAL, "cloud_off is NULL");
+    if (cloud_off[0] != 0) return fail(CHAFF_EINVAL, "cloud_off[0] must be 0");
+    for (int c = 0; c < p->n_clouds; ++c)
+        if (cloud_off[c + 1] < cloud_off[c]) return fail(CHAFF_EINVAL, "cloud_off must be non-decreasing");
+    if (cloud_off[p->n_clouds] != p->n_wires) return fail(CHAFF_EINVAL, "cloud_off[n_clouds] must equal n_wires");
+    return CHAFF_OK;
+}
+
+extern "C" {
+
+const char* chaff_last_error(void) { return g_last_error.c_str(); }
+const char* chaff_version(void) { return "chaff-gfx950 1.0"; }
+
+size_t chaff_build_workspace_bytes(int64_t n_wires, int32_t n_clouds, int64_t max_nnzb) {
+    if (n_wires < 1 || n_clouds < 1 || max_nnzb < n_wires) return 0;
+    return build_workspace_bytes(n_wires, n_clouds, max_nnzb);
+}
+
+chaff_status chaff_build_cloud(const chaff_params* p, const int64_t* cloud_off, const double* center,
+                               const double* tangent, const double* length, const double* radius, void* ws,
+                               size_t ws_bytes, int64_t* nnzb, chaff_stream stream, chaff_cloud* out) {
+    CHAFF_GUARD_BEGIN
+    chaff_status s = check_params(p, cloud_off);
+    if (s != CHAFF_OK) return s;
+    if (!center || !tangent || !length || !radius) return fail(CHAFF_EINVAL, "geometry pointer is NULL");
+    if (!nnzb || !out) return fail(CHAFF_EINVAL, "nnzb/out is NULL");
+    if (!ws) return fail(CHAFF_EINVAL, "workspace is NULL");
+    *out = nullptr;
+    *nnzb = 0;
+    size_t need = build_workspace_bytes(p->n_wires, p->n_clouds, p->max_nnzb);
+    if (ws_bytes < need)
+        return fail(CHAFF_EWORKSPACE, "build workspace too small: need " + std::to_string(need));
+    Cloud* c = nullptr;
+    s = build_cloud(p, cloud_off, center, tangent, length, radius, ws, ws_bytes, nnzb, (hipStream_t)stream, &c);
+    if (s != CHAFF_OK) return s;
+    chaff_cloud_s* h = new chaff_cloud_s;
+    h->c = *c;
+    delete c;
+    *out = h;
+    return CHAFF_OK;
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_get_info(chaff_cloud h, chaff_cloud_info* info) {
+    if (!h || !info) return fail(CHAFF_EINVAL, "NULL handle/info");
+    const Cloud& c = h->c;
+    info->n_wires = c.n;
+    info->nnzb = c.nnzb;
+    info->n_pairs = c.n_pairs;
+    info->n_clouds = c.n_clouds;
+    info->n_seg = NSEG;
+    info->wavelength = c.wavelength;
+    info->d_c = c.d_c;
+    info->row_ptr = c.row_ptr;
+    info->col_idx = c.col_idx;
+    info->perm = c.perm;
+    info->diag_pos = c.diag_pos;
+    return CHAFF_OK;
+}
+
+chaff_status chaff_fill_Z(chaff_cloud h, chaff_prec prec, void* Z, void* Pinv, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h) return fail(CHAFF_EINVAL, "NULL handle");
+    if (!Z) return fail(CHAFF_EINVAL, "Z is NULL");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
+    return fill_Z(&h->c, prec, Z, Pinv, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+static chaff_status check_opts(const chaff_solve_opts* o) {
+    if (!o) return fail(CHAFF_EINVAL, "opts is NULL");
+    if (!(o->tol > 0) || !(o->tol < 1)) return fail(CHAFF_EINVAL, "tol must be in (0, 1)");
+    if (!(o->inner_tol > 0) || !(o->inner_tol < 1)) return fail(CHAFF_EINVAL, "inner_tol must be in (0, 1)");
+    if (o->restart < 1 || o->restart > 200) return fail(CHAFF_EINVAL, "restart must be in [1, 200]");
+    if (o->max_cycles < 1) return fail(CHAFF_EINVAL, "max_cycles must be >= 1");
+    if (o->prec != CHAFF_C64 && o->prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
+    if (o->spmm_variant < -1 || o->spmm_variant > 2) return fail(CHAFF_EINVAL, "spmm_variant must be in [-1, 2]");
+    return CHAFF_OK;
+}
+
+size_t chaff_solve_workspace_bytes(chaff_cloud h, const chaff_solve_opts* o, int64_t n_rhs) {
+    if (!h || !o || n_rhs < 1 || check_opts(o) != CHAFF_OK) return 0;
+    return solve_workspace_bytes(&h->c, o, n_rhs);
+}
+
+chaff_status chaff_solve(chaff_cloud h, const chaff_solve_opts* o, const void* Z, const void* Pinv,
+                         const double* k_hat, const double* e_hat, int64_t n_rhs, void* X, void* ws, size_t ws_bytes,
+                         chaff_solve_stats* st, double* rel_res, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h) return fail(CHAFF_EINVAL, "NULL handle");
+    chaff_status s = check_opts(o);
+    if (s != CHAFF_OK) return s;
+    if (!Z || !Pinv) return fail(CHAFF_EINVAL, "Z and Pinv are required");
+    if (!k_hat || !e_hat || !X || !ws) return fail(CHAFF_EINVAL, "NULL k_hat/e_hat/X/ws");
+    if (n_rhs < 1 || n_rhs > 65535) return fail(CHAFF_EINVAL, "n_rhs must be in [1, 65535]");
+    size_t need = solve_workspace_bytes(&h->c, o, n_rhs);
+    if (ws_bytes < need) return fail(CHAFF_EWORKSPACE, "solve workspace too small: need " + std::to_string(need));
+    return solve(&h->c, o, Z, Pinv, k_hat, e_hat, n_rhs, X, ws, ws_bytes, st, rel_res, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_excitation(chaff_cloud h, const double* k_hat, const double* e_hat, int64_t n_rhs, void* U,
+                              chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !k_hat || !e_hat || !U) return fail(CHAFF_EINVAL, "NULL argument");
+    if (n_rhs < 1) return fail(CHAFF_EINVAL, "n_rhs must be >= 1");
+    return excitation(&h->c, k_hat, e_hat, n_rhs, U, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_spmm(chaff_cloud h, chaff_prec prec, const void* Z, const void* X, void* Y, int64_t s,
+                        int32_t variant, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !Z || !X || !Y) return fail(CHAFF_EINVAL, "NULL argument");
+    if (s < 1 || s > 65535) return fail(CHAFF_EINVAL, "s must be in [1, 65535]");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "bad prec");
+    if (variant < -1 || variant > 2) return fail(CHAFF_EINVAL, "variant must be in [-1, 2]");
+    return spmm_public(&h->c, prec, Z, X, Y, s, variant, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+size_t chaff_rcs_workspace_bytes(chaff_cloud h, int64_t n_rhs, int64_t n_dirs, int32_t monostatic) {
+    if (!h || n_rhs < 1 || n_dirs < 1) return 0;
+    return rcs_workspace_bytes(&h->c, n_rhs, n_dirs, monostatic);
+}
+
+chaff_status chaff_rcs(chaff_cloud h, const void* X, int64_t n_rhs, const double* obs_dir, const double* obs_pol,
+                       int64_t n_dirs, int32_t monostatic, double* sigma, void* ws, size_t ws_bytes,
+                       chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !X || !obs_dir || !obs_pol || !sigma || !ws) return fail(CHAFF_EINVAL, "NULL argument");
+    if (n_rhs < 1 || n_dirs < 1) return fail(CHAFF_EINVAL, "n_rhs and n_dirs must be >= 1");
+    if (monostatic && n_dirs != n_rhs) return fail(CHAFF_EINVAL, "monostatic needs n_dirs == n_rhs");
+    if (!monostatic && n_rhs > 65535) return fail(CHAFF_EINVAL, "bistatic n_rhs must be <= 65535");
+    size_t need = rcs_workspace_bytes(&h->c, n_rhs, n_dirs, monostatic);
+    if (ws_bytes < need) return fail(CHAFF_EWORKSPACE, "rcs workspace too small: need " + std::to_string(need));
+    return rcs(&h->c, X, n_rhs, obs_dir, obs_pol, n_dirs, monostatic, sigma, ws, ws_bytes, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+void chaff_destroy(chaff_cloud h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+// Far-field reduction: monostatic and bistatic RCS (Sec. III).
+//
+// S(r_hat, e) = sum_p (t_p . e) exp(+j k r_hat . c_p) D_p sinc^2(b D_p / 2)
+//               * sum_q x_{p,q} exp(+j b s_q),     b = k r_hat . t_p,
+// the closed-form triangle transform of every rooftop; sigma = |S|^2/(4 pi).
+// Everything is FP64 (the phase k r_hat . c_p reaches hundreds of radians).
+//
+//  * monostatic: direction m pairs with RHS m; blocks reduce fixed wire
+//    chunks of one cloud with wave64 shuffles + LDS, then a second pass sums
+//    the chunks of each cloud in order (no atomics, bit-reproducible);
+//  * bistatic: one thread per direction, the chunk's wires and currents
+//    staged in LDS, partial sums per chunk, same second pass.
+#include "common.hpp"
+#include "prof.hpp"
+
+#include <algorithm>
+
+namespace chaff {
+
+constexpr double PI_F = 3.14159265358979323846;
+constexpr int FF_CHUNK = 256;   // wires per chunk
+
+__device__ __forceinline__ double sinc_ff(double x) {
+    return fabs(x) < 1e-4 ? 1.0 - x * x / 6.0 : sin(x) / x;
+}
+
+// one wire's contribution for direction (rx,ry,rz), polarisation (ex,ey,ez)
+__device__ __forceinline__ c128 wire_term(const Wire& w, const c128* __restrict__ x, int64_t xstride, double k,
+                                          double rx, double ry, double rz, double ex, double ey, double ez) {
+    const double tp = w.tx * ex + w.ty * ey + w.tz * ez;
+    const double b = k * (rx * w.tx + ry * w.ty + rz * w.tz);
+    const double ph0 = k * (rx * w.cx + ry * w.cy + rz * w.cz);
+    const double D = w.len / NSEG;
+    const double sc = sinc_ff(0.5 * b * D);
+    const double env = tp * D * sc * sc;
+    // exp(j b s_q), s_q = -L/2 + (q+1) D, by recurrence in q
+    double s1, c1, sd, cd;
+    sincos(ph0 + b * (-0.5 * w.len + D), &s1, &c1);
+    sincos(b * D, &sd, &cd);
+    c128 ph = {c1, s1};
+    const c128 step = {cd, sd};
+    c128 acc = {0, 0};
+    for (int q = 0; q < NB; ++q) {
+        cfma(acc, ph, x[q * xstride]);
+        ph = cmul(ph, step);
+    }
+    return cscale(acc, env);
+}
+
+// partial[chunk][r] for monostatic pairs (dir r, rhs r); X caller order
+__global__ __launch_bounds__(256) void k_mono(const Wire* __restrict__ wires, const int32_t* __restrict__ perm,
+                                              const int64_t* __restrict__ chunk_w0, int n_chunks, int64_t R,
+                                              const c128* __restrict__ X, const double* __restrict__ dir,
+                                              const double* __restrict__ pol, double k, c128* __restrict__ part) {
+    __shared__ double red_re[256], red_im[256];
+    const int ch = blockIdx.x;
+    const int64_t r = blockIdx.y;
+    const int64_t w0 = chunk_w0[ch], w1 = chunk_w0[ch + 1];
+    const double rx = dir[3 * r], ry = dir[3 * r + 1], rz = dir[3 * r + 2];
+    const double ex = pol[3 * r], ey = pol[3 * r + 1], ez = pol[3 * r + 2];
+    c128 acc = {0, 0};
+    for (int64_t i = w0 + threadIdx.x; i < w1; i += blockDim.x) {
+        const Wire w = wires[i];
+        const c128* xp = X + (int64_t)perm[i] * NB * R + r;
+        acc = cadd(acc, wire_term(w, xp, R, k, rx, ry, rz, ex, ey, ez));
+    }
+    red_re[threadIdx.x] = acc.re;
+    red_im[threadIdx.x] = acc.im;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            red_re[threadIdx.x] += red_re[threadIdx.x + st];
+            red_im[threadIdx.x] += red_im[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)ch * R + r] = c128{red_re[0], red_im[0]};
+}
+
+// partial[chunk][r][m] for every (rhs r, direction m)
+__global__ __launch_bounds__(256) void k_bistatic(const Wire* __restrict__ wires, const int32_t* __restrict__ perm,
+                                                  const int64_t* __restrict__ chunk_w0, int64_t R, int64_t M,
+                                                  const c128* __restrict__ X, const double* __restrict__ dir,
+                                                  const double* __restrict__ pol, double k, c128* __restrict__ part) {
+    __shared__ Wire sw[FF_CHUNK];
+    __shared__ c128 sx[FF_CHUNK * NB];
+    const int ch = blockIdx.y;
+    const int64_t r = blockIdx.z;
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w0 = chunk_w0[ch], w1 = chunk_w0[ch + 1];
+    const int nw = (int)(w1 - w0);
+    for (int t = threadIdx.x; t < nw; t += blockDim.x) {
+        sw[t] = wires[w0 + t];
+        const int64_t p = perm[w0 + t];
+        for (int q = 0; q < NB; ++q) sx[t * NB + q] = X[(p * NB + q) * R + r];
+    }
+    __syncthreads();
+    if (m >= M) return;
+    const double rx = dir[3 * m], ry = dir[3 * m + 1], rz = dir[3 * m + 2];
+    const double ex = pol[3 * m], ey = pol[3 * m + 1], ez = pol[3 * m + 2];
+    c128 acc = {0, 0};
+    for (int t = 0; t < nw; ++t) acc = cadd(acc, wire_term(sw[t], &sx[t * NB], 1, k, rx, ry, rz, ex, ey, ez));
+    part[((int64_t)ch * R + r) * M + m] = acc;
+}
+
+// sigma[cloud][j] = |sum over the cloud's chunks of part[chunk][j]|^2 / (4 pi), j < J
+__global__ void k_ff_finish(const c128* __restrict__ part, const int32_t* __restrict__ cloud_chunk_off,
+                            int n_clouds, int64_t J, double* __restrict__ sigma) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_clouds * J) return;
+    const int c = (int)(t / J);
+    const int64_t j = t - (int64_t)c * J;
+    c128 acc = {0, 0};
+    for (int ch = cloud_chunk_off[c]; ch < cloud_chunk_off[c + 1]; ++ch) acc = cadd(acc, part[(int64_t)ch * J + j]);
+    sigma[t] = (acc.re * acc.re + acc.im * acc.im) / (4.0 * PI_F);
+}
+
+static void ff_chunks(const Cloud* c, std::vector<int64_t>& w0, std::vector<int32_t>& coff) {
+    w0.clear();
+    coff.assign(c->n_clouds + 1, 0);
+    for (int k = 0; k < c->n_clouds; ++k) {
+        coff[k] = (int32_t)w0.size();
+        for (int64_t a = c->cloud_off[k]; a < c->cloud_off[k + 1]; a += FF_CHUNK) w0.push_back(a);
+    }
+    coff[c->n_clouds] = (int32_t)w0.size();
+}
+
+size_t rcs_workspace_bytes(const Cloud* c, int64_t R, int64_t M, int32_t mono) {
+    std::vector<int64_t> w0;
+    std::vector<int32_t> coff;
+    ff_chunks(c, w0, coff);
+    const int64_t nch = (int64_t)w0.size();
+    const int64_t J = mono ? R : R * M;
+    size_t b = align_up((nch + 1) * sizeof(int64_t), 256) + align_up((c->n_clouds + 1) * sizeof(int32_t), 256) +
+               align_up((size_t)std::max<int64_t>(nch, 1) * J * sizeof(c128), 256);
+    return b + 256;
+}
+
+chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const double* pol, int64_t M, int32_t mono,
+                 double* sigma, void* ws, size_t ws_bytes, hipStream_t st) {
+    std::vector<int64_t> w0;
+    std::vector<int32_t> coff;
+    ff_chunks(c, w0, coff);
+    const int nch = (int)w0.size();
+    const int64_t J = mono ? R : R * M;
+    Carve cv(ws, ws_bytes);
+    int64_t* d_w0 = cv.take<int64_t>(nch + 1);
+    int32_t* d_coff = cv.take<int32_t>(c->n_clouds + 1);
+    c128* part = cv.take<c128>((size_t)std::max(nch, 1) * J);
+    if (!cv.ok()) return fail(CHAFF_EWORKSPACE, "rcs workspace too small");
+    // chunk i covers wires [bounds[i], bounds[i+1]); chunks start at cloud
+    // boundaries, so the next chunk's start is always this chunk's end
+    std::vector<int64_t> bounds(w0);
+    bounds.push_back(c->n);
+    CHAFF_HIP(hipMemcpyAsync(d_w0, bounds.data(), bounds.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    CHAFF_HIP(hipMemcpyAsync(d_coff, coff.data(), coff.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const double k = 2.0 * PI_F / c->wavelength;
+    const c128* X = static_cast<const c128*>(Xv);
+    if (nch > 0) {
+        // monostatic: X read once + wire records; bistatic: 55 flops per wire and direction
+        ProfScope ps(mono ? "rcs_mono" : "rcs_bistatic", st,
+                     mono ? 16.0 * NB * (double)c->n * R + 64.0 * c->n : 55.0 * (double)c->n * R * M, !mono);
+        if (mono) {
+            hipLaunchKernelGGL(k_mono, dim3(nch, (unsigned)R), dim3(256), 0, st, (const Wire*)c->wires,
+                               (const int32_t*)c->perm, (const int64_t*)d_w0, nch, R, X, dir, pol, k, part);
+        } else {
+            dim3 grid((unsigned)((M + 255) / 256), nch, (unsigned)R);
+            hipLaunchKernelGGL(k_bistatic, grid, dim3(256), 0, st, (const Wire*)c->wires, (const int32_t*)c->perm,
+                               (const int64_t*)d_w0, R, M, X, dir, pol, k, part);
+        }
+        CHAFF_LAUNCH_CHECK();
+    }
+    const int64_t tot = (int64_t)c->n_clouds * J;
+    hipLaunchKernelGGL(k_ff_finish, dim3((unsigned)std::max<int64_t>(1, (tot + 255) / 256)), dim3(256), 0, st,
+                       (const c128*)part, (const int32_t*)d_coff, c->n_clouds, J, sigma);
+    CHAFF_LAUNCH_CHECK();
+    CHAFF_HIP(hipStreamSynchronize(st));  // host staging vectors go out of scope
+    return CHAFF_OK;
+}
+
+}  // namespace chaff

@@ -1,0 +1,383 @@
+// Galerkin impedance fill (eqs. 5-8) on the S-NFC pattern.
+//
+//  * Mutual blocks: one wave64 per unique wire pair (i < j).  Lane
+//    (alpha, beta) = (lane/8, lane%8) owns one of the 8 x 8 segment pairs and
+//    runs the Q x Q Gauss samples of G for it, accumulating the four
+//    first-order moments of the rooftop halves.  The pair separation and the
+//    segment offsets are formed in FP64 and rounded once; the samples run in
+//    the block precision R.  The 7 x 7 block is assembled with cross-lane
+//    permutes (each output needs the four segment pairs its two rooftops
+//    overlap) and stored twice: Z_ij and Z_ji = Z_ij^T.
+//  * Self blocks: one wave64 per wire.  They are Toeplitz in the segment
+//    offset d = alpha - beta, so lanes (d, k) cover the 8 offsets x 8 test
+//    nodes; for d <= 1 the static part 1/(4 pi R) is added in closed form
+//    (FP64 iterated antiderivatives) and only (exp(-jkR) - 1)/(4 pi R) is
+//    sampled.  The same wave inverts the block (Gauss-Jordan, partial
+//    pivoting) for the block-diagonal preconditioner.
+#include "common.hpp"
+#include "prof.hpp"
+
+namespace chaff {
+
+constexpr double PI = 3.14159265358979323846;
+
+struct FillParams {
+    double k;            // wavenumber
+    double inv_lambda;   // 1 / wavelength
+    int32_t q;           // Gauss order
+    int32_t pad;
+    double xq[MAXQ];     // nodes on [0,1]
+    double wq[MAXQ];     // weights
+};
+
+// exp(-j 2 pi rev) split into (cos, -sin) with the phase in revolutions.
+__device__ __forceinline__ void phase_cs(float rev, float& c, float& s) {
+    float f = __builtin_amdgcn_fractf(rev);
+    s = __builtin_amdgcn_sinf(f);   // sin(2 pi f)
+    c = __builtin_amdgcn_cosf(f);   // cos(2 pi f)
+}
+__device__ __forceinline__ void phase_cs(double rev, double& c, double& s) {
+    double f = rev - floor(rev);
+    sincospi(2.0 * f, &s, &c);
+}
+// sin^2(pi rev) (for the cancellation-free exp(-j x) - 1)
+__device__ __forceinline__ float half_sin(float rev) { return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(0.5f * rev)); }
+__device__ __forceinline__ double half_sin(double rev) { return sinpi(rev); }
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+
+// ------------------------------------------------------------------ static self integrals (FP64)
+// F(v) = (v^2 + b^2)^(-1/2) and its iterated antiderivatives F1..F4.
+struct Anti {
+    double f1, f2, f3, f4;
+};
+__device__ __forceinline__ Anti anti(double v, double b) {
+    double s = sqrt(v * v + b * b);
+    double ash = asinh(v / b);
+    Anti a;
+    a.f1 = ash;
+    a.f2 = v * ash - s;
+    a.f3 = (0.5 * v * v - 0.25 * b * b) * ash - 0.75 * v * s;
+    a.f4 = (v * v * v / 6.0 - 0.25 * b * b * v) * ash - (11.0 / 36.0) * s * s * s + (5.0 / 12.0) * b * b * s;
+    return a;
+}
+// K_mn(d) = int_0^1 int_0^1 xi^m xi'^n F(d + xi - xi') dxi' dxi by repeated
+// integration by parts (xi: test segment, xi': source segment).  Returns the
+// rooftop-half combinations K[a][b] with phi_+ = xi, phi_- = 1 - xi.
+__device__ void static_self(int d, double b, double K[2][2]) {
+    Anti p1 = anti(d + 1.0, b), p0 = anti((double)d, b), m1 = anti(d - 1.0, b);
+    double k00 = (p1.f2 - p0.f2) - (p0.f2 - m1.f2);
+    double k01 = -(p0.f2 - m1.f2) + (p1.f3 - p0.f3) - (p0.f3 - m1.f3);
+    double k10 = (p1.f2 - p0.f2) - (p1.f3 - 2.0 * p0.f3 + m1.f3);
+    double k11 = (-p0.f2 + p1.f3 - p0.f3) - (-p0.f3 + p1.f4 - p0.f4) + (-m1.f3 + p0.f4 - m1.f4);
+    K[0][0] = k11;
+    K[0][1] = k10 - k11;
+    K[1][0] = k01 - k11;
+    K[1][1] = k00 - k10 - k01 + k11;
+}
+
+// ------------------------------------------------------------------ self blocks
+
+template <typename R>
+__global__ __launch_bounds__(64) void k_self(const Wire* __restrict__ wires, int64_t n,
+                                             const int64_t* __restrict__ diag_pos,
+                                             cplx<R>* __restrict__ Z, cplx<R>* __restrict__ Pinv,
+                                             FillParams prm, int32_t* __restrict__ status) {
+    using C = cplx<R>;
+    __shared__ C T[8][2][2];       // T_ab(d), d = 0..7
+    __shared__ C Ab[7][14];        // augmented [Z | I] for the inverse
+    const int lane = threadIdx.x;
+    const int64_t w = blockIdx.x;
+    if (w >= n) return;
+    const Wire wr = wires[w];
+    const int d = lane >> 3, kk = lane & 7;
+    const double Dd = wr.len / NSEG;
+    const R D = (R)Dd;
+    const R a2 = (R)(wr.rad * wr.rad);
+    const R inv_lam = (R)prm.inv_lambda;
+    const int q = prm.q;
+
+    C m00 = {0, 0}, m01 = {0, 0}, m10 = {0, 0}, m11 = {0, 0};
+    if (kk < q) {
+        const R xk = (R)prm.xq[kk];
+        C s0 = {0, 0}, s1 = {0, 0};
+        for (int l = 0; l < q; ++l) {
+            const R xl = (R)prm.xq[l];
+            const R gl = (R)prm.wq[l];
+            R u = D * ((R)d + (xk - xl));
+            R r2 = u * u + a2;
+            R ir = rsq(r2);
+            R rr = r2 * ir;
+            R rev = rr * inv_lam;
+            R gre, gim;
+            if (d <= 1) {  // (exp(-jkR) - 1)/R = (-2 sin^2(kR/2) - j sin kR)/R
+                R hs = half_sin(rev);
+                R c, s;
+                phase_cs(rev, c, s);
+                gre = (R)-2 * hs * hs * ir;
+                gim = -s * ir;
+            } else {
+                R c, s;
+                phase_cs(rev, c, s);
+                gre = c * ir;
+                gim = -s * ir;
+            }
+            s0.re += gl * gre; s0.im += gl * gim;
+            s1.re += gl * xl * gre; s1.im += gl * xl * gim;
+        }
+        const R gk = (R)prm.wq[kk];
+        m00 = cscale(s0, gk);
+        m01 = cscale(s1, gk);
+        m10 = cscale(s0, gk * xk);
+        m11 = cscale(s1, gk * xk);
+    }
+    // sum over the 8 test nodes of each offset
+    for (int o = 1; o < 8; o <<= 1) {
+        m00.re += __shfl_xor(m00.re, o); m00.im += __shfl_xor(m00.im, o);
+        m01.re += __shfl_xor(m01.re, o); m01.im += __shfl_xor(m01.im, o);
+        m10.re += __shfl_xor(m10.re, o); m10.im += __shfl_xor(m10.im, o);
+        m11.re += __shfl_xor(m11.re, o); m11.im += __shfl_xor(m11.im, o);
+    }
+    if (kk == 0) {
+        const R sc = (R)(Dd * Dd / (4.0 * PI));
+        C A[2][2];
+        A[0][0] = cscale(m11, sc);
+        A[0][1] = cscale(csub(m10, m11), sc);
+        A[1][0] = cscale(csub(m01, m11), sc);
+        A[1][1] = cscale(cadd(csub(csub(m00, m10), m01), m11), sc);
+        if (d <= 1) {
+            double K[2][2];
+            static_self(d, wr.rad / Dd, K);
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) A[a][b].re += (R)(Dd / (4.0 * PI) * K[a][b]);
+        }
+        C B = cadd(cadd(A[0][0], A[0][1]), cadd(A[1][0], A[1][1]));
+        const R sz = (R)(1.0 / (prm.k * prm.k * Dd * Dd));
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                R sg = (a == b) ? (R)1 : (R)-1;
+                T[d][a][b] = csub(A[a][b], cscale(B, sg * sz));
+            }
+    }
+    __syncthreads();
+    C* Zb = Z + diag_pos[w] * NB2;
+    if (lane < NB2) {
+        const int qi = lane / NB, qj = lane % NB;
+        // evaluate the upper-triangle entry for both (qi,qj) and (qj,qi): exact symmetry
+        const int qa = qi < qj ? qi : qj, qb = qi < qj ? qj : qi;
+        C acc = {0, 0};
+        for (int da = 0; da < 2; ++da)
+            for (int db = 0; db < 2; ++db) {
+                int dd = (qa + da) - (qb + db);
+                C t = dd >= 0 ? T[dd][da][db] : T[-dd][db][da];
+                acc = cadd(acc, t);
+            }
+        Zb[lane] = acc;
+        Ab[qi][qj] = acc;
+        Ab[qi][NB + qj] = (qi == qj) ? C{1, 0} : C{0, 0};
+    }
+    __syncthreads();
+    if (Pinv == nullptr) return;
+    // Gauss-Jordan with partial pivoting; lane c < 14 owns column c
+    bool singular = false;
+    for (int piv = 0; piv < NB; ++piv) {
+        int best = piv;
+        R bm = Ab[piv][piv].re * Ab[piv][piv].re + Ab[piv][piv].im * Ab[piv][piv].im;
+        for (int r = piv + 1; r < NB; ++r) {
+            R m = Ab[r][piv].re * Ab[r][piv].re + Ab[r][piv].im * Ab[r][piv].im;
+            if (m > bm) { bm = m; best = r; }
+        }
+        if (!(bm > (R)0)) { singular = true; break; }
+        C pv = Ab[best][piv];
+        C f[NB];
+        for (int r = 0; r < NB; ++r) f[r] = Ab[r][piv];
+        __syncthreads();
+        if (lane < 2 * NB) {
+            C tmp = Ab[piv][lane];
+            Ab[piv][lane] = Ab[best][lane];
+            Ab[best][lane] = tmp;
+        }
+        __syncthreads();
+        if (best != piv) { C t = f[piv]; f[piv] = f[best]; f[best] = t; }
+        R inv_m = (R)1 / bm;
+        C ip = {pv.re * inv_m, -pv.im * inv_m};
+        if (lane < 2 * NB) {
+            C rowp = cmul(Ab[piv][lane], ip);
+            Ab[piv][lane] = rowp;
+            for (int r = 0; r < NB; ++r)
+                if (r != piv) Ab[r][lane] = csub(Ab[r][lane], cmul(f[r], rowp));
+        }
+        __syncthreads();
+    }
+    if (singular) {
+        if (lane == 0) atomicOr(status, 1);
+        return;
+    }
+    if (lane < NB2) Pinv[w * NB2 + lane] = Ab[lane / NB][NB + lane % NB];
+}
+
+// ------------------------------------------------------------------ mutual blocks
+
+template <typename R, int Q>
+__global__ __launch_bounds__(256) void k_mutual(const Wire* __restrict__ wires,
+                                                const Pair* __restrict__ pairs, int64_t n_pairs,
+                                                cplx<R>* __restrict__ Z, FillParams prm) {
+    using C = cplx<R>;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    const int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+    if (e >= n_pairs) return;
+    const Pair pr = pairs[e];
+    const Wire wi = wires[pr.i];
+    const Wire wj = wires[pr.j];
+    const int al = lane >> 3, be = lane & 7;
+
+    // FP64 geometry of this segment pair, rounded once to R
+    const double Di = wi.len / NSEG, Dj = wj.len / NSEG;
+    const double sep[3] = {wj.cx - wi.cx, wj.cy - wi.cy, wj.cz - wi.cz};
+    const double s0i = -0.5 * wi.len + al * Di;   // start of segment alpha on wire i
+    const double s0j = -0.5 * wj.len + be * Dj;   // start of segment beta on wire j
+    // r_i(xi) - r_j(xi') = (s0i t_i - sep - s0j t_j) + xi Di t_i - xi' Dj t_j
+    const R bx = (R)(s0i * wi.tx - sep[0] - s0j * wj.tx);
+    const R by = (R)(s0i * wi.ty - sep[1] - s0j * wj.ty);
+    const R bz = (R)(s0i * wi.tz - sep[2] - s0j * wj.tz);
+    const R uix = (R)(Di * wi.tx), uiy = (R)(Di * wi.ty), uiz = (R)(Di * wi.tz);
+    const R ujx = (R)(Dj * wj.tx), ujy = (R)(Dj * wj.ty), ujz = (R)(Dj * wj.tz);
+    const R a2 = (R)(0.5 * (wi.rad * wi.rad + wj.rad * wj.rad));
+    const R inv_lam = (R)prm.inv_lambda;
+
+    R xq[Q], wq[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        xq[k] = (R)prm.xq[k];
+        wq[k] = (R)prm.wq[k];
+    }
+    // source node offsets (relative): -xi'_l Dj t_j
+    R px[Q], py[Q], pz[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        px[l] = bx - xq[l] * ujx;
+        py[l] = by - xq[l] * ujy;
+        pz[l] = bz - xq[l] * ujz;
+    }
+    C m00 = {0, 0}, m01 = {0, 0}, m10 = {0, 0}, m11 = {0, 0};
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const R ox = xq[k] * uix, oy = xq[k] * uiy, oz = xq[k] * uiz;
+        C s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+        for (int l = 0; l < Q; ++l) {
+            R dx = px[l] + ox, dy = py[l] + oy, dz = pz[l] + oz;
+            R r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, a2)));
+            R ir = rsq(r2);
+            R rev = r2 * ir * inv_lam;
+            R c, s;
+            phase_cs(rev, c, s);
+            R gre = c * ir, gim = -s * ir;
+            s0.re = fma(wq[l], gre, s0.re);
+            s0.im = fma(wq[l], gim, s0.im);
+            R wl = wq[l] * xq[l];
+            s1.re = fma(wl, gre, s1.re);
+            s1.im = fma(wl, gim, s1.im);
+        }
+        const R wk = wq[k], wkx = wq[k] * xq[k];
+        m00.re = fma(wk, s0.re, m00.re); m00.im = fma(wk, s0.im, m00.im);
+        m01.re = fma(wk, s1.re, m01.re); m01.im = fma(wk, s1.im, m01.im);
+        m10.re = fma(wkx, s0.re, m10.re); m10.im = fma(wkx, s0.im, m10.im);
+        m11.re = fma(wkx, s1.re, m11.re); m11.im = fma(wkx, s1.im, m11.im);
+    }
+    // rooftop halves: A_ab = Di Dj/(4 pi) * moment combination; T_ab = tt A_ab - s_a s_b B/(k^2 Di Dj)
+    const R sc = (R)(Di * Dj / (4.0 * PI));
+    const R tt = (R)(wi.tx * wj.tx + wi.ty * wj.ty + wi.tz * wj.tz);
+    const R sz = (R)(1.0 / (prm.k * prm.k * Di * Dj));
+    C App = cscale(m11, sc);
+    C Apm = cscale(csub(m10, m11), sc);
+    C Amp = cscale(csub(m01, m11), sc);
+    C Amm = cscale(cadd(csub(csub(m00, m10), m01), m11), sc);
+    C B = cadd(cadd(App, Apm), cadd(Amp, Amm));
+    C Bs = cscale(B, sz);
+    C Tpp = csub(cscale(App, tt), Bs);
+    C Tpm = cadd(cscale(Apm, tt), Bs);
+    C Tmp = cadd(cscale(Amp, tt), Bs);
+    C Tmm = csub(cscale(Amm, tt), Bs);
+
+    // output lane o < 49 -> (q, q'): needs lanes (q,q') (q,q'+1) (q+1,q') (q+1,q'+1)
+    const int o = lane < NB2 ? lane : 0;
+    const int qi = o / NB, qj = o % NB;
+    const int l00 = qi * 8 + qj;
+    C z;
+    z.re = __shfl(Tpp.re, l00);
+    z.im = __shfl(Tpp.im, l00);
+    z.re += __shfl(Tpm.re, l00 + 1);
+    z.im += __shfl(Tpm.im, l00 + 1);
+    z.re += __shfl(Tmp.re, l00 + 8);
+    z.im += __shfl(Tmp.im, l00 + 8);
+    z.re += __shfl(Tmm.re, l00 + 9);
+    z.im += __shfl(Tmm.im, l00 + 9);
+    if (lane < NB2) {
+        Z[pr.pos_ij * NB2 + qi * NB + qj] = z;
+        Z[pr.pos_ji * NB2 + qj * NB + qi] = z;
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+__global__ void k_fill_status(int32_t* __restrict__ status) {
+    if (threadIdx.x == 0) status[0] = 0;
+}
+
+template <typename R>
+static chaff_status fill_impl(Cloud* c, void* Zv, void* Pinv, hipStream_t st) {
+    using C = cplx<R>;
+    C* Z = static_cast<C*>(Zv);
+    FillParams ps{};
+    ps.k = 2.0 * PI / c->wavelength;
+    ps.inv_lambda = 1.0 / c->wavelength;
+    ps.q = c->q_self;
+    for (int i = 0; i < MAXQ; ++i) { ps.xq[i] = c->xq_s[i]; ps.wq[i] = c->wq_s[i]; }
+    FillParams pm = ps;
+    pm.q = c->q_mutual;
+    for (int i = 0; i < MAXQ; ++i) { pm.xq[i] = c->xq_m[i]; pm.wq[i] = c->wq_m[i]; }
+
+    hipLaunchKernelGGL(k_fill_status, dim3(1), dim3(64), 0, st, c->d_status);
+    CHAFF_LAUNCH_CHECK();
+    if (c->n_pairs > 0) {
+        const int wpb = 4;
+        dim3 grid((unsigned)((c->n_pairs + wpb - 1) / wpb));
+        // 24 flops per Green sample, (8 Q)^2 samples per pair
+        ProfScope ps("fill_mutual", st, 24.0 * 64.0 * c->q_mutual * c->q_mutual * (double)c->n_pairs, true);
+        switch (c->q_mutual) {
+#define CHAFF_Q(QQ)                                                                               \
+    case QQ:                                                                                      \
+        hipLaunchKernelGGL((k_mutual<R, QQ>), grid, dim3(64 * wpb), 0, st, (const Wire*)c->wires, \
+                           (const Pair*)c->pairs, c->n_pairs, Z, pm);                             \
+        break;
+            CHAFF_Q(1) CHAFF_Q(2) CHAFF_Q(3) CHAFF_Q(4) CHAFF_Q(5) CHAFF_Q(6) CHAFF_Q(7) CHAFF_Q(8)
+#undef CHAFF_Q
+            default:
+                return fail(CHAFF_EINVAL, "quad_mutual out of range");
+        }
+        CHAFF_LAUNCH_CHECK();
+    }
+    {
+        ProfScope pss("fill_self", st, 24.0 * 8.0 * c->q_self * c->q_self * (double)c->n, true);
+        hipLaunchKernelGGL((k_self<R>), dim3((unsigned)c->n), dim3(64), 0, st, (const Wire*)c->wires, c->n,
+                           (const int64_t*)c->diag_pos, Z, static_cast<C*>(Pinv), ps, c->d_status);
+    }
+    CHAFF_LAUNCH_CHECK();
+    if (Pinv) {
+        int32_t flag = 0;
+        CHAFF_HIP(hipMemcpyAsync(&flag, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        CHAFF_HIP(hipStreamSynchronize(st));
+        if (flag) return fail(CHAFF_ESINGULAR, "a self block has a zero pivot");
+    }
+    return CHAFF_OK;
+}
+
+chaff_status fill_Z(Cloud* c, chaff_prec prec, void* Z, void* Pinv, hipStream_t st) {
+    if (prec == CHAFF_C64) return fill_impl<float>(c, Z, Pinv, st);
+    return fill_impl<double>(c, Z, Pinv, st);
+}
+
+}  // namespace chaff

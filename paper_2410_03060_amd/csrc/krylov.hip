@@ -1,0 +1,801 @@
+// Block-sparse products and the multi-RHS restarted GMRES with FP64
+// iterative refinement (Sec. II-B: iterative solve of the S-NFC system with a
+// block-diagonal preconditioner; matvec cost O(b_mean N)).
+//
+// Layout: every vector block is row-major [N*7][s] in the internal (Morton)
+// wire order, so the 7 x s slab of one wire is contiguous and a column tile
+// of s right-hand sides is read with unit stride.  Systems are independent
+// per (cloud, RHS); all of them advance in lockstep so that each sparse
+// product reads Z once for every right-hand side, while dot products are
+// reduced per cloud over fixed row chunks in a fixed order (deterministic).
+#include "common.hpp"
+#include "prof.hpp"
+
+#include <algorithm>
+#include <chrono>
+
+namespace chaff {
+
+constexpr double PI_K = 3.14159265358979323846;
+
+// ------------------------------------------------------------------ SpMM
+// MODE 0: Y = Z X    MODE 1: Y = B - Z X    MODE 2: Y += Z X
+// DIAG: the pattern is the block diagonal (block i of Z applied to wire i).
+
+template <typename CY> struct acc_t { using R = typename real_of<CY>::type; };
+
+// Variant 0: lanes -> (block row, output row q); one RHS column per grid.y.
+template <typename CZ, typename CX, typename CY, int MODE, bool DIAG>
+__global__ __launch_bounds__(256) void k_spmm_rowq(const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col_idx,
+                                                   const CZ* __restrict__ Z, const CX* __restrict__ X,
+                                                   const CY* __restrict__ B, CY* __restrict__ Y,
+                                                   int64_t n, int64_t s) {
+    using R = typename real_of<CY>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / NB;
+    const int q = (int)(t - i * NB);
+    const int64_t r = blockIdx.y;
+    if (i >= n) return;
+    const int64_t e0 = DIAG ? i : row_ptr[i];
+    const int64_t e1 = DIAG ? i + 1 : row_ptr[i + 1];
+    cplx<R> acc = {0, 0};
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t col = DIAG ? i : col_idx[e];
+        const CZ* zr = Z + e * NB2 + q * NB;
+        const CX* xb = X + col * NB * s + r;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            cplx<R> z = ccast<cplx<R>>(zr[k]);
+            cplx<R> x = ccast<cplx<R>>(xb[k * s]);
+            cfma(acc, z, x);
+        }
+    }
+    const int64_t o = (i * NB + q) * s + r;
+    if (MODE == 0) Y[o] = ccast<CY>(acc);
+    if (MODE == 1) Y[o] = ccast<CY>(csub(ccast<cplx<R>>(B[o]), acc));
+    if (MODE == 2) Y[o] = ccast<CY>(cadd(ccast<cplx<R>>(Y[o]), acc));
+}
+
+// Variant 1: lanes -> (block row sub-index, RHS column); ST columns per row,
+// each thread produces the 7 outputs of its (row, column).
+template <typename CZ, typename CX, typename CY, int MODE, bool DIAG, int ST>
+__global__ __launch_bounds__(256) void k_spmm_tile(const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col_idx,
+                                                   const CZ* __restrict__ Z, const CX* __restrict__ X,
+                                                   const CY* __restrict__ B, CY* __restrict__ Y,
+                                                   int64_t n, int64_t s) {
+    using R = typename real_of<CY>::type;
+    const int rows_per_block = 256 / ST;
+    const int64_t i = (int64_t)blockIdx.x * rows_per_block + threadIdx.x / ST;
+    const int64_t r = (int64_t)blockIdx.y * ST + (threadIdx.x % ST);
+    if (i >= n || r >= s) return;
+    const int64_t e0 = DIAG ? i : row_ptr[i];
+    const int64_t e1 = DIAG ? i + 1 : row_ptr[i + 1];
+    cplx<R> acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t col = DIAG ? i : col_idx[e];
+        const CZ* zb = Z + e * NB2;
+        const CX* xb = X + col * NB * s + r;
+        cplx<R> x[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) x[k] = ccast<cplx<R>>(xb[k * s]);
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) cfma(acc[q], ccast<cplx<R>>(zb[q * NB + k]), x[k]);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int64_t o = (i * NB + q) * s + r;
+        if (MODE == 0) Y[o] = ccast<CY>(acc[q]);
+        if (MODE == 1) Y[o] = ccast<CY>(csub(ccast<cplx<R>>(B[o]), acc[q]));
+        if (MODE == 2) Y[o] = ccast<CY>(cadd(ccast<cplx<R>>(Y[o]), acc[q]));
+    }
+}
+
+static int spmm_tile_width(int64_t s) {
+    int st = 1;
+    while (st < s && st < 64) st <<= 1;
+    return st;
+}
+
+// variant: 0 = rowq, 1 = tile (ST from s), 2 = tile with ST halved (more rows per wave)
+template <typename CZ, typename CX, typename CY, int MODE, bool DIAG>
+static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, const CZ* Z, const CX* X,
+                                const CY* B, CY* Y, int64_t n, int64_t nnzb, int64_t s, int variant,
+                                hipStream_t st, const char* tag = "spmm") {
+    if (n == 0 || s == 0) return CHAFF_OK;
+    // algorithmic HBM bytes: Z (and its indices) once, X once, Y once (+ B or Y read for MODE 1/2)
+    const double zb = DIAG ? (double)sizeof(CZ) * NB2 * n
+                           : ((double)sizeof(CZ) * NB2 + 4.0) * (double)nnzb + 8.0 * (n + 1);
+    const double vb = 7.0 * n * s * ((double)sizeof(CX) + sizeof(CY) + (MODE == 0 ? 0.0 : (double)sizeof(CY)));
+    ProfScope ps(tag, st, zb + vb, false);
+    if (variant < 0) variant = (s == 1) ? 0 : 1;
+    if (variant == 0) {
+        dim3 grid((unsigned)((n * NB + 255) / 256), (unsigned)s);
+        hipLaunchKernelGGL((k_spmm_rowq<CZ, CX, CY, MODE, DIAG>), grid, dim3(256), 0, st, row_ptr, col_idx,
+                           Z, X, B, Y, n, s);
+        CHAFF_LAUNCH_CHECK();
+        return CHAFF_OK;
+    }
+    int w = spmm_tile_width(s);
+    if (variant == 2 && w > 1) w >>= 1;
+    const unsigned ty = (unsigned)((s + w - 1) / w);
+#define CHAFF_TILE(W)                                                                                    \
+    case W: {                                                                                            \
+        dim3 grid((unsigned)((n + (256 / W) - 1) / (256 / W)), ty);                                      \
+        hipLaunchKernelGGL((k_spmm_tile<CZ, CX, CY, MODE, DIAG, W>), grid, dim3(256), 0, st, row_ptr,    \
+                           col_idx, Z, X, B, Y, n, s);                                                   \
+        break;                                                                                           \
+    }
+    switch (w) {
+        CHAFF_TILE(1) CHAFF_TILE(2) CHAFF_TILE(4) CHAFF_TILE(8) CHAFF_TILE(16) CHAFF_TILE(32) CHAFF_TILE(64)
+        default: return fail(CHAFF_EINVAL, "bad tile width");
+    }
+#undef CHAFF_TILE
+    CHAFF_LAUNCH_CHECK();
+    return CHAFF_OK;
+}
+
+chaff_status spmm_public(Cloud* c, chaff_prec prec, const void* Z, const void* X, void* Y, int64_t s,
+                         int variant, hipStream_t st) {
+    if (prec == CHAFF_C64)
+        return spmm_launch<c64, c64, c64, 0, false>(c->row_ptr, c->col_idx, (const c64*)Z, (const c64*)X,
+                                                    nullptr, (c64*)Y, c->n, c->nnzb, s, variant, st);
+    return spmm_launch<c128, c128, c128, 0, false>(c->row_ptr, c->col_idx, (const c128*)Z, (const c128*)X,
+                                                   nullptr, (c128*)Y, c->n, c->nnzb, s, variant, st);
+}
+
+// ------------------------------------------------------------------ excitation (FP64)
+
+__device__ __forceinline__ double sinc(double x) {
+    return fabs(x) < 1e-4 ? 1.0 - x * x / 6.0 : sin(x) / x;
+}
+
+// U[i*7+q][r] (internal wire i) or, with `perm`, at caller row perm[i].
+__global__ void k_excitation(const Wire* __restrict__ wires, const int32_t* __restrict__ perm, int64_t n,
+                             const double* __restrict__ k_hat, const double* __restrict__ e_hat,
+                             int64_t s, double k, c128* __restrict__ U) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * s) return;
+    const int64_t i = t / s, r = t - (t / s) * s;
+    const Wire w = wires[i];
+    const double kx = k_hat[3 * r], ky = k_hat[3 * r + 1], kz = k_hat[3 * r + 2];
+    const double ex = e_hat[3 * r], ey = e_hat[3 * r + 1], ez = e_hat[3 * r + 2];
+    const double tp = w.tx * ex + w.ty * ey + w.tz * ez;
+    const double beta = k * (kx * w.tx + ky * w.ty + kz * w.tz);
+    const double ph0 = k * (kx * w.cx + ky * w.cy + kz * w.cz);
+    const double D = w.len / NSEG;
+    const double sc = sinc(0.5 * beta * D);
+    const double env = tp * D * sc * sc;
+    const int64_t row = perm ? (int64_t)perm[i] : i;
+    for (int q = 0; q < NB; ++q) {
+        const double sq = -0.5 * w.len + (q + 1) * D;
+        double sn, cs;
+        sincos(ph0 + beta * sq, &sn, &cs);
+        U[(row * NB + q) * s + r] = c128{env * cs, -env * sn};
+    }
+}
+
+// ------------------------------------------------------------------ row-chunk reductions
+
+struct Chunk {
+    int64_t w0, w1;      // wire range (internal order), within one cloud
+    int32_t cloud;
+    int32_t pad;
+};
+
+constexpr int RB = 256;  // threads per reduction block
+constexpr int GV = 8;    // basis vectors per dot group
+
+// Per-thread mapping inside a chunk: ST columns, 256/ST rows per pass.
+struct RowMap {
+    int st, rsub, r;
+};
+__device__ __forceinline__ RowMap rowmap(int st) {
+    RowMap m;
+    m.st = st;
+    m.rsub = threadIdx.x / st;
+    m.r = blockIdx.y * st + threadIdx.x % st;
+    return m;
+}
+
+// Reduce acc over the threads sharing a column; lane ST-strided tree in LDS.
+__device__ __forceinline__ c128 block_col_reduce(c128 v, int st, c128* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int stride = RB / 2; stride >= st; stride >>= 1) {
+        if (threadIdx.x < stride) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + stride]);
+        __syncthreads();
+    }
+    c128 out = red[threadIdx.x % st];
+    __syncthreads();
+    return out;
+}
+
+// part[chunk][slot][s] += dots of V_i (i in [i0, i0+ng)) with W over the chunk
+template <typename C>
+__global__ __launch_bounds__(RB) void k_dots(const Chunk* __restrict__ chunks, const C* __restrict__ V,
+                                             int64_t vstride, int i0, int ng, const C* __restrict__ W,
+                                             int64_t s, int st, c128* __restrict__ part, int nslot) {
+    __shared__ c128 red[RB];
+    const Chunk ch = chunks[blockIdx.x];
+    const RowMap m = rowmap(st);
+    c128 acc[GV];
+#pragma unroll
+    for (int g = 0; g < GV; ++g) acc[g] = {0, 0};
+    if (m.r < s) {
+        for (int64_t row = ch.w0 * NB + m.rsub; row < ch.w1 * NB; row += RB / st) {
+            const int64_t o = row * s + m.r;
+            c128 w = ccast<c128>(W[o]);
+#pragma unroll
+            for (int g = 0; g < GV; ++g)
+                if (g < ng) cfma_conj(acc[g], ccast<c128>(V[(int64_t)(i0 + g) * vstride + o]), w);
+        }
+    }
+    for (int g = 0; g < ng; ++g) {
+        c128 v = block_col_reduce(acc[g], st, red);
+        if (threadIdx.x < st && m.r < s) part[((int64_t)blockIdx.x * nslot + i0 + g) * s + m.r] = v;
+    }
+}
+
+// W -= sum_i V_i h[i][cloud][r]  (i < nv); optional squared norm of the result into slot `nslot_norm`
+template <typename C, bool NORM>
+__global__ __launch_bounds__(RB) void k_update(const Chunk* __restrict__ chunks, const C* __restrict__ V,
+                                               int64_t vstride, int nv, const c128* __restrict__ h,
+                                               int n_clouds, C* __restrict__ W, int64_t s, int st,
+                                               c128* __restrict__ part, int nslot, int slot_norm) {
+    using R = typename real_of<C>::type;
+    __shared__ c128 red[RB];
+    const Chunk ch = chunks[blockIdx.x];
+    const RowMap m = rowmap(st);
+    c128 acc = {0, 0};
+    if (m.r < s) {
+        const int64_t hsys = (int64_t)ch.cloud * s + m.r;
+        const int64_t hst = (int64_t)n_clouds * s;
+        for (int64_t row = ch.w0 * NB + m.rsub; row < ch.w1 * NB; row += RB / st) {
+            const int64_t o = row * s + m.r;
+            cplx<R> w = W[o];
+            for (int i = 0; i < nv; ++i) {
+                cplx<R> hc = ccast<cplx<R>>(h[i * hst + hsys]);
+                cplx<R> v = V[(int64_t)i * vstride + o];
+                cfma(w, cmk<R>(-v.re, -v.im), hc);
+            }
+            W[o] = w;
+            if (NORM) acc.re += (double)w.re * w.re + (double)w.im * w.im;
+        }
+    }
+    if (NORM) {
+        c128 v = block_col_reduce(acc, st, red);
+        if (threadIdx.x < st && m.r < s) part[((int64_t)blockIdx.x * nslot + slot_norm) * s + m.r] = v;
+    }
+}
+
+// squared norms of a vector block into slot
+template <typename C>
+__global__ __launch_bounds__(RB) void k_norm2(const Chunk* __restrict__ chunks, const C* __restrict__ W,
+                                              int64_t s, int st, c128* __restrict__ part, int nslot, int slot) {
+    __shared__ c128 red[RB];
+    const Chunk ch = chunks[blockIdx.x];
+    const RowMap m = rowmap(st);
+    c128 acc = {0, 0};
+    if (m.r < s) {
+        for (int64_t row = ch.w0 * NB + m.rsub; row < ch.w1 * NB; row += RB / st) {
+            c128 w = ccast<c128>(W[row * s + m.r]);
+            acc.re += w.re * w.re + w.im * w.im;
+        }
+    }
+    c128 v = block_col_reduce(acc, st, red);
+    if (threadIdx.x < st && m.r < s) part[((int64_t)blockIdx.x * nslot + slot) * s + m.r] = v;
+}
+
+// out[slot - slot0][cloud][r] = sum over the cloud's chunks (in order) of part[chunk][slot][r]
+__global__ void k_chunk_sum(const c128* __restrict__ part, const int32_t* __restrict__ cloud_chunk_off,
+                            int n_clouds, int nslot, int slot0, int ns, int64_t s, c128* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)ns * n_clouds * s;
+    if (t >= total) return;
+    const int64_t r = t % s;
+    const int c = (int)((t / s) % n_clouds);
+    const int rel = (int)(t / (s * n_clouds));
+    const int slot = slot0 + rel;
+    c128 acc = {0, 0};
+    for (int ch = cloud_chunk_off[c]; ch < cloud_chunk_off[c + 1]; ++ch)
+        acc = cadd(acc, part[((int64_t)ch * nslot + slot) * s + r]);
+    out[((int64_t)rel * n_clouds + c) * s + r] = acc;
+}
+
+// ------------------------------------------------------------------ per-system GMRES state (FP64)
+
+struct SysState {
+    int32_t done;      // 1 once converged or broken down
+    int32_t k_used;    // Krylov columns used by the least-squares solve
+    double inv_beta;   // 1 / h_{j+1,j} for the next basis vector (0 after breakdown)
+    double est;        // current residual estimate relative to the cycle start
+    double target;     // stop when est <= target
+};
+
+// column j of H from the two CGS passes and ||w||, Givens update, convergence flags
+__global__ void k_givens(int64_t nsys, int j, int m, const c128* __restrict__ h1, const c128* __restrict__ h2,
+                         const c128* __restrict__ nrm, c128* __restrict__ H, c128* __restrict__ G,
+                         double* __restrict__ cs, c128* __restrict__ sn, SysState* __restrict__ sys,
+                         int32_t* __restrict__ n_active) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsys) return;
+    SysState S = sys[t];
+    c128* Hc = H + t * (int64_t)(m + 1) * m;   // H[i][j] at Hc[i*m + j]
+    c128* g = G + t * (int64_t)(m + 1);
+    double* c_ = cs + t * (int64_t)m;
+    c128* s_ = sn + t * (int64_t)m;
+    double beta = sqrt(fmax(nrm[t].re, 0.0));
+    for (int i = 0; i <= j; ++i) Hc[i * m + j] = cadd(h1[(int64_t)i * nsys + t], h2[(int64_t)i * nsys + t]);
+    Hc[(j + 1) * m + j] = c128{beta, 0.0};
+    if (S.done) {
+        sys[t].inv_beta = 0.0;
+        return;
+    }
+    // previous rotations
+    for (int i = 0; i < j; ++i) {
+        c128 x = Hc[i * m + j], y = Hc[(i + 1) * m + j];
+        c128 nx = cadd(cscale(x, c_[i]), cmul(s_[i], y));
+        c128 ny = csub(cscale(y, c_[i]), cmul(c128{s_[i].re, -s_[i].im}, x));
+        Hc[i * m + j] = nx;
+        Hc[(i + 1) * m + j] = ny;
+    }
+    c128 a = Hc[j * m + j];
+    double aa = sqrt(a.re * a.re + a.im * a.im);
+    double cj;
+    c128 sj, rr;
+    if (beta == 0.0) {
+        cj = 1.0; sj = c128{0, 0}; rr = a;
+    } else if (aa == 0.0) {
+        cj = 0.0; sj = c128{1, 0}; rr = c128{beta, 0};
+    } else {
+        double tn = sqrt(aa * aa + beta * beta);
+        c128 ph = c128{a.re / aa, a.im / aa};
+        cj = aa / tn;
+        sj = cscale(ph, beta / tn);
+        rr = cscale(ph, tn);
+    }
+    c_[j] = cj;
+    s_[j] = sj;
+    Hc[j * m + j] = rr;
+    Hc[(j + 1) * m + j] = c128{0, 0};
+    c128 gj = g[j];
+    g[j] = cscale(gj, cj);
+    g[j + 1] = cmul(c128{-sj.re, sj.im}, gj);
+    double est = sqrt(g[j + 1].re * g[j + 1].re + g[j + 1].im * g[j + 1].im);
+    S.est = est;
+    S.k_used = j + 1;
+    const double hscale = sqrt(aa * aa + beta * beta);
+    const bool breakdown = !(beta > 1e-14 * hscale) || !isfinite(beta);
+    S.inv_beta = breakdown ? 0.0 : 1.0 / beta;
+    if (est <= S.target || breakdown || j + 1 >= m) S.done = 1;
+    sys[t] = S;
+    if (!S.done) atomicAdd(n_active, 1);
+}
+
+// y = R^{-1} g over the first k_used columns, scaled by the cycle's residual norm
+__global__ void k_lsq(int64_t nsys, int m, const c128* __restrict__ H, const c128* __restrict__ G,
+                      const SysState* __restrict__ sys, const double* __restrict__ rnorm,
+                      c128* __restrict__ Y, int nv_max) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsys) return;
+    const c128* Hc = H + t * (int64_t)(m + 1) * m;
+    const c128* g = G + t * (int64_t)(m + 1);
+    const int k = sys[t].k_used;
+    c128 y[256];
+    for (int i = k - 1; i >= 0; --i) {
+        c128 acc = g[i];
+        for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(Hc[i * m + l], y[l]));
+        c128 d = Hc[i * m + i];
+        double dd = d.re * d.re + d.im * d.im;
+        y[i] = dd > 0 ? cmul(acc, c128{d.re / dd, -d.im / dd}) : c128{0, 0};
+    }
+    const double sc = rnorm[t];
+    for (int i = 0; i < nv_max; ++i) Y[(int64_t)i * nsys + t] = i < k ? cscale(y[i], sc) : c128{0, 0};
+}
+
+// elementwise helpers -----------------------------------------------------------
+
+// V0 = R * (1/||r||) cast to C; zero for inactive systems
+template <typename C>
+__global__ void k_start_vector(const c128* __restrict__ Rv, const int32_t* __restrict__ wire_cloud,
+                               const double* __restrict__ inv_rn, int n_clouds, int64_t n_rows, int64_t s,
+                               C* __restrict__ V0) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s) return;
+    const int64_t row = t / s, r = t - (t / s) * s;
+    const int c = wire_cloud[row / NB];
+    const double f = inv_rn[(int64_t)c * s + r];
+    V0[t] = ccast<C>(cscale(Rv[t], f));
+}
+
+// Vnext = W * inv_beta(system)
+template <typename C>
+__global__ void k_scale_next(const C* __restrict__ W, const int32_t* __restrict__ wire_cloud,
+                             const SysState* __restrict__ sys, int64_t n_rows, int64_t s, C* __restrict__ Vn) {
+    using R = typename real_of<C>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s) return;
+    const int64_t row = t / s, r = t - (t / s) * s;
+    const int c = wire_cloud[row / NB];
+    const R f = (R)sys[(int64_t)c * s + r].inv_beta;
+    Vn[t] = cscale(W[t], f);
+}
+
+// T = sum_{i<nv} V_i Y_i(system)
+template <typename C>
+__global__ void k_combine(const C* __restrict__ V, int64_t vstride, int nv, const c128* __restrict__ Y,
+                          const int32_t* __restrict__ wire_cloud, int n_clouds, int64_t n_rows, int64_t s,
+                          C* __restrict__ T) {
+    using R = typename real_of<C>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s) return;
+    const int64_t row = t / s, r = t - (t / s) * s;
+    const int64_t sysi = (int64_t)wire_cloud[row / NB] * s + r;
+    const int64_t nsys = (int64_t)n_clouds * s;
+    cplx<R> acc = {0, 0};
+    for (int i = 0; i < nv; ++i) cfma(acc, V[(int64_t)i * vstride + t], ccast<cplx<R>>(Y[(int64_t)i * nsys + sysi]));
+    T[t] = acc;
+}
+
+// caller <-> internal permutation of [N*7][s] complex double blocks
+__global__ void k_permute_rows(const c128* __restrict__ src, const int32_t* __restrict__ map, int64_t n,
+                               int64_t s, c128* __restrict__ dst, int to_caller) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * NB * s) return;
+    const int64_t row = t / s, r = t - (t / s) * s;
+    const int64_t i = row / NB, q = row - (row / NB) * NB;
+    // to_caller: dst[perm[i]] = src[i]  (map = perm);  else dst[i] = src[perm[i]]
+    const int64_t p = map[i];
+    if (to_caller) dst[(p * NB + q) * s + r] = src[t];
+    else dst[t] = src[(p * NB + q) * s + r];
+}
+
+__global__ void k_copy_c128(const c128* __restrict__ a, int64_t n, c128* __restrict__ b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = a[t];
+}
+__global__ void k_zero_bytes(uint32_t* __restrict__ a, int64_t nwords) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nwords;
+         t += (int64_t)gridDim.x * blockDim.x)
+        a[t] = 0u;
+}
+
+// ------------------------------------------------------------------ host driver
+
+static unsigned blocks_for(int64_t n, int threads = 256) {
+    return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads);
+}
+
+struct SolveLayout {
+    size_t bytes;
+    c128 *b, *x, *r;                 // FP64 [rows][s]
+    void* V;                         // (m+1) x [rows][s] of C
+    void* W;                         // [rows][s] of C
+    void* T;                         // [rows][s] of C
+    c128* part;                      // [nch][nslot][s]
+    c128 *h1, *h2, *nrm, *red;       // [slot][cloud][s]
+    c128 *H, *G, *sn, *Y;            // per system
+    double *cs, *bn, *rn, *inv_rn;   // per system
+    SysState* sys;
+    Chunk* chunks;
+    int32_t* cloud_chunk_off;
+    int32_t* counter;
+};
+
+struct SolveShape {
+    int64_t n, rows, s, nsys;
+    int m, nslot, n_chunks, n_clouds;
+    size_t csize;
+};
+
+static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec) {
+    SolveShape sh;
+    sh.n = c->n;
+    sh.rows = c->n * NB;
+    sh.s = s;
+    sh.n_clouds = c->n_clouds;
+    sh.nsys = (int64_t)c->n_clouds * s;
+    sh.m = m;
+    sh.nslot = m + 2;
+    const int64_t cw = std::max<int64_t>(32, (c->n + 2047) / 2048);
+    int64_t nch = 0;
+    for (int k = 0; k < c->n_clouds; ++k) {
+        int64_t nw = c->cloud_off[k + 1] - c->cloud_off[k];
+        nch += (nw + cw - 1) / cw;
+    }
+    sh.n_chunks = (int)nch;
+    sh.csize = prec == CHAFF_C64 ? sizeof(c64) : sizeof(c128);
+    return sh;
+}
+
+static SolveLayout carve_solve(void* ws, size_t ws_bytes, const SolveShape& sh) {
+    Carve cv(ws, ws_bytes);
+    SolveLayout L;
+    const int64_t vs = sh.rows * sh.s;
+    L.b = cv.take<c128>(vs);
+    L.x = cv.take<c128>(vs);
+    L.r = cv.take<c128>(vs);
+    L.V = cv.take<char>((size_t)(sh.m + 1) * vs * sh.csize);
+    L.W = cv.take<char>((size_t)vs * sh.csize);
+    L.T = cv.take<char>((size_t)vs * sh.csize);
+    L.part = cv.take<c128>((size_t)std::max(sh.n_chunks, 1) * sh.nslot * sh.s);
+    L.h1 = cv.take<c128>((size_t)(sh.m + 1) * sh.nsys);
+    L.h2 = cv.take<c128>((size_t)(sh.m + 1) * sh.nsys);
+    L.nrm = cv.take<c128>((size_t)sh.nsys);
+    L.red = cv.take<c128>((size_t)sh.nsys);
+    L.H = cv.take<c128>((size_t)sh.nsys * (sh.m + 1) * sh.m);
+    L.G = cv.take<c128>((size_t)sh.nsys * (sh.m + 1));
+    L.sn = cv.take<c128>((size_t)sh.nsys * sh.m);
+    L.Y = cv.take<c128>((size_t)sh.nsys * (sh.m + 1));
+    L.cs = cv.take<double>((size_t)sh.nsys * sh.m);
+    L.bn = cv.take<double>((size_t)sh.nsys);
+    L.rn = cv.take<double>((size_t)sh.nsys);
+    L.inv_rn = cv.take<double>((size_t)sh.nsys);
+    L.sys = cv.take<SysState>((size_t)sh.nsys);
+    L.chunks = cv.take<Chunk>((size_t)std::max(sh.n_chunks, 1));
+    L.cloud_chunk_off = cv.take<int32_t>((size_t)sh.n_clouds + 1);
+    L.counter = cv.take<int32_t>(64);
+    L.bytes = cv.off + 256;
+    return L;
+}
+
+size_t solve_workspace_bytes(const Cloud* c, const chaff_solve_opts* o, int64_t s) {
+    const int m = o->restart;
+    SolveShape sh = solve_shape(c, m, s, (chaff_prec)o->prec);
+    return carve_solve(nullptr, 0, sh).bytes;
+}
+
+// per-system squared norms of an FP64 block into host vector (sync)
+template <typename C>
+static chaff_status norms_to(const SolveShape& sh, SolveLayout& L, const C* v, c128* dst, hipStream_t st) {
+    const int wst = spmm_tile_width(sh.s);
+    dim3 grid(sh.n_chunks, (unsigned)((sh.s + wst - 1) / wst));
+    if (sh.n_chunks > 0) {
+        hipLaunchKernelGGL((k_norm2<C>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, v, sh.s, wst, L.part,
+                           sh.nslot, 0);
+        CHAFF_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for(sh.nsys)), dim3(256), 0, st, (const c128*)L.part,
+                       (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, 1, sh.s, dst);
+    CHAFF_LAUNCH_CHECK();
+    return CHAFF_OK;
+}
+
+template <typename C, typename CZ>
+static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z, const CZ* Pinv,
+                               const double* k_hat, const double* e_hat, int64_t s, c128* Xout, void* ws,
+                               size_t ws_bytes, chaff_solve_stats* stats, double* rel_res_out, hipStream_t st) {
+    auto t_start = std::chrono::steady_clock::now();
+    const int m = o->restart;
+    SolveShape sh = solve_shape(c, m, s, (chaff_prec)o->prec);
+    SolveLayout L = carve_solve(ws, ws_bytes, sh);
+    if (L.bytes > ws_bytes)
+        return fail(CHAFF_EWORKSPACE, "solve workspace too small: need " + std::to_string(L.bytes));
+    const int64_t rows = sh.rows, vs = rows * s, nsys = sh.nsys;
+    C* V = static_cast<C*>(L.V);
+    C* W = static_cast<C*>(L.W);
+    C* T = static_cast<C*>(L.T);
+    const int wst = spmm_tile_width(s);
+    const unsigned ry = (unsigned)((s + wst - 1) / wst);
+
+    // --- chunk tables (host -> device)
+    {
+        const int64_t cw = std::max<int64_t>(32, (c->n + 2047) / 2048);
+        std::vector<Chunk> ch;
+        std::vector<int32_t> off(sh.n_clouds + 1, 0);
+        for (int k = 0; k < sh.n_clouds; ++k) {
+            off[k] = (int32_t)ch.size();
+            for (int64_t w0 = c->cloud_off[k]; w0 < c->cloud_off[k + 1]; w0 += cw)
+                ch.push_back(Chunk{w0, std::min<int64_t>(w0 + cw, c->cloud_off[k + 1]), k, 0});
+        }
+        off[sh.n_clouds] = (int32_t)ch.size();
+        if (!ch.empty())
+            CHAFF_HIP(hipMemcpyAsync(L.chunks, ch.data(), ch.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
+        CHAFF_HIP(hipMemcpyAsync(L.cloud_chunk_off, off.data(), off.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st));
+        CHAFF_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
+    }
+
+    // --- excitation and initial guess (internal order, FP64)
+    const double k = 2.0 * PI_K / c->wavelength;
+    hipLaunchKernelGGL(k_excitation, dim3(blocks_for(c->n * s)), dim3(256), 0, st, (const Wire*)c->wires,
+                       (const int32_t*)nullptr, c->n, k_hat, e_hat, s, k, L.b);
+    CHAFF_LAUNCH_CHECK();
+    if (o->use_x0) {
+        hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)Xout,
+                           (const int32_t*)c->perm, c->n, s, L.x, 0);
+    } else {
+        hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(vs * 4, 256)), dim3(256), 0, st, (uint32_t*)L.x,
+                           vs * 4);
+    }
+    CHAFF_LAUNCH_CHECK();
+    chaff_status sst = norms_to<c128>(sh, L, L.b, L.red, st);
+    if (sst != CHAFF_OK) return sst;
+    std::vector<c128> hb(nsys), hr(nsys);
+    CHAFF_HIP(hipMemcpyAsync(hb.data(), L.red, nsys * sizeof(c128), hipMemcpyDeviceToHost, st));
+    CHAFF_HIP(hipStreamSynchronize(st));
+    std::vector<double> bnorm(nsys), rel(nsys, 0.0);
+    for (int64_t i = 0; i < nsys; ++i) bnorm[i] = std::sqrt(std::max(hb[i].re, 0.0));
+
+    const bool refine = std::is_same<C, c64>::value;
+    int cycles = 0, iters = 0;
+    bool converged = false;
+    std::vector<double> hinv(nsys), hrn(nsys);
+    std::vector<SysState> hsys(nsys);
+    for (;;) {
+        // true residual r = b - Z x (FP64 accumulation over the stored Z)
+        if (cycles == 0 && !o->use_x0) {
+            hipLaunchKernelGGL(k_copy_c128, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.b, vs, L.r);
+            CHAFF_LAUNCH_CHECK();
+        } else {
+            sst = spmm_launch<CZ, c128, c128, 1, false>(c->row_ptr, c->col_idx, Z, L.x, L.b, L.r, c->n, c->nnzb, s, -1, st,
+                                                        "spmm_residual_fp64");
+            if (sst != CHAFF_OK) return sst;
+        }
+        sst = norms_to<c128>(sh, L, L.r, L.red, st);
+        if (sst != CHAFF_OK) return sst;
+        CHAFF_HIP(hipMemcpyAsync(hr.data(), L.red, nsys * sizeof(c128), hipMemcpyDeviceToHost, st));
+        CHAFF_HIP(hipStreamSynchronize(st));
+        double worst = 0.0;
+        int64_t active = 0;
+        for (int64_t i = 0; i < nsys; ++i) {
+            double rn = std::sqrt(std::max(hr[i].re, 0.0));
+            rel[i] = bnorm[i] > 0 ? rn / bnorm[i] : 0.0;
+            worst = std::max(worst, rel[i]);
+            bool act = rel[i] > o->tol && std::isfinite(rel[i]);
+            active += act;
+            hrn[i] = act ? rn : 0.0;
+            hinv[i] = act ? 1.0 / rn : 0.0;
+            SysState S{};
+            S.done = act ? 0 : 1;
+            S.k_used = 0;
+            S.inv_beta = 0.0;
+            S.est = 1.0;
+            // FP32 cycles aim at a fixed reduction; FP64 cycles straight at the target
+            double need = act ? (o->tol * bnorm[i] / rn) : 1.0;
+            S.target = refine ? std::max(o->inner_tol, std::min(need, 1.0) * 0.5) : std::min(need * 0.5, 1.0);
+            hsys[i] = S;
+        }
+        if (active == 0) { converged = true; break; }
+        if (cycles >= o->max_cycles) break;
+        ++cycles;
+        CHAFF_HIP(hipMemcpyAsync(L.rn, hrn.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
+        CHAFF_HIP(hipMemcpyAsync(L.inv_rn, hinv.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
+        CHAFF_HIP(hipMemcpyAsync(L.sys, hsys.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, st));
+        // g = e_1 for every system
+        {
+            std::vector<c128> g0((size_t)nsys * (m + 1), c128{0, 0});
+            for (int64_t i = 0; i < nsys; ++i) g0[(size_t)i * (m + 1)] = c128{1, 0};
+            CHAFF_HIP(hipMemcpyAsync(L.G, g0.data(), g0.size() * sizeof(c128), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL((k_start_vector<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.r,
+                               (const int32_t*)c->wire_cloud, (const double*)L.inv_rn, sh.n_clouds, rows, s, V);
+            CHAFF_LAUNCH_CHECK();
+            CHAFF_HIP(hipStreamSynchronize(st));
+        }
+        int j = 0;
+        for (; j < m; ++j) {
+            ++iters;
+            C* vj = V + (int64_t)j * vs;
+            // W = Z P v_j
+            sst = spmm_launch<CZ, C, C, 0, true>(nullptr, nullptr, Pinv, vj, (const C*)nullptr, T, c->n, c->n, s, -1, st,
+                                                 "precond");
+            if (sst != CHAFF_OK) return sst;
+            sst = spmm_launch<CZ, C, C, 0, false>(c->row_ptr, c->col_idx, Z, T, (const C*)nullptr, W, c->n, c->nnzb,
+                                                  s, o->spmm_variant, st);
+            if (sst != CHAFF_OK) return sst;
+            const int nv = j + 1;
+            dim3 grid(sh.n_chunks, ry);
+            {  // classical Gram-Schmidt, twice, and the new vector's norm
+            // CGS pass 1
+            for (int i0 = 0; i0 < nv; i0 += GV) {
+                ProfScope p1("k_dots", st, (double)(std::min(GV, nv - i0) + 1) * vs * sizeof(C));
+                hipLaunchKernelGGL((k_dots<C>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)V, vs, i0,
+                                   std::min(GV, nv - i0), (const C*)W, s, wst, L.part, sh.nslot);
+                CHAFF_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for((int64_t)nv * nsys)), dim3(256), 0, st,
+                               (const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, nv,
+                               s, L.h1);
+            CHAFF_LAUNCH_CHECK();
+            {
+                ProfScope p2("k_update", st, (double)(nv + 2) * vs * sizeof(C));
+                hipLaunchKernelGGL((k_update<C, false>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)V,
+                                   vs, nv, (const c128*)L.h1, sh.n_clouds, W, s, wst, L.part, sh.nslot, 0);
+            }
+            CHAFF_LAUNCH_CHECK();
+            // CGS pass 2 (re-orthogonalisation) + norm
+            for (int i0 = 0; i0 < nv; i0 += GV) {
+                ProfScope p1("k_dots", st, (double)(std::min(GV, nv - i0) + 1) * vs * sizeof(C));
+                hipLaunchKernelGGL((k_dots<C>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)V, vs, i0,
+                                   std::min(GV, nv - i0), (const C*)W, s, wst, L.part, sh.nslot);
+                CHAFF_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for((int64_t)nv * nsys)), dim3(256), 0, st,
+                               (const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, nv,
+                               s, L.h2);
+            CHAFF_LAUNCH_CHECK();
+            {
+                ProfScope p3("k_update_norm", st, (double)(nv + 2) * vs * sizeof(C));
+                hipLaunchKernelGGL((k_update<C, true>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)V,
+                                   vs, nv, (const c128*)L.h2, sh.n_clouds, W, s, wst, L.part, sh.nslot,
+                                   sh.nslot - 1);
+            }
+            CHAFF_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for(nsys)), dim3(256), 0, st, (const c128*)L.part,
+                               (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, sh.nslot - 1, 1, s, L.nrm);
+            CHAFF_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)L.counter, (int64_t)1);
+            CHAFF_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_givens, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, j, m, (const c128*)L.h1,
+                               (const c128*)L.h2, (const c128*)L.nrm, L.H, L.G, L.cs, L.sn, L.sys, L.counter);
+            CHAFF_LAUNCH_CHECK();
+            if (j + 1 < m) {
+                hipLaunchKernelGGL((k_scale_next<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const C*)W,
+                                   (const int32_t*)c->wire_cloud, (const SysState*)L.sys, rows, s,
+                                   V + (int64_t)(j + 1) * vs);
+                CHAFF_LAUNCH_CHECK();
+            }
+            int32_t n_act = 0;
+            CHAFF_HIP(hipMemcpyAsync(&n_act, L.counter, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            CHAFF_HIP(hipStreamSynchronize(st));
+            if (n_act == 0) break;
+        }
+        // x += P (V y)
+        const int nv_max = std::min(j + 1, m);
+        hipLaunchKernelGGL(k_lsq, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, m, (const c128*)L.H,
+                           (const c128*)L.G, (const SysState*)L.sys, (const double*)L.rn, L.Y, nv_max);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_combine<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const C*)V, vs, nv_max,
+                           (const c128*)L.Y, (const int32_t*)c->wire_cloud, sh.n_clouds, rows, s, T);
+        CHAFF_LAUNCH_CHECK();
+        sst = spmm_launch<CZ, C, c128, 2, true>(nullptr, nullptr, Pinv, T, (const c128*)nullptr, L.x, c->n, c->n, s,
+                                                -1, st, "precond_update_fp64");
+        if (sst != CHAFF_OK) return sst;
+    }
+    // --- output (caller order)
+    hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.x,
+                       (const int32_t*)c->perm, c->n, s, Xout, 1);
+    CHAFF_LAUNCH_CHECK();
+    CHAFF_HIP(hipStreamSynchronize(st));
+    double worst = 0.0;
+    for (int64_t i = 0; i < nsys; ++i) worst = std::max(worst, rel[i]);
+    if (rel_res_out)
+        for (int64_t i = 0; i < nsys; ++i) rel_res_out[i] = rel[i];
+    if (stats) {
+        stats->cycles = cycles;
+        stats->iterations = iters;
+        stats->max_rel_residual = worst;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (!converged)
+        return fail(CHAFF_ENOCONV, "no convergence after " + std::to_string(cycles) +
+                                       " cycles; max relative residual " + std::to_string(worst));
+    return CHAFF_OK;
+}
+
+chaff_status solve(Cloud* c, const chaff_solve_opts* o, const void* Z, const void* Pinv, const double* k_hat,
+                   const double* e_hat, int64_t s, void* X, void* ws, size_t ws_bytes, chaff_solve_stats* st_out,
+                   double* rel_res, hipStream_t st) {
+    if (o->prec == CHAFF_C64)
+        return solve_impl<c64, c64>(c, o, (const c64*)Z, (const c64*)Pinv, k_hat, e_hat, s, (c128*)X, ws,
+                                    ws_bytes, st_out, rel_res, st);
+    return solve_impl<c128, c128>(c, o, (const c128*)Z, (const c128*)Pinv, k_hat, e_hat, s, (c128*)X, ws,
+                                  ws_bytes, st_out, rel_res, st);
+}
+
+chaff_status excitation(Cloud* c, const double* k_hat, const double* e_hat, int64_t s, void* U, hipStream_t st) {
+    const double k = 2.0 * PI_K / c->wavelength;
+    hipLaunchKernelGGL(k_excitation, dim3(blocks_for(c->n * s)), dim3(256), 0, st, (const Wire*)c->wires,
+                       (const int32_t*)c->perm, c->n, k_hat, e_hat, s, k, (c128*)U);
+    CHAFF_LAUNCH_CHECK();
+    return CHAFF_OK;
+}
+
+}  // namespace chaff
