@@ -32,18 +32,23 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed) peak, TFLOP/s
 
 CONFIGS = {
-    # name: (workload factory kwargs, prec, restart, description)
-    "c1": dict(prec="c128", restart=60, desc="64 half-wave wires, 10-wavelength cube, d_c=2 lambda, "
-                                              "1 incidence, complex128"),
-    "c2": dict(prec="c64", restart=30, desc="2,000 wires, Gaussian sigma=15 lambda, d_c=1.5 lambda, "
-                                             "1 incidence, complex64 + FP64 refinement"),
-    "c3": dict(prec="c64", restart=20, desc="20,000-wire Gaussian cloud + 16 side clouds (500-5,000 wires), "
-                                             "d_c=2 lambda, 360 azimuth incidences, one launch per stage"),
-    "c4_eval": dict(prec="c64", restart=20, desc="100,000 wires, uniform sphere R=40 lambda, d_c=1.5 lambda, "
-                                                  "8 incidences"),
-    "c5": dict(prec="c64", restart=10, desc="1,000,000 wires (7M unknowns), uniform sphere R=50 lambda, "
-                                             "d_c=1 lambda, 64 azimuth incidences, complex64 + FP64 refinement"),
+    # prec: Krylov/fill precision; method: Krylov method per refinement cycle;
+    # restart: GMRES cycle length or COCG step cap; inner_tol: reduction per cycle
+    "c1": dict(prec="c128", method="gmres", restart=60, inner_tol=1e-4,
+               desc="64 half-wave wires, 10-wavelength cube, d_c=2 lambda, 1 incidence, complex128"),
+    "c2": dict(prec="c64", method="gmres", restart=30, inner_tol=1e-4,
+               desc="2,000 wires, Gaussian sigma=15 lambda, d_c=1.5 lambda, 1 incidence, "
+                    "complex64 + FP64 refinement"),
+    "c3": dict(prec="c64", method="gmres", restart=20, inner_tol=1e-4,
+               desc="20,000-wire Gaussian cloud + 16 side clouds (500-5,000 wires), d_c=2 lambda, "
+                    "360 azimuth incidences, one launch per stage for all 17 clouds"),
+    "c4_eval": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5,
+                    desc="100,000 wires, uniform sphere R=40 lambda, d_c=1.5 lambda, 8 incidences"),
+    "c5": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5,
+               desc="1,000,000 wires (7M unknowns), uniform sphere R=50 lambda, d_c=1 lambda, "
+                    "64 azimuth incidences, complex64 + FP64 refinement"),
 }
+METHODS = {"gmres": 0, "cocg": 1, "cocg_rr": 2}
 
 
 def make_workload(name):
@@ -122,6 +127,8 @@ def main(argv=None) -> int:
     ap.add_argument("--config", default="c5", choices=sorted(CONFIGS))
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=None)
+    ap.add_argument("--method", default=None, choices=sorted(METHODS))
+    ap.add_argument("--inner-tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
     a = ap.parse_args(argv)
@@ -144,7 +151,9 @@ def main(argv=None) -> int:
     kh = torch.as_tensor(wl.inc.k_hat, device="cuda")
     eh = torch.as_tensor(wl.inc.e_hat, device="cuda")
     R = kh.shape[0]
-    opts = B.solve_opts(tol=a.tol, restart=restart, max_cycles=60, prec=prec)
+    method = a.method or cfg["method"]
+    opts = B.solve_opts(tol=a.tol, restart=restart, max_cycles=60, prec=prec, method=METHODS[method],
+                        inner_tol=a.inner_tol or cfg["inner_tol"])
     torch.cuda.synchronize()
 
     def step():
@@ -215,7 +224,8 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {"workload": a.config, "description": cfg["desc"], "wires": int(wl.cloud.n),
                    "clouds": int(wl.cloud.n_clouds), "rhs": int(R), "unknowns": int(wl.cloud.n * 7),
-                   "nnzb": int(cl.nnzb), "pairs": int(cl.n_pairs), "restart": restart, "tol": a.tol},
+                   "nnzb": int(cl.nnzb), "pairs": int(cl.n_pairs), "method": method, "restart": restart,
+                   "tol": a.tol},
         "solver": {"cycles": infos[-1]["cycles"], "iterations": infos[-1]["iterations"],
                    "max_rel_residual": infos[-1]["max_rel_residual"],
                    "systems_per_step": int(wl.cloud.n_clouds * R), "solved_total": solved},

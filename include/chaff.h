@@ -150,8 +150,16 @@ typedef struct {
     int32_t use_x0;           /* 1: X holds an initial guess on entry */
     int32_t prec;             /* chaff_prec of Z, Pinv and the Krylov vectors */
     int32_t spmm_variant;     /* -1: autotuned/heuristic choice; else a fixed kernel variant */
-    int32_t reserved;
+    int32_t method;           /* chaff_method */
 } chaff_solve_opts;
+
+/* Krylov method of each refinement cycle.  GMRES(m) with classical
+ * Gram-Schmidt applied twice; COCG = conjugate-orthogonal CG, valid because
+ * Z and its block-diagonal inverse are complex symmetric (bilinear a^T b),
+ * with five vectors and no restart inside a cycle.  CHAFF_COCG restarts the
+ * recurrence at every refinement checkpoint; CHAFF_COCG_RR keeps the search
+ * direction and only replaces the recursive residual by the FP64 true one. */
+typedef enum { CHAFF_GMRES = 0, CHAFF_COCG = 1, CHAFF_COCG_RR = 2 } chaff_method;
 
 typedef struct {
     int32_t cycles;           /* refinement sweeps (= GMRES restart cycles) run */
@@ -161,7 +169,8 @@ typedef struct {
 } chaff_solve_stats;
 
 size_t chaff_solve_workspace_bytes(chaff_cloud c, const chaff_solve_opts* o, int64_t n_rhs);
-/*   Z, Pinv  from chaff_fill_Z with the same prec.
+/*   Z, Pinv  from chaff_fill_Z with the same prec (COCG needs both symmetric: they are).
+ *   restart  GMRES cycle length, or the step cap of one COCG cycle.
  *   k_hat, e_hat [R][3] double: propagation direction and polarisation (unit).
  *   X        [N*7][R] complex double, caller order; input guess if use_x0.
  *   ws       device workspace of chaff_solve_workspace_bytes.

@@ -50,7 +50,7 @@ class CloudInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("restart", C.c_int32),
                 ("max_cycles", C.c_int32), ("use_x0", C.c_int32), ("prec", C.c_int32),
-                ("spmm_variant", C.c_int32), ("reserved", C.c_int32)]
+                ("spmm_variant", C.c_int32), ("method", C.c_int32)]
 
 
 class KernelTime(C.Structure):
@@ -274,9 +274,12 @@ def fill_Z(cl: Cloud, prec: int = C64, with_pinv: bool = True):
     return Z, P
 
 
+GMRES, COCG, COCG_RR = 0, 1, 2
+
+
 def solve_opts(tol=1e-6, inner_tol=1e-4, restart=30, max_cycles=50, use_x0=False, prec=C64,
-               spmm_variant=-1) -> SolveOpts:
-    return SolveOpts(tol, inner_tol, restart, max_cycles, int(use_x0), prec, spmm_variant, 0)
+               spmm_variant=-1, method=GMRES) -> SolveOpts:
+    return SolveOpts(tol, inner_tol, restart, max_cycles, int(use_x0), prec, spmm_variant, method)
 
 
 def solve(cl: Cloud, Z, Pinv, k_hat, e_hat, opts: SolveOpts | None = None, x0=None,

@@ -182,10 +182,14 @@ static chaff_status check_opts(const chaff_solve_opts* o) {
     if (!o) return fail(CHAFF_EINVAL, "opts is NULL");
     if (!(o->tol > 0) || !(o->tol < 1)) return fail(CHAFF_EINVAL, "tol must be in (0, 1)");
     if (!(o->inner_tol > 0) || !(o->inner_tol < 1)) return fail(CHAFF_EINVAL, "inner_tol must be in (0, 1)");
-    if (o->restart < 1 || o->restart > 200) return fail(CHAFF_EINVAL, "restart must be in [1, 200]");
+    if (o->restart < 1 || (o->method == CHAFF_GMRES && o->restart > 200))
+        return fail(CHAFF_EINVAL, "restart must be in [1, 200] (GMRES) or >= 1 (COCG)");
     if (o->max_cycles < 1) return fail(CHAFF_EINVAL, "max_cycles must be >= 1");
     if (o->prec != CHAFF_C64 && o->prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
     if (o->spmm_variant < -1 || o->spmm_variant > 2) return fail(CHAFF_EINVAL, "spmm_variant must be in [-1, 2]");
+    if (o->method != CHAFF_GMRES && o->method != CHAFF_COCG && o->method != CHAFF_COCG_RR)
+        return fail(CHAFF_EINVAL, "method must be CHAFF_GMRES, CHAFF_COCG or CHAFF_COCG_RR");
+    if (o->method != CHAFF_GMRES && o->restart > 1000000) return fail(CHAFF_EINVAL, "restart too large");
     return CHAFF_OK;
 }
 

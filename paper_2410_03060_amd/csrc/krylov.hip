@@ -13,6 +13,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 
 namespace chaff {
 
@@ -466,7 +468,302 @@ __global__ void k_zero_bytes(uint32_t* __restrict__ a, int64_t nwords) {
         a[t] = 0u;
 }
 
+
+// ------------------------------------------------------------------ COCG (complex symmetric CG)
+// Z = Z^T exactly (each unique pair is filled once and stored twice, self
+// blocks are symmetric by construction) and the block-Jacobi inverse is
+// complex symmetric too, so the preconditioned conjugate-orthogonal CG
+// recurrence (bilinear form a^T b, no conjugation) applies: five vectors, no
+// restarts, one sparse product per step.
+
+struct CgState {
+    double rho, rho_im;             // r^T z of the current step
+    double rho_prev, rho_prev_im;   // r^T z of the previous step
+    double alpha_re, alpha_im;
+    double beta_re, beta_im;
+    double rnorm;                   // recursive ||r|| (in units of the run's scale)
+    double target;                  // freeze once rnorm <= target
+    double ckpt;                    // end the cycle once every system is below its checkpoint
+    int32_t done;
+    int32_t pad;
+};
+
+// part[chunk][slot0][r] = sum a^T b ; part[chunk][slot0+1][r] = sum |c|^2 (if c)
+template <typename C>
+__global__ __launch_bounds__(RB) void k_dot2(const Chunk* __restrict__ chunks, const C* __restrict__ a,
+                                             const C* __restrict__ b, const C* __restrict__ c, int64_t s, int st,
+                                             c128* __restrict__ part, int nslot, int slot0) {
+    __shared__ c128 red[RB];
+    const Chunk ch = chunks[blockIdx.x];
+    const RowMap m = rowmap(st);
+    c128 acc = {0, 0}, acc2 = {0, 0};
+    if (m.r < s) {
+        for (int64_t row = ch.w0 * NB + m.rsub; row < ch.w1 * NB; row += RB / st) {
+            const int64_t o = row * s + m.r;
+            cfma(acc, ccast<c128>(a[o]), ccast<c128>(b[o]));
+            if (c) {
+                c128 v = ccast<c128>(c[o]);
+                acc2.re += v.re * v.re + v.im * v.im;
+            }
+        }
+    }
+    c128 v = block_col_reduce(acc, st, red);
+    if (threadIdx.x < st && m.r < s) part[((int64_t)blockIdx.x * nslot + slot0) * s + m.r] = v;
+    if (c) {
+        c128 v2 = block_col_reduce(acc2, st, red);
+        if (threadIdx.x < st && m.r < s) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + m.r] = v2;
+    }
+}
+
+// alpha = rho / (p^T q)
+__global__ void k_cg_alpha(int64_t nsys, const c128* __restrict__ pq, CgState* __restrict__ cg) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsys) return;
+    CgState S = cg[t];
+    const c128 d = pq[t];
+    const double dd = d.re * d.re + d.im * d.im;
+    if (S.done || !(dd > 0.0) || !isfinite(dd)) {
+        S.alpha_re = S.alpha_im = 0.0;
+        S.done = 1;
+    } else {
+        const c128 rho = {S.rho, S.rho_im};
+        const c128 a = cmul(rho, c128{d.re / dd, -d.im / dd});
+        S.alpha_re = a.re;
+        S.alpha_im = a.im;
+    }
+    cg[t] = S;
+}
+
+// x += alpha p ; r -= alpha q
+template <typename C>
+__global__ void k_cg_xr(const int32_t* __restrict__ wire_cloud, const CgState* __restrict__ cg, int64_t n_rows,
+                        int64_t s, const C* __restrict__ p, const C* __restrict__ q, C* __restrict__ x,
+                        C* __restrict__ r) {
+    using R = typename real_of<C>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s) return;
+    const int64_t row = t / s, rr = t - (t / s) * s;
+    const CgState& S = cg[(int64_t)wire_cloud[row / NB] * s + rr];
+    const cplx<R> a = {(R)S.alpha_re, (R)S.alpha_im};
+    cplx<R> xv = x[t], rv = r[t];
+    cfma(xv, a, p[t]);
+    cfma(rv, cplx<R>{-a.re, -a.im}, q[t]);
+    x[t] = xv;
+    r[t] = rv;
+}
+
+// beta = rho_new / rho, convergence flags (rz = r^T z, rr = ||r||^2)
+__global__ void k_cg_beta(int64_t nsys, const c128* __restrict__ rz, const c128* __restrict__ rr,
+                          CgState* __restrict__ cg, int32_t* __restrict__ n_active) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsys) return;
+    CgState S = cg[t];
+    const double rn = sqrt(fmax(rr[t].re, 0.0));
+    if (!S.done) S.rnorm = rn;
+    const c128 rho_old = {S.rho, S.rho_im};
+    const c128 rho_new = rz[t];
+    const double d = rho_old.re * rho_old.re + rho_old.im * rho_old.im;
+    if (S.done || rn <= S.target || !(d > 0.0) || !isfinite(rn)) {
+        S.done = 1;
+        S.beta_re = S.beta_im = 0.0;
+    } else {
+        const c128 b = cmul(rho_new, c128{rho_old.re / d, -rho_old.im / d});
+        S.beta_re = b.re;
+        S.beta_im = b.im;
+        S.rho = rho_new.re;
+        S.rho_im = rho_new.im;
+    }
+    cg[t] = S;
+    if (!S.done) atomicAdd(n_active, 1);
+}
+
+// p = z + beta p
+template <typename C>
+__global__ void k_cg_p(const int32_t* __restrict__ wire_cloud, const CgState* __restrict__ cg, int64_t n_rows,
+                       int64_t s, const C* __restrict__ z, C* __restrict__ p) {
+    using R = typename real_of<C>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s) return;
+    const int64_t row = t / s, rr = t - (t / s) * s;
+    const CgState& S = cg[(int64_t)wire_cloud[row / NB] * s + rr];
+    cplx<R> pv = z[t];
+    cfma(pv, cplx<R>{(R)S.beta_re, (R)S.beta_im}, p[t]);
+    p[t] = pv;
+}
+
+// x64 += scale(system) * xc
+template <typename C>
+__global__ void k_add_scaled(const int32_t* __restrict__ wire_cloud, const double* __restrict__ scale, int64_t n_rows,
+                             int64_t s, const C* __restrict__ xc, c128* __restrict__ x) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s) return;
+    const int64_t row = t / s, rr = t - (t / s) * s;
+    const double f = scale[(int64_t)wire_cloud[row / NB] * s + rr];
+    const c128 v = ccast<c128>(xc[t]);
+    x[t] = c128{x[t].re + f * v.re, x[t].im + f * v.im};
+}
+
+// Fused COCG kernels (chunk-structured so that the bilinear forms reduce per
+// cloud in a fixed order).  Thread (rsub, r): RHS column r of wire rows
+// i = w0 + rsub, w0 + rsub + 256/ST, ... of the block's chunk.
+
+// q = Z p for the chunk's block rows, with sigma = p^T q accumulated in FP64
+template <typename CZ, typename C, int ST>
+__global__ __launch_bounds__(RB) void k_spmm_dot(const Chunk* __restrict__ chunks, const int64_t* __restrict__ row_ptr,
+                                                 const int32_t* __restrict__ col_idx, const CZ* __restrict__ Z,
+                                                 const C* __restrict__ P, C* __restrict__ Q, int64_t s,
+                                                 c128* __restrict__ part, int nslot, int slot) {
+    using R = typename real_of<C>::type;
+    __shared__ c128 red[RB];
+    const Chunk ch = chunks[blockIdx.x];
+    const int rsub = threadIdx.x / ST;
+    const int64_t r = (int64_t)blockIdx.y * ST + threadIdx.x % ST;
+    c128 dot = {0, 0};
+    if (r < s) {
+        for (int64_t i = ch.w0 + rsub; i < ch.w1; i += RB / ST) {
+            cplx<R> acc[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                const int64_t col = col_idx[e];
+                const CZ* zb = Z + e * NB2;
+                const C* xb = P + col * NB * s + r;
+                cplx<R> x[NB];
+#pragma unroll
+                for (int k = 0; k < NB; ++k) x[k] = xb[k * s];
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) cfma(acc[q], ccast<cplx<R>>(zb[q * NB + k]), x[k]);
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int64_t o = (i * NB + q) * s + r;
+                Q[o] = acc[q];
+                cfma(dot, ccast<c128>(P[o]), ccast<c128>(acc[q]));
+            }
+        }
+    }
+    c128 v = block_col_reduce(dot, ST, red);
+    if (threadIdx.x < ST && r < s) part[((int64_t)blockIdx.x * nslot + slot) * s + r] = v;
+}
+
+// x += alpha p ; r -= alpha q ; z = P_i r ; partial r^T z and ||r||^2
+template <typename CZ, typename C, int ST>
+__global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
+                                                  const CZ* __restrict__ Pinv, const C* __restrict__ p,
+                                                  const C* __restrict__ q, C* __restrict__ x, C* __restrict__ rv,
+                                                  C* __restrict__ z, int64_t s, c128* __restrict__ part, int nslot,
+                                                  int slot0) {
+    using R = typename real_of<C>::type;
+    __shared__ c128 red[RB];
+    const Chunk ch = chunks[blockIdx.x];
+    const int rsub = threadIdx.x / ST;
+    const int64_t r = (int64_t)blockIdx.y * ST + threadIdx.x % ST;
+    c128 rz = {0, 0}, rr = {0, 0};
+    if (r < s) {
+        const CgState& S = cg[(int64_t)ch.cloud * s + r];
+        const cplx<R> a = {(R)S.alpha_re, (R)S.alpha_im};
+        const cplx<R> na = {-a.re, -a.im};
+        for (int64_t i = ch.w0 + rsub; i < ch.w1; i += RB / ST) {
+            cplx<R> res[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const int64_t o = (i * NB + k) * s + r;
+                cplx<R> xv = x[o], pv = p[o], rk = rv[o], qv = q[o];
+                cfma(xv, a, pv);
+                cfma(rk, na, qv);
+                x[o] = xv;
+                rv[o] = rk;
+                res[k] = rk;
+            }
+            const CZ* pb = Pinv + i * NB2;
+#pragma unroll
+            for (int qq = 0; qq < NB; ++qq) {
+                cplx<R> acc = {0, 0};
+#pragma unroll
+                for (int k = 0; k < NB; ++k) cfma(acc, ccast<cplx<R>>(pb[qq * NB + k]), res[k]);
+                z[(i * NB + qq) * s + r] = acc;
+                cfma(rz, ccast<c128>(res[qq]), ccast<c128>(acc));
+                rr.re += (double)res[qq].re * res[qq].re + (double)res[qq].im * res[qq].im;
+            }
+        }
+    }
+    c128 v = block_col_reduce(rz, ST, red);
+    if (threadIdx.x < ST && r < s) part[((int64_t)blockIdx.x * nslot + slot0) * s + r] = v;
+    c128 v2 = block_col_reduce(rr, ST, red);
+    if (threadIdx.x < ST && r < s) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + r] = v2;
+}
+
+// After the update: new rho = r^T z, recursive norm; convergence and checkpoint
+// flags; beta for p = z + beta p.  mode 0: first step of a run (beta = 0);
+// mode 1: ordinary step; mode 2: step right after a residual replacement
+// (rho_prev is kept as the denominator).
+__global__ void k_cg_step(int64_t nsys, const c128* __restrict__ rz, const c128* __restrict__ rr, int mode,
+                          CgState* __restrict__ cg, int32_t* __restrict__ n_active) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsys) return;
+    CgState S = cg[t];
+    const double rn = sqrt(fmax(rr[t].re, 0.0));
+    const c128 rho_new = rz[t];
+    if (!S.done) S.rnorm = rn;
+    if (!S.done && (rn <= S.target || !isfinite(rn))) S.done = 1;
+    const c128 den = (mode == 1) ? c128{S.rho, S.rho_im} : c128{S.rho_prev, S.rho_prev_im};
+    const double dd = den.re * den.re + den.im * den.im;
+    if (S.done) {
+        S.beta_re = S.beta_im = 0.0;
+        S.alpha_re = S.alpha_im = 0.0;
+    } else if (mode == 0 || !(dd > 0.0)) {
+        S.beta_re = S.beta_im = 0.0;
+    } else {
+        const c128 b = cmul(rho_new, c128{den.re / dd, -den.im / dd});
+        S.beta_re = b.re;
+        S.beta_im = b.im;
+    }
+    if (mode == 1) {
+        S.rho_prev = S.rho;
+        S.rho_prev_im = S.rho_im;
+    }
+    S.rho = rho_new.re;
+    S.rho_im = rho_new.im;
+    cg[t] = S;
+    if (!S.done && rn > S.ckpt) atomicAdd(n_active, 1);
+}
+
+// start of a cycle: targets, checkpoint, alpha = 0 (the update kernel then only forms z)
+__global__ void k_cg_cycle_start(int64_t nsys, const double* __restrict__ target, const double* __restrict__ ckpt,
+                                 const int32_t* __restrict__ active, int first, CgState* __restrict__ cg) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsys) return;
+    CgState S = first ? CgState{} : cg[t];
+    S.target = target[t];
+    S.ckpt = ckpt[t];
+    S.done = active[t] ? 0 : 1;
+    S.alpha_re = S.alpha_im = 0.0;
+    cg[t] = S;
+}
+
+// rho = r^T z at the start of a cycle
+__global__ void k_cg_init(int64_t nsys, const c128* __restrict__ rz, const int32_t* __restrict__ active,
+                          const double* __restrict__ target, CgState* __restrict__ cg) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsys) return;
+    CgState S{};
+    S.rho = rz[t].re;
+    S.rho_im = rz[t].im;
+    S.rnorm = 1.0;
+    S.target = target[t];
+    S.done = active[t] ? 0 : 1;
+    cg[t] = S;
+}
+
 // ------------------------------------------------------------------ host driver
+
+// CHAFF_VERBOSE=1 in the environment prints one line per refinement cycle
+static const bool g_verbose = [] {
+    const char* v = std::getenv("CHAFF_VERBOSE");
+    return v && v[0] == '1';
+}();
 
 static unsigned blocks_for(int64_t n, int threads = 256) {
     return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads);
@@ -483,6 +780,9 @@ struct SolveLayout {
     c128 *H, *G, *sn, *Y;            // per system
     double *cs, *bn, *rn, *inv_rn;   // per system
     SysState* sys;
+    CgState* cg;
+    double* target;
+    int32_t* active;
     Chunk* chunks;
     int32_t* cloud_chunk_off;
     int32_t* counter;
@@ -491,18 +791,22 @@ struct SolveLayout {
 struct SolveShape {
     int64_t n, rows, s, nsys;
     int m, nslot, n_chunks, n_clouds;
+    int method, nvec, mg;   // mg: Hessenberg width (GMRES m, COCG 1)
     size_t csize;
 };
 
-static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec) {
+static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec, int method) {
     SolveShape sh;
+    sh.method = method;
+    sh.mg = method != CHAFF_GMRES ? 1 : m;
+    sh.nvec = method != CHAFF_GMRES ? 5 : m + 1;
     sh.n = c->n;
     sh.rows = c->n * NB;
     sh.s = s;
     sh.n_clouds = c->n_clouds;
     sh.nsys = (int64_t)c->n_clouds * s;
     sh.m = m;
-    sh.nslot = m + 2;
+    sh.nslot = sh.mg + 3;
     const int64_t cw = std::max<int64_t>(32, (c->n + 2047) / 2048);
     int64_t nch = 0;
     for (int k = 0; k < c->n_clouds; ++k) {
@@ -521,23 +825,27 @@ static SolveLayout carve_solve(void* ws, size_t ws_bytes, const SolveShape& sh) 
     L.b = cv.take<c128>(vs);
     L.x = cv.take<c128>(vs);
     L.r = cv.take<c128>(vs);
-    L.V = cv.take<char>((size_t)(sh.m + 1) * vs * sh.csize);
-    L.W = cv.take<char>((size_t)vs * sh.csize);
-    L.T = cv.take<char>((size_t)vs * sh.csize);
+    const bool gm = sh.method == CHAFF_GMRES;
+    L.V = cv.take<char>((size_t)sh.nvec * vs * sh.csize);
+    L.W = gm ? cv.take<char>((size_t)vs * sh.csize) : nullptr;
+    L.T = gm ? cv.take<char>((size_t)vs * sh.csize) : nullptr;
     L.part = cv.take<c128>((size_t)std::max(sh.n_chunks, 1) * sh.nslot * sh.s);
-    L.h1 = cv.take<c128>((size_t)(sh.m + 1) * sh.nsys);
-    L.h2 = cv.take<c128>((size_t)(sh.m + 1) * sh.nsys);
+    L.h1 = cv.take<c128>((size_t)(sh.mg + 1) * sh.nsys);
+    L.h2 = cv.take<c128>((size_t)(sh.mg + 1) * sh.nsys);
     L.nrm = cv.take<c128>((size_t)sh.nsys);
     L.red = cv.take<c128>((size_t)sh.nsys);
-    L.H = cv.take<c128>((size_t)sh.nsys * (sh.m + 1) * sh.m);
-    L.G = cv.take<c128>((size_t)sh.nsys * (sh.m + 1));
-    L.sn = cv.take<c128>((size_t)sh.nsys * sh.m);
-    L.Y = cv.take<c128>((size_t)sh.nsys * (sh.m + 1));
-    L.cs = cv.take<double>((size_t)sh.nsys * sh.m);
+    L.H = cv.take<c128>((size_t)sh.nsys * (sh.mg + 1) * sh.mg);
+    L.G = cv.take<c128>((size_t)sh.nsys * (sh.mg + 1));
+    L.sn = cv.take<c128>((size_t)sh.nsys * sh.mg);
+    L.Y = cv.take<c128>((size_t)sh.nsys * (sh.mg + 1));
+    L.cs = cv.take<double>((size_t)sh.nsys * sh.mg);
     L.bn = cv.take<double>((size_t)sh.nsys);
     L.rn = cv.take<double>((size_t)sh.nsys);
     L.inv_rn = cv.take<double>((size_t)sh.nsys);
     L.sys = cv.take<SysState>((size_t)sh.nsys);
+    L.cg = cv.take<CgState>((size_t)sh.nsys);
+    L.target = cv.take<double>((size_t)sh.nsys);
+    L.active = cv.take<int32_t>((size_t)sh.nsys);
     L.chunks = cv.take<Chunk>((size_t)std::max(sh.n_chunks, 1));
     L.cloud_chunk_off = cv.take<int32_t>((size_t)sh.n_clouds + 1);
     L.counter = cv.take<int32_t>(64);
@@ -547,7 +855,7 @@ static SolveLayout carve_solve(void* ws, size_t ws_bytes, const SolveShape& sh) 
 
 size_t solve_workspace_bytes(const Cloud* c, const chaff_solve_opts* o, int64_t s) {
     const int m = o->restart;
-    SolveShape sh = solve_shape(c, m, s, (chaff_prec)o->prec);
+    SolveShape sh = solve_shape(c, m, s, (chaff_prec)o->prec, o->method);
     return carve_solve(nullptr, 0, sh).bytes;
 }
 
@@ -567,13 +875,126 @@ static chaff_status norms_to(const SolveShape& sh, SolveLayout& L, const C* v, c
     return CHAFF_OK;
 }
 
+
+template <typename CZ, typename C, int ST>
+static void launch_cg_update(const SolveShape& sh, SolveLayout& L, const CZ* Pinv, C* V, int64_t vs, hipStream_t st) {
+    const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
+    hipLaunchKernelGGL((k_cg_update<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const CgState*)L.cg,
+                       Pinv, (const C*)(V + 3 * vs), (const C*)(V + 4 * vs), V, V + vs, V + 2 * vs, sh.s, L.part,
+                       sh.nslot, 0);
+}
+template <typename CZ, typename C, int ST>
+static void launch_spmm_dot(const Cloud* c, const SolveShape& sh, SolveLayout& L, const CZ* Z, C* V, int64_t vs,
+                            hipStream_t st) {
+    const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
+    hipLaunchKernelGGL((k_spmm_dot<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks,
+                       (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, Z, (const C*)(V + 3 * vs), V + 4 * vs,
+                       sh.s, L.part, sh.nslot, 2);
+}
+
+// One COCG refinement cycle.  L.r holds the FP64 true residual; it replaces the
+// recursive residual (in units of the run's fixed per-system scale), while the
+// search direction p and r^T z carry over from the previous cycle ("reliable
+// updates"): no Krylov information is thrown away at a refinement checkpoint.
+// The cycle ends once every active system's recursive residual fell below its
+// checkpoint (or its final target); then x += scale * (accumulated correction).
+template <typename C, typename CZ>
+static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveShape& sh, SolveLayout& L,
+                               const CZ* Z, const CZ* Pinv, const std::vector<double>& target,
+                               const std::vector<double>& ckpt, const std::vector<int32_t>& act, bool first,
+                               int& iters, hipStream_t st) {
+    const int64_t rows = sh.rows, s = sh.s, vs = rows * s, nsys = sh.nsys;
+    C* V = static_cast<C*>(L.V);   // [x_c | r | z | p | q]
+    C* xc = V;
+    C* r = V + vs;
+    C* p = V + 3 * vs;
+    const int wst = spmm_tile_width(s);
+    const bool use_rr = o->method == CHAFF_COCG_RR;
+    CHAFF_HIP(hipMemcpyAsync(L.target, target.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
+    CHAFF_HIP(hipMemcpyAsync(L.h2, ckpt.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
+    CHAFF_HIP(hipMemcpyAsync(L.active, act.data(), nsys * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_cg_cycle_start, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const double*)L.target,
+                       (const double*)L.h2, (const int32_t*)L.active, first ? 1 : 0, L.cg);
+    CHAFF_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_start_vector<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.r,
+                       (const int32_t*)c->wire_cloud, (const double*)L.inv_rn, sh.n_clouds, rows, s, r);
+    CHAFF_LAUNCH_CHECK();
+    const int64_t words = vs * (int64_t)sizeof(C) / 4;
+    hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(words)), dim3(256), 0, st, (uint32_t*)xc, words);
+    CHAFF_LAUNCH_CHECK();
+    if (first || !use_rr) {   // p and q enter the first step multiplied by zero: they must be finite
+        hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(2 * words)), dim3(256), 0, st, (uint32_t*)p, 2 * words);
+        CHAFF_LAUNCH_CHECK();
+    }
+    CHAFF_HIP(hipStreamSynchronize(st));   // host staging vectors may leave scope
+    int mode = (first || !use_rr) ? 0 : 2;
+    for (int k = 0; k <= o->restart; ++k) {
+        {   // x += alpha p, r -= alpha q, z = P r, r^T z, ||r||^2 (alpha = 0 on entry)
+            ProfScope pu("k_cg_update", st, (7.0 * vs + 0.0) * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
+            switch (wst) {
+                case 1: launch_cg_update<CZ, C, 1>(sh, L, Pinv, V, vs, st); break;
+                case 2: launch_cg_update<CZ, C, 2>(sh, L, Pinv, V, vs, st); break;
+                case 4: launch_cg_update<CZ, C, 4>(sh, L, Pinv, V, vs, st); break;
+                case 8: launch_cg_update<CZ, C, 8>(sh, L, Pinv, V, vs, st); break;
+                case 16: launch_cg_update<CZ, C, 16>(sh, L, Pinv, V, vs, st); break;
+                case 32: launch_cg_update<CZ, C, 32>(sh, L, Pinv, V, vs, st); break;
+                default: launch_cg_update<CZ, C, 64>(sh, L, Pinv, V, vs, st); break;
+            }
+        }
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for(2 * nsys)), dim3(256), 0, st, (const c128*)L.part,
+                           (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, 2, s, L.h1);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)L.counter, (int64_t)1);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cg_step, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const c128*)L.h1,
+                           (const c128*)(L.h1 + nsys), mode, L.cg, L.counter);
+        CHAFF_LAUNCH_CHECK();
+        int32_t n_act = 0;
+        CHAFF_HIP(hipMemcpyAsync(&n_act, L.counter, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        CHAFF_HIP(hipStreamSynchronize(st));
+        if (n_act == 0 || k == o->restart) break;
+        mode = 1;
+        ++iters;
+        {
+            ProfScope pp("k_cg_p", st, 3.0 * vs * sizeof(C));
+            hipLaunchKernelGGL((k_cg_p<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const int32_t*)c->wire_cloud,
+                               (const CgState*)L.cg, rows, s, (const C*)(V + 2 * vs), p);
+        }
+        CHAFF_LAUNCH_CHECK();
+        {   // q = Z p and p^T q
+            ProfScope ps("spmm", st, ((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 8.0 * (c->n + 1) +
+                                         3.0 * vs * sizeof(C));
+            switch (wst) {
+                case 1: launch_spmm_dot<CZ, C, 1>(c, sh, L, Z, V, vs, st); break;
+                case 2: launch_spmm_dot<CZ, C, 2>(c, sh, L, Z, V, vs, st); break;
+                case 4: launch_spmm_dot<CZ, C, 4>(c, sh, L, Z, V, vs, st); break;
+                case 8: launch_spmm_dot<CZ, C, 8>(c, sh, L, Z, V, vs, st); break;
+                case 16: launch_spmm_dot<CZ, C, 16>(c, sh, L, Z, V, vs, st); break;
+                case 32: launch_spmm_dot<CZ, C, 32>(c, sh, L, Z, V, vs, st); break;
+                default: launch_spmm_dot<CZ, C, 64>(c, sh, L, Z, V, vs, st); break;
+            }
+        }
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for(nsys)), dim3(256), 0, st, (const c128*)L.part,
+                           (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 2, 1, s, L.nrm);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cg_alpha, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const c128*)L.nrm, L.cg);
+        CHAFF_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL((k_add_scaled<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const int32_t*)c->wire_cloud,
+                       (const double*)L.rn, rows, s, (const C*)xc, L.x);
+    CHAFF_LAUNCH_CHECK();
+    return CHAFF_OK;
+}
+
 template <typename C, typename CZ>
 static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z, const CZ* Pinv,
                                const double* k_hat, const double* e_hat, int64_t s, c128* Xout, void* ws,
                                size_t ws_bytes, chaff_solve_stats* stats, double* rel_res_out, hipStream_t st) {
     auto t_start = std::chrono::steady_clock::now();
     const int m = o->restart;
-    SolveShape sh = solve_shape(c, m, s, (chaff_prec)o->prec);
+    SolveShape sh = solve_shape(c, m, s, (chaff_prec)o->prec, o->method);
     SolveLayout L = carve_solve(ws, ws_bytes, sh);
     if (L.bytes > ws_bytes)
         return fail(CHAFF_EWORKSPACE, "solve workspace too small: need " + std::to_string(L.bytes));
@@ -626,7 +1047,7 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     const bool refine = std::is_same<C, c64>::value;
     int cycles = 0, iters = 0;
     bool converged = false;
-    std::vector<double> hinv(nsys), hrn(nsys);
+    std::vector<double> hinv(nsys), hrn(nsys), cocg_scale;
     std::vector<SysState> hsys(nsys);
     for (;;) {
         // true residual r = b - Z x (FP64 accumulation over the stored Z)
@@ -662,11 +1083,35 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
             S.target = refine ? std::max(o->inner_tol, std::min(need, 1.0) * 0.5) : std::min(need * 0.5, 1.0);
             hsys[i] = S;
         }
+        if (g_verbose)
+            std::fprintf(stderr, "[chaff] cycle %d: active %lld max rel residual %.3e (iterations so far %d)\n",
+                         cycles, (long long)active, worst, iters);
         if (active == 0) { converged = true; break; }
         if (cycles >= o->max_cycles) break;
         ++cycles;
         CHAFF_HIP(hipMemcpyAsync(L.rn, hrn.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
         CHAFF_HIP(hipMemcpyAsync(L.inv_rn, hinv.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
+        if (sh.method != CHAFF_GMRES) {
+            // fixed per-system scale for the whole run (set by the first cycle)
+            const bool first = cocg_scale.empty();
+            if (first) cocg_scale.assign(nsys, 0.0);
+            std::vector<double> tg(nsys), ck(nsys), sc_inv(nsys), sc(nsys);
+            std::vector<int32_t> act(nsys);
+            for (int64_t i = 0; i < nsys; ++i) {
+                const double rn = std::sqrt(std::max(hr[i].re, 0.0));
+                if (cocg_scale[i] <= 0.0) cocg_scale[i] = rn > 0 ? rn : 1.0;
+                sc[i] = hsys[i].done ? 0.0 : cocg_scale[i];
+                sc_inv[i] = hsys[i].done ? 0.0 : 1.0 / cocg_scale[i];
+                act[i] = hsys[i].done ? 0 : 1;
+                tg[i] = 0.5 * o->tol * bnorm[i] / cocg_scale[i];
+                ck[i] = std::max(tg[i], o->inner_tol * rn / cocg_scale[i]);
+            }
+            CHAFF_HIP(hipMemcpyAsync(L.rn, sc.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
+            CHAFF_HIP(hipMemcpyAsync(L.inv_rn, sc_inv.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
+            sst = cocg_cycle<C, CZ>(c, o, sh, L, Z, Pinv, tg, ck, act, first, iters, st);
+            if (sst != CHAFF_OK) return sst;
+            continue;
+        }
         CHAFF_HIP(hipMemcpyAsync(L.sys, hsys.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, st));
         // g = e_1 for every system
         {

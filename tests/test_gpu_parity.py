@@ -187,12 +187,16 @@ def test_c1_complex128_solve_and_bistatic_rcs(B, dense):
     assert abs(sm[0] - smo[0]) <= 1e-9 * smo[0]
 
 
-def test_c2_fp32_refined_solve(B):
+@pytest.mark.parametrize("method", ["gmres", "cocg"])
+def test_c2_fp32_refined_solve(B, method):
     wl = W.c2()
-    say("[solve] c2 complex64 + FP64 refinement to 1e-6")
+    say(f"[solve] c2 complex64 + FP64 refinement to 1e-6, {method}")
     cl = B.build_cloud(wl.cloud)
     Z, P = B.fill_Z(cl, B.C64)
-    X, info = B.solve(cl, Z, P, wl.inc.k_hat, wl.inc.e_hat, B.solve_opts(tol=1e-6))
+    meth = B.COCG if method == "cocg" else B.GMRES
+    X, info = B.solve(cl, Z, P, wl.inc.k_hat, wl.inc.e_hat,
+                      B.solve_opts(tol=1e-6, method=meth, restart=30 if meth == B.GMRES else 500,
+                                   inner_tol=1e-4 if meth == B.GMRES else 1e-2))
     say(f"  cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e}")
     assert info["max_rel_residual"] <= 1e-6
     Zs, _ = mom.snfc_matrix(wl.cloud)
@@ -208,7 +212,8 @@ def test_c2_fp32_refined_solve(B):
     assert e_db <= 0.1
 
 
-def test_multicloud_multirhs_one_launch(B):
+@pytest.mark.parametrize("method", ["gmres", "cocg"])
+def test_multicloud_multirhs_one_launch(B, method):
     """Three uneven clouds (one empty) x 6 azimuth RHS in one build/fill/solve/rcs."""
     lam = W.WAVELENGTH
     parts = [W.random_cloud(5, 400, box_lam=12.0, d_c_lam=2.0),
@@ -223,7 +228,10 @@ def test_multicloud_multirhs_one_launch(B):
     say(f"[solve] multi-cloud N={cloud.n} clouds={cloud.n_clouds} R=6")
     cl = B.build_cloud(cloud)
     Z, P = B.fill_Z(cl, B.C64)
-    X, info = B.solve(cl, Z, P, inc.k_hat, inc.e_hat, B.solve_opts(tol=1e-6))
+    meth = B.COCG if method == "cocg" else B.GMRES
+    X, info = B.solve(cl, Z, P, inc.k_hat, inc.e_hat,
+                      B.solve_opts(tol=1e-6, method=meth, restart=30 if meth == B.GMRES else 500,
+                                   inner_tol=1e-4 if meth == B.GMRES else 1e-2))
     say(f"  cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e}")
     assert info["max_rel_residual"] <= 1e-6
     Zs, _ = mom.snfc_matrix(cloud)
