@@ -131,7 +131,20 @@ def main(argv=None) -> int:
     ap.add_argument("--inner-tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     a = ap.parse_args(argv)
+    if a.copy_calibration:
+        import torch
+        n = 1 << 30
+        x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(4):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read_per_launch": n, "bytes_written_per_launch": n,
+                                               "launches": 4}}))
+        return 0
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); this build has no multi-GPU "
               "path. Run with --gpus 1.", file=sys.stderr)

@@ -186,7 +186,7 @@ static chaff_status check_opts(const chaff_solve_opts* o) {
         return fail(CHAFF_EINVAL, "restart must be in [1, 200] (GMRES) or >= 1 (COCG)");
     if (o->max_cycles < 1) return fail(CHAFF_EINVAL, "max_cycles must be >= 1");
     if (o->prec != CHAFF_C64 && o->prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
-    if (o->spmm_variant < -1 || o->spmm_variant > 2) return fail(CHAFF_EINVAL, "spmm_variant must be in [-1, 2]");
+    if (o->spmm_variant < -1 || o->spmm_variant > 4) return fail(CHAFF_EINVAL, "spmm_variant must be in [-1, 4]");
     if (o->method != CHAFF_GMRES && o->method != CHAFF_COCG && o->method != CHAFF_COCG_RR)
         return fail(CHAFF_EINVAL, "method must be CHAFF_GMRES, CHAFF_COCG or CHAFF_COCG_RR");
     if (o->method != CHAFF_GMRES && o->restart > 1000000) return fail(CHAFF_EINVAL, "restart too large");
@@ -229,7 +229,7 @@ chaff_status chaff_spmm(chaff_cloud h, chaff_prec prec, const void* Z, const voi
     if (!h || !Z || !X || !Y) return fail(CHAFF_EINVAL, "NULL argument");
     if (s < 1 || s > 65535) return fail(CHAFF_EINVAL, "s must be in [1, 65535]");
     if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "bad prec");
-    if (variant < -1 || variant > 2) return fail(CHAFF_EINVAL, "variant must be in [-1, 2]");
+    if (variant < -1 || variant > 4) return fail(CHAFF_EINVAL, "variant must be in [-1, 4]");
     return spmm_public(&h->c, prec, Z, X, Y, s, variant, (hipStream_t)stream);
     CHAFF_GUARD_END
 }

@@ -98,13 +98,67 @@ __global__ __launch_bounds__(256) void k_spmm_tile(const int64_t* __restrict__ r
     }
 }
 
+// Variant 3/4: the tile kernel with an XCD-aware workgroup order.  Workgroups
+// are dispatched round-robin over the 8 XCDs (id % 8), each with its own L2;
+// remapping id -> (row tile, column tile) so that XCD x walks rows
+// [x*n/8, (x+1)*n/8) in Morton order keeps the neighbour slabs a row gathers
+// inside that XCD's L2 while its neighbours are being processed.
+constexpr int NXCD = 8;
+template <typename CZ, typename CX, typename CY, int MODE, int ST>
+__global__ __launch_bounds__(256) void k_spmm_xcd(const int64_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col_idx,
+                                                  const CZ* __restrict__ Z, const CX* __restrict__ X,
+                                                  const CY* __restrict__ B, CY* __restrict__ Y,
+                                                  int64_t n, int64_t s, int64_t row_tiles, int col_tiles) {
+    using R = typename real_of<CY>::type;
+    const int rows_per_block = 256 / ST;
+    const int64_t id = blockIdx.x;
+    const int xcd = (int)(id % NXCD);
+    const int64_t local = id / NXCD;
+    const int64_t per_xcd = (row_tiles + NXCD - 1) / NXCD;
+    const int64_t tile = (int64_t)xcd * per_xcd + local / col_tiles;
+    const int ctile = (int)(local % col_tiles);
+    if (tile >= row_tiles) return;
+    const int sub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
+    const int64_t i = tile * rows_per_block + sub;
+    const int64_t r = (int64_t)ctile * ST + (threadIdx.x % ST);
+    if (i >= n) return;
+    const bool live = r < s;
+    const int64_t rc = live ? r : 0;
+    cplx<R> acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
+    const int64_t e1 = row_ptr[i + 1];
+    for (int64_t e = row_ptr[i]; e < e1; ++e) {
+        const int64_t col = col_idx[e];
+        const CZ* zb = Z + e * NB2;
+        const CX* xb = X + col * NB * s + rc;
+        cplx<R> x[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) x[k] = ccast<cplx<R>>(xb[k * s]);
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) cfma(acc[q], ccast<cplx<R>>(zb[q * NB + k]), x[k]);
+    }
+    if (!live) return;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int64_t o = (i * NB + q) * s + r;
+        if (MODE == 0) Y[o] = ccast<CY>(acc[q]);
+        if (MODE == 1) Y[o] = ccast<CY>(csub(ccast<cplx<R>>(B[o]), acc[q]));
+        if (MODE == 2) Y[o] = ccast<CY>(cadd(ccast<cplx<R>>(Y[o]), acc[q]));
+    }
+}
+
 static int spmm_tile_width(int64_t s) {
     int st = 1;
     while (st < s && st < 64) st <<= 1;
     return st;
 }
 
-// variant: 0 = rowq, 1 = tile (ST from s), 2 = tile with ST halved (more rows per wave)
+// variant: 0 = rowq, 1 = tile (ST from s), 2 = tile with ST halved (more rows per wave),
+// 3 = tile in XCD-aware order, 4 = XCD-aware with ST halved
 template <typename CZ, typename CX, typename CY, int MODE, bool DIAG>
 static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, const CZ* Z, const CX* X,
                                 const CY* B, CY* Y, int64_t n, int64_t nnzb, int64_t s, int variant,
@@ -124,8 +178,25 @@ static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, 
         return CHAFF_OK;
     }
     int w = spmm_tile_width(s);
-    if (variant == 2 && w > 1) w >>= 1;
+    if ((variant == 2 || variant == 4) && w > 1) w >>= 1;
     const unsigned ty = (unsigned)((s + w - 1) / w);
+    if (!DIAG && (variant == 3 || variant == 4)) {
+        const int64_t row_tiles = (n + (256 / w) - 1) / (256 / w);
+        const int64_t per_xcd = (row_tiles + NXCD - 1) / NXCD;
+        const unsigned nblk = (unsigned)(per_xcd * NXCD * ty);
+#define CHAFF_XCD(W)                                                                                  \
+    case W:                                                                                           \
+        hipLaunchKernelGGL((k_spmm_xcd<CZ, CX, CY, MODE, W>), dim3(nblk), dim3(256), 0, st, row_ptr,  \
+                           col_idx, Z, X, B, Y, n, s, row_tiles, (int)ty);                            \
+        break;
+        switch (w) {
+            CHAFF_XCD(1) CHAFF_XCD(2) CHAFF_XCD(4) CHAFF_XCD(8) CHAFF_XCD(16) CHAFF_XCD(32) CHAFF_XCD(64)
+            default: return fail(CHAFF_EINVAL, "bad tile width");
+        }
+#undef CHAFF_XCD
+        CHAFF_LAUNCH_CHECK();
+        return CHAFF_OK;
+    }
 #define CHAFF_TILE(W)                                                                                    \
     case W: {                                                                                            \
         dim3 grid((unsigned)((n + (256 / W) - 1) / (256 / W)), ty);                                      \
@@ -294,20 +365,44 @@ __global__ __launch_bounds__(RB) void k_norm2(const Chunk* __restrict__ chunks, 
     if (threadIdx.x < st && m.r < s) part[((int64_t)blockIdx.x * nslot + slot) * s + m.r] = v;
 }
 
-// out[slot - slot0][cloud][r] = sum over the cloud's chunks (in order) of part[chunk][slot][r]
-__global__ void k_chunk_sum(const c128* __restrict__ part, const int32_t* __restrict__ cloud_chunk_off,
-                            int n_clouds, int nslot, int slot0, int ns, int64_t s, c128* __restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)ns * n_clouds * s;
-    if (t >= total) return;
-    const int64_t r = t % s;
-    const int c = (int)((t / s) % n_clouds);
-    const int rel = (int)(t / (s * n_clouds));
-    const int slot = slot0 + rel;
+// out[rel][g][r] = sum over k in [off[g], off[g+1]) of in[k*ch_stride + (slot0+rel)*slot_stride + r].
+// One 1024-thread block per (rel, g, 64-column tile): wave w sums k = off[g]+w,
+// +16, ... (coalesced over the columns), then the 16 wave sums are added in
+// wave order.  Fixed order throughout, so the result is reproducible.
+constexpr int CS_WAVES = 16;
+__global__ __launch_bounds__(64 * CS_WAVES) void k_group_sum(const c128* __restrict__ in, int64_t ch_stride,
+                                                             int64_t slot_stride, int slot0,
+                                                             const int32_t* __restrict__ off, int n_groups,
+                                                             int64_t s, c128* __restrict__ out) {
+    __shared__ c128 red[CS_WAVES][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = blockIdx.x % n_groups;
+    const int rel = blockIdx.x / n_groups;
+    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
     c128 acc = {0, 0};
-    for (int ch = cloud_chunk_off[c]; ch < cloud_chunk_off[c + 1]; ++ch)
-        acc = cadd(acc, part[((int64_t)ch * nslot + slot) * s + r]);
-    out[((int64_t)rel * n_clouds + c) * s + r] = acc;
+    if (r < s)
+        for (int64_t k = off[g] + w; k < off[g + 1]; k += CS_WAVES)
+            acc = cadd(acc, in[k * ch_stride + (int64_t)(slot0 + rel) * slot_stride + r]);
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && r < s) {
+        c128 t = red[0][lane];
+        for (int k = 1; k < CS_WAVES; ++k) t = cadd(t, red[k][lane]);
+        out[((int64_t)rel * n_groups + g) * s + r] = t;
+    }
+}
+
+static inline void group_sum(const c128* in, int64_t ch_stride, int64_t slot_stride, int slot0, int ns,
+                             const int32_t* off, int n_groups, int64_t s, c128* out, hipStream_t st) {
+    dim3 grid((unsigned)(ns * n_groups), (unsigned)((s + 63) / 64));
+    hipLaunchKernelGGL(k_group_sum, grid, dim3(64 * CS_WAVES), 0, st, in, ch_stride, slot_stride, slot0, off,
+                       n_groups, s, out);
+}
+
+// out[slot - slot0][cloud][r] = sum over the cloud's chunks of part[chunk][slot][r]
+static inline void chunk_sum(const c128* part, const int32_t* cloud_chunk_off, int n_clouds, int nslot, int slot0,
+                             int ns, int64_t s, c128* out, hipStream_t st) {
+    group_sum(part, (int64_t)nslot * s, s, slot0, ns, cloud_chunk_off, n_clouds, s, out, st);
 }
 
 // ------------------------------------------------------------------ per-system GMRES state (FP64)
@@ -473,7 +568,7 @@ __global__ void k_zero_bytes(uint32_t* __restrict__ a, int64_t nwords) {
 // Z = Z^T exactly (each unique pair is filled once and stored twice, self
 // blocks are symmetric by construction) and the block-Jacobi inverse is
 // complex symmetric too, so the preconditioned conjugate-orthogonal CG
-// recurrence (bilinear form a^T b, no conjugation) applies: five vectors, no
+// recurrence (bilinear form a^T b, no conjugation) applies: six vectors, no
 // restarts, one sparse product per step.
 
 struct CgState {
@@ -487,33 +582,6 @@ struct CgState {
     int32_t done;
     int32_t pad;
 };
-
-// part[chunk][slot0][r] = sum a^T b ; part[chunk][slot0+1][r] = sum |c|^2 (if c)
-template <typename C>
-__global__ __launch_bounds__(RB) void k_dot2(const Chunk* __restrict__ chunks, const C* __restrict__ a,
-                                             const C* __restrict__ b, const C* __restrict__ c, int64_t s, int st,
-                                             c128* __restrict__ part, int nslot, int slot0) {
-    __shared__ c128 red[RB];
-    const Chunk ch = chunks[blockIdx.x];
-    const RowMap m = rowmap(st);
-    c128 acc = {0, 0}, acc2 = {0, 0};
-    if (m.r < s) {
-        for (int64_t row = ch.w0 * NB + m.rsub; row < ch.w1 * NB; row += RB / st) {
-            const int64_t o = row * s + m.r;
-            cfma(acc, ccast<c128>(a[o]), ccast<c128>(b[o]));
-            if (c) {
-                c128 v = ccast<c128>(c[o]);
-                acc2.re += v.re * v.re + v.im * v.im;
-            }
-        }
-    }
-    c128 v = block_col_reduce(acc, st, red);
-    if (threadIdx.x < st && m.r < s) part[((int64_t)blockIdx.x * nslot + slot0) * s + m.r] = v;
-    if (c) {
-        c128 v2 = block_col_reduce(acc2, st, red);
-        if (threadIdx.x < st && m.r < s) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + m.r] = v2;
-    }
-}
 
 // alpha = rho / (p^T q)
 __global__ void k_cg_alpha(int64_t nsys, const c128* __restrict__ pq, CgState* __restrict__ cg) {
@@ -534,47 +602,78 @@ __global__ void k_cg_alpha(int64_t nsys, const c128* __restrict__ pq, CgState* _
     cg[t] = S;
 }
 
-// x += alpha p ; r -= alpha q
+// x64 += scale(system) * xc
 template <typename C>
-__global__ void k_cg_xr(const int32_t* __restrict__ wire_cloud, const CgState* __restrict__ cg, int64_t n_rows,
-                        int64_t s, const C* __restrict__ p, const C* __restrict__ q, C* __restrict__ x,
-                        C* __restrict__ r) {
-    using R = typename real_of<C>::type;
+__global__ void k_add_scaled(const int32_t* __restrict__ wire_cloud, const double* __restrict__ scale, int64_t n_rows,
+                             int64_t s, const C* __restrict__ xc, c128* __restrict__ x) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_rows * s) return;
     const int64_t row = t / s, rr = t - (t / s) * s;
-    const CgState& S = cg[(int64_t)wire_cloud[row / NB] * s + rr];
-    const cplx<R> a = {(R)S.alpha_re, (R)S.alpha_im};
-    cplx<R> xv = x[t], rv = r[t];
-    cfma(xv, a, p[t]);
-    cfma(rv, cplx<R>{-a.re, -a.im}, q[t]);
-    x[t] = xv;
-    r[t] = rv;
+    const double f = scale[(int64_t)wire_cloud[row / NB] * s + rr];
+    const c128 v = ccast<c128>(xc[t]);
+    x[t] = c128{x[t].re + f * v.re, x[t].im + f * v.im};
 }
 
-// beta = rho_new / rho, convergence flags (rz = r^T z, rr = ||r||^2)
-__global__ void k_cg_beta(int64_t nsys, const c128* __restrict__ rz, const c128* __restrict__ rr,
-                          CgState* __restrict__ cg, int32_t* __restrict__ n_active) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nsys) return;
-    CgState S = cg[t];
-    const double rn = sqrt(fmax(rr[t].re, 0.0));
-    if (!S.done) S.rnorm = rn;
-    const c128 rho_old = {S.rho, S.rho_im};
-    const c128 rho_new = rz[t];
-    const double d = rho_old.re * rho_old.re + rho_old.im * rho_old.im;
-    if (S.done || rn <= S.target || !(d > 0.0) || !isfinite(rn)) {
-        S.done = 1;
-        S.beta_re = S.beta_im = 0.0;
-    } else {
-        const c128 b = cmul(rho_new, c128{rho_old.re / d, -rho_old.im / d});
-        S.beta_re = b.re;
-        S.beta_im = b.im;
-        S.rho = rho_new.re;
-        S.rho_im = rho_new.im;
+// Fused COCG kernels (chunk-structured so that the bilinear forms reduce per
+// cloud in a fixed order).  Thread (rsub, r): RHS column r of wire rows
+// i = w0 + rsub, w0 + rsub + 256/ST, ... of the block's chunk.
+//
+// COCG product q = Z p over small cloud-aligned tiles (256/ST wires, one
+// block row per thread row) in XCD-aware order: XCD x walks tiles
+// [x*T/8, (x+1)*T/8) in Morton order, so the neighbour slabs a row gathers
+// stay in that XCD's L2 while its neighbours are processed.  sigma = p^T q is
+// reduced per tile in FP64 (tpart[tile][r]); two fixed-order passes then sum
+// tiles per group and groups per cloud.
+template <typename CZ, typename C, int ST>
+__global__ __launch_bounds__(RB) void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles,
+                                                  const int64_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col_idx, const CZ* __restrict__ Z,
+                                                  const C* __restrict__ P, C* __restrict__ Q, int64_t s,
+                                                  c128* __restrict__ tpart) {
+    using R = typename real_of<C>::type;
+    __shared__ c128 red[RB];
+    const int64_t id = blockIdx.x;
+    const int xcd = (int)(id % NXCD);
+    const int64_t local = id / NXCD;
+    const int64_t per_xcd = (n_tiles + NXCD - 1) / NXCD;
+    const int64_t t = (int64_t)xcd * per_xcd + local / col_tiles;
+    const int ctile = (int)(local % col_tiles);
+    if (t >= n_tiles) return;   // uniform over the block
+    const Chunk tl = tiles[t];
+    const int sub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
+    const int64_t i = tl.w0 + sub;
+    const int64_t r = (int64_t)ctile * ST + threadIdx.x % ST;
+    const bool live = r < s && i < tl.w1;
+    const int64_t rc = r < s ? r : 0;
+    c128 dot = {0, 0};
+    if (i < tl.w1) {
+        cplx<R> acc[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
+        const int64_t e1 = row_ptr[i + 1];
+        for (int64_t e = row_ptr[i]; e < e1; ++e) {
+            const int64_t col = col_idx[e];
+            const CZ* zb = Z + e * NB2;
+            const C* xb = P + col * NB * s + rc;
+            cplx<R> x[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) x[k] = xb[k * s];
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int k = 0; k < NB; ++k) cfma(acc[q], ccast<cplx<R>>(zb[q * NB + k]), x[k]);
+        }
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int64_t o = (i * NB + q) * s + r;
+                Q[o] = acc[q];
+                cfma(dot, ccast<c128>(P[o]), ccast<c128>(acc[q]));
+            }
+        }
     }
-    cg[t] = S;
-    if (!S.done) atomicAdd(n_active, 1);
+    c128 v = block_col_reduce(dot, ST, red);
+    if (threadIdx.x < ST && r < s) tpart[t * s + r] = v;
 }
 
 // p = z + beta p
@@ -591,63 +690,6 @@ __global__ void k_cg_p(const int32_t* __restrict__ wire_cloud, const CgState* __
     p[t] = pv;
 }
 
-// x64 += scale(system) * xc
-template <typename C>
-__global__ void k_add_scaled(const int32_t* __restrict__ wire_cloud, const double* __restrict__ scale, int64_t n_rows,
-                             int64_t s, const C* __restrict__ xc, c128* __restrict__ x) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_rows * s) return;
-    const int64_t row = t / s, rr = t - (t / s) * s;
-    const double f = scale[(int64_t)wire_cloud[row / NB] * s + rr];
-    const c128 v = ccast<c128>(xc[t]);
-    x[t] = c128{x[t].re + f * v.re, x[t].im + f * v.im};
-}
-
-// Fused COCG kernels (chunk-structured so that the bilinear forms reduce per
-// cloud in a fixed order).  Thread (rsub, r): RHS column r of wire rows
-// i = w0 + rsub, w0 + rsub + 256/ST, ... of the block's chunk.
-
-// q = Z p for the chunk's block rows, with sigma = p^T q accumulated in FP64
-template <typename CZ, typename C, int ST>
-__global__ __launch_bounds__(RB) void k_spmm_dot(const Chunk* __restrict__ chunks, const int64_t* __restrict__ row_ptr,
-                                                 const int32_t* __restrict__ col_idx, const CZ* __restrict__ Z,
-                                                 const C* __restrict__ P, C* __restrict__ Q, int64_t s,
-                                                 c128* __restrict__ part, int nslot, int slot) {
-    using R = typename real_of<C>::type;
-    __shared__ c128 red[RB];
-    const Chunk ch = chunks[blockIdx.x];
-    const int rsub = threadIdx.x / ST;
-    const int64_t r = (int64_t)blockIdx.y * ST + threadIdx.x % ST;
-    c128 dot = {0, 0};
-    if (r < s) {
-        for (int64_t i = ch.w0 + rsub; i < ch.w1; i += RB / ST) {
-            cplx<R> acc[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
-            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-                const int64_t col = col_idx[e];
-                const CZ* zb = Z + e * NB2;
-                const C* xb = P + col * NB * s + r;
-                cplx<R> x[NB];
-#pragma unroll
-                for (int k = 0; k < NB; ++k) x[k] = xb[k * s];
-#pragma unroll
-                for (int q = 0; q < NB; ++q)
-#pragma unroll
-                    for (int k = 0; k < NB; ++k) cfma(acc[q], ccast<cplx<R>>(zb[q * NB + k]), x[k]);
-            }
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const int64_t o = (i * NB + q) * s + r;
-                Q[o] = acc[q];
-                cfma(dot, ccast<c128>(P[o]), ccast<c128>(acc[q]));
-            }
-        }
-    }
-    c128 v = block_col_reduce(dot, ST, red);
-    if (threadIdx.x < ST && r < s) part[((int64_t)blockIdx.x * nslot + slot) * s + r] = v;
-}
-
 // x += alpha p ; r -= alpha q ; z = P_i r ; partial r^T z and ||r||^2
 template <typename CZ, typename C, int ST>
 __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
@@ -658,7 +700,7 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
     using R = typename real_of<C>::type;
     __shared__ c128 red[RB];
     const Chunk ch = chunks[blockIdx.x];
-    const int rsub = threadIdx.x / ST;
+    const int rsub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
     const int64_t r = (int64_t)blockIdx.y * ST + threadIdx.x % ST;
     c128 rz = {0, 0}, rr = {0, 0};
     if (r < s) {
@@ -666,16 +708,22 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
         const cplx<R> a = {(R)S.alpha_re, (R)S.alpha_im};
         const cplx<R> na = {-a.re, -a.im};
         for (int64_t i = ch.w0 + rsub; i < ch.w1; i += RB / ST) {
-            cplx<R> res[NB];
+            cplx<R> res[NB], xv[NB], pv[NB], qv[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {   // issue all 28 loads before any arithmetic
+                const int64_t o = (i * NB + k) * s + r;
+                xv[k] = x[o];
+                pv[k] = p[o];
+                res[k] = rv[o];
+                qv[k] = q[o];
+            }
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 const int64_t o = (i * NB + k) * s + r;
-                cplx<R> xv = x[o], pv = p[o], rk = rv[o], qv = q[o];
-                cfma(xv, a, pv);
-                cfma(rk, na, qv);
-                x[o] = xv;
-                rv[o] = rk;
-                res[k] = rk;
+                cfma(xv[k], a, pv[k]);
+                cfma(res[k], na, qv[k]);
+                x[o] = xv[k];
+                rv[o] = res[k];
             }
             const CZ* pb = Pinv + i * NB2;
 #pragma unroll
@@ -743,20 +791,6 @@ __global__ void k_cg_cycle_start(int64_t nsys, const double* __restrict__ target
     cg[t] = S;
 }
 
-// rho = r^T z at the start of a cycle
-__global__ void k_cg_init(int64_t nsys, const c128* __restrict__ rz, const int32_t* __restrict__ active,
-                          const double* __restrict__ target, CgState* __restrict__ cg) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nsys) return;
-    CgState S{};
-    S.rho = rz[t].re;
-    S.rho_im = rz[t].im;
-    S.rnorm = 1.0;
-    S.target = target[t];
-    S.done = active[t] ? 0 : 1;
-    cg[t] = S;
-}
-
 // ------------------------------------------------------------------ host driver
 
 // CHAFF_VERBOSE=1 in the environment prints one line per refinement cycle
@@ -786,12 +820,24 @@ struct SolveLayout {
     Chunk* chunks;
     int32_t* cloud_chunk_off;
     int32_t* counter;
+    Chunk* tiles;              // COCG product tiles
+    int32_t* group_tile_off;   // [n_groups+1] tile ranges of the groups
+    int32_t* cloud_group_off;  // [n_clouds+1] group ranges of the clouds
+    c128* tpart;               // [n_tiles][s]
+    c128* gpart;               // [n_groups][s]
 };
+
+// Wires per reduction chunk (about 2048 chunks in total): streaming kernels
+// reduce per chunk; COCG's product uses its own small tiles (see k_cocg_spmm).
+static int64_t chunk_wires(int64_t n, int /*method*/) { return std::max<int64_t>(32, (n + 2047) / 2048); }
+constexpr int TILE_GROUP = 256;   // tiles per first-stage group of the sigma reduction
 
 struct SolveShape {
     int64_t n, rows, s, nsys;
     int m, nslot, n_chunks, n_clouds;
     int method, nvec, mg;   // mg: Hessenberg width (GMRES m, COCG 1)
+    int64_t n_tiles;        // COCG product tiles (cloud-aligned, tile_w wires)
+    int n_groups, tile_w;   // tile groups (cloud-aligned, TILE_GROUP tiles)
     size_t csize;
 };
 
@@ -807,13 +853,24 @@ static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec,
     sh.nsys = (int64_t)c->n_clouds * s;
     sh.m = m;
     sh.nslot = sh.mg + 3;
-    const int64_t cw = std::max<int64_t>(32, (c->n + 2047) / 2048);
+    const int64_t cw = chunk_wires(c->n, method);
     int64_t nch = 0;
     for (int k = 0; k < c->n_clouds; ++k) {
         int64_t nw = c->cloud_off[k + 1] - c->cloud_off[k];
         nch += (nw + cw - 1) / cw;
     }
     sh.n_chunks = (int)nch;
+    sh.n_tiles = 0;
+    sh.n_groups = 0;
+    sh.tile_w = 256 / spmm_tile_width(s);
+    if (method != CHAFF_GMRES) {
+        for (int k = 0; k < c->n_clouds; ++k) {
+            const int64_t nw = c->cloud_off[k + 1] - c->cloud_off[k];
+            const int64_t nt = (nw + sh.tile_w - 1) / sh.tile_w;
+            sh.n_tiles += nt;
+            sh.n_groups += (int)((nt + TILE_GROUP - 1) / TILE_GROUP);
+        }
+    }
     sh.csize = prec == CHAFF_C64 ? sizeof(c64) : sizeof(c128);
     return sh;
 }
@@ -849,6 +906,11 @@ static SolveLayout carve_solve(void* ws, size_t ws_bytes, const SolveShape& sh) 
     L.chunks = cv.take<Chunk>((size_t)std::max(sh.n_chunks, 1));
     L.cloud_chunk_off = cv.take<int32_t>((size_t)sh.n_clouds + 1);
     L.counter = cv.take<int32_t>(64);
+    L.tiles = cv.take<Chunk>((size_t)std::max<int64_t>(sh.n_tiles, 1));
+    L.group_tile_off = cv.take<int32_t>((size_t)sh.n_groups + 1);
+    L.cloud_group_off = cv.take<int32_t>((size_t)sh.n_clouds + 1);
+    L.tpart = cv.take<c128>((size_t)std::max<int64_t>(sh.n_tiles, 1) * sh.s);
+    L.gpart = cv.take<c128>((size_t)std::max(sh.n_groups, 1) * sh.s);
     L.bytes = cv.off + 256;
     return L;
 }
@@ -869,27 +931,28 @@ static chaff_status norms_to(const SolveShape& sh, SolveLayout& L, const C* v, c
                            sh.nslot, 0);
         CHAFF_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for(sh.nsys)), dim3(256), 0, st, (const c128*)L.part,
-                       (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, 1, sh.s, dst);
+    chunk_sum((const c128*)L.part,
+                       (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, 1, sh.s, dst, st);
     CHAFF_LAUNCH_CHECK();
     return CHAFF_OK;
 }
 
 
 template <typename CZ, typename C, int ST>
-static void launch_cg_update(const SolveShape& sh, SolveLayout& L, const CZ* Pinv, C* V, int64_t vs, hipStream_t st) {
+static void launch_cg_update(const SolveShape& sh, SolveLayout& L, const CZ* Pinv, C* V, const C* p, int64_t vs,
+                             hipStream_t st) {
     const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
     hipLaunchKernelGGL((k_cg_update<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const CgState*)L.cg,
-                       Pinv, (const C*)(V + 3 * vs), (const C*)(V + 4 * vs), V, V + vs, V + 2 * vs, sh.s, L.part,
-                       sh.nslot, 0);
+                       Pinv, p, (const C*)(V + 4 * vs), V, V + vs, V + 2 * vs, sh.s, L.part, sh.nslot, 0);
 }
 template <typename CZ, typename C, int ST>
-static void launch_spmm_dot(const Cloud* c, const SolveShape& sh, SolveLayout& L, const CZ* Z, C* V, int64_t vs,
-                            hipStream_t st) {
-    const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
-    hipLaunchKernelGGL((k_spmm_dot<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks,
-                       (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, Z, (const C*)(V + 3 * vs), V + 4 * vs,
-                       sh.s, L.part, sh.nslot, 2);
+static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& L, const CZ* Z, const C* p, C* q,
+                             hipStream_t st) {
+    const int ct = (int)((sh.s + ST - 1) / ST);
+    const int64_t per_xcd = (sh.n_tiles + NXCD - 1) / NXCD;
+    hipLaunchKernelGGL((k_cocg_spmm<CZ, C, ST>), dim3((unsigned)(per_xcd * NXCD * ct)), dim3(RB), 0, st,
+                       (const Chunk*)L.tiles, sh.n_tiles, ct, (const int64_t*)c->row_ptr,
+                       (const int32_t*)c->col_idx, Z, p, q, sh.s, L.tpart);
 }
 
 // One COCG refinement cycle.  L.r holds the FP64 true residual; it replaces the
@@ -907,7 +970,9 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     C* V = static_cast<C*>(L.V);   // [x_c | r | z | p | q]
     C* xc = V;
     C* r = V + vs;
+    C* z = V + 2 * vs;
     C* p = V + 3 * vs;
+    C* q = V + 4 * vs;
     const int wst = spmm_tile_width(s);
     const bool use_rr = o->method == CHAFF_COCG_RR;
     CHAFF_HIP(hipMemcpyAsync(L.target, target.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
@@ -931,19 +996,20 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     for (int k = 0; k <= o->restart; ++k) {
         {   // x += alpha p, r -= alpha q, z = P r, r^T z, ||r||^2 (alpha = 0 on entry)
             ProfScope pu("k_cg_update", st, (7.0 * vs + 0.0) * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
+            const C* pc = p;
             switch (wst) {
-                case 1: launch_cg_update<CZ, C, 1>(sh, L, Pinv, V, vs, st); break;
-                case 2: launch_cg_update<CZ, C, 2>(sh, L, Pinv, V, vs, st); break;
-                case 4: launch_cg_update<CZ, C, 4>(sh, L, Pinv, V, vs, st); break;
-                case 8: launch_cg_update<CZ, C, 8>(sh, L, Pinv, V, vs, st); break;
-                case 16: launch_cg_update<CZ, C, 16>(sh, L, Pinv, V, vs, st); break;
-                case 32: launch_cg_update<CZ, C, 32>(sh, L, Pinv, V, vs, st); break;
-                default: launch_cg_update<CZ, C, 64>(sh, L, Pinv, V, vs, st); break;
+                case 1: launch_cg_update<CZ, C, 1>(sh, L, Pinv, V, pc, vs, st); break;
+                case 2: launch_cg_update<CZ, C, 2>(sh, L, Pinv, V, pc, vs, st); break;
+                case 4: launch_cg_update<CZ, C, 4>(sh, L, Pinv, V, pc, vs, st); break;
+                case 8: launch_cg_update<CZ, C, 8>(sh, L, Pinv, V, pc, vs, st); break;
+                case 16: launch_cg_update<CZ, C, 16>(sh, L, Pinv, V, pc, vs, st); break;
+                case 32: launch_cg_update<CZ, C, 32>(sh, L, Pinv, V, pc, vs, st); break;
+                default: launch_cg_update<CZ, C, 64>(sh, L, Pinv, V, pc, vs, st); break;
             }
         }
         CHAFF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for(2 * nsys)), dim3(256), 0, st, (const c128*)L.part,
-                           (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, 2, s, L.h1);
+        chunk_sum((const c128*)L.part,
+                           (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, 2, s, L.h1, st);
         CHAFF_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)L.counter, (int64_t)1);
         CHAFF_LAUNCH_CHECK();
@@ -959,25 +1025,27 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         {
             ProfScope pp("k_cg_p", st, 3.0 * vs * sizeof(C));
             hipLaunchKernelGGL((k_cg_p<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const int32_t*)c->wire_cloud,
-                               (const CgState*)L.cg, rows, s, (const C*)(V + 2 * vs), p);
+                               (const CgState*)L.cg, rows, s, (const C*)z, p);
         }
         CHAFF_LAUNCH_CHECK();
-        {   // q = Z p and p^T q
+        {   // q = Z p with per-tile p^T q
             ProfScope ps("spmm", st, ((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 8.0 * (c->n + 1) +
                                          3.0 * vs * sizeof(C));
             switch (wst) {
-                case 1: launch_spmm_dot<CZ, C, 1>(c, sh, L, Z, V, vs, st); break;
-                case 2: launch_spmm_dot<CZ, C, 2>(c, sh, L, Z, V, vs, st); break;
-                case 4: launch_spmm_dot<CZ, C, 4>(c, sh, L, Z, V, vs, st); break;
-                case 8: launch_spmm_dot<CZ, C, 8>(c, sh, L, Z, V, vs, st); break;
-                case 16: launch_spmm_dot<CZ, C, 16>(c, sh, L, Z, V, vs, st); break;
-                case 32: launch_spmm_dot<CZ, C, 32>(c, sh, L, Z, V, vs, st); break;
-                default: launch_spmm_dot<CZ, C, 64>(c, sh, L, Z, V, vs, st); break;
+                case 1: launch_cocg_spmm<CZ, C, 1>(c, sh, L, Z, p, q, st); break;
+                case 2: launch_cocg_spmm<CZ, C, 2>(c, sh, L, Z, p, q, st); break;
+                case 4: launch_cocg_spmm<CZ, C, 4>(c, sh, L, Z, p, q, st); break;
+                case 8: launch_cocg_spmm<CZ, C, 8>(c, sh, L, Z, p, q, st); break;
+                case 16: launch_cocg_spmm<CZ, C, 16>(c, sh, L, Z, p, q, st); break;
+                case 32: launch_cocg_spmm<CZ, C, 32>(c, sh, L, Z, p, q, st); break;
+                default: launch_cocg_spmm<CZ, C, 64>(c, sh, L, Z, p, q, st); break;
             }
         }
         CHAFF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for(nsys)), dim3(256), 0, st, (const c128*)L.part,
-                           (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 2, 1, s, L.nrm);
+        // sigma: tiles -> groups -> clouds, fixed order
+        group_sum(L.tpart, s, 0, 0, 1, L.group_tile_off, sh.n_groups, s, L.gpart, st);
+        CHAFF_LAUNCH_CHECK();
+        group_sum(L.gpart, s, 0, 0, 1, L.cloud_group_off, sh.n_clouds, s, L.nrm, st);
         CHAFF_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_cg_alpha, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const c128*)L.nrm, L.cg);
         CHAFF_LAUNCH_CHECK();
@@ -1007,7 +1075,7 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
 
     // --- chunk tables (host -> device)
     {
-        const int64_t cw = std::max<int64_t>(32, (c->n + 2047) / 2048);
+        const int64_t cw = chunk_wires(c->n, o->method);
         std::vector<Chunk> ch;
         std::vector<int32_t> off(sh.n_clouds + 1, 0);
         for (int k = 0; k < sh.n_clouds; ++k) {
@@ -1020,6 +1088,26 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
             CHAFF_HIP(hipMemcpyAsync(L.chunks, ch.data(), ch.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
         CHAFF_HIP(hipMemcpyAsync(L.cloud_chunk_off, off.data(), off.size() * sizeof(int32_t),
                                  hipMemcpyHostToDevice, st));
+        // COCG product tiles (cloud-aligned) and their groups (cloud-aligned)
+        std::vector<Chunk> tl;
+        std::vector<int32_t> gto, cgo(sh.n_clouds + 1, 0);
+        if (sh.method != CHAFF_GMRES) {
+            for (int k = 0; k < sh.n_clouds; ++k) {
+                cgo[k] = (int32_t)gto.size();
+                const int64_t t0 = (int64_t)tl.size();
+                for (int64_t w0 = c->cloud_off[k]; w0 < c->cloud_off[k + 1]; w0 += sh.tile_w)
+                    tl.push_back(Chunk{w0, std::min<int64_t>(w0 + sh.tile_w, c->cloud_off[k + 1]), k, 0});
+                for (int64_t g = t0; g < (int64_t)tl.size(); g += TILE_GROUP) gto.push_back((int32_t)g);
+            }
+            cgo[sh.n_clouds] = (int32_t)gto.size();
+            gto.push_back((int32_t)tl.size());
+            if (!tl.empty())
+                CHAFF_HIP(hipMemcpyAsync(L.tiles, tl.data(), tl.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
+            CHAFF_HIP(hipMemcpyAsync(L.group_tile_off, gto.data(), gto.size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice, st));
+            CHAFF_HIP(hipMemcpyAsync(L.cloud_group_off, cgo.data(), cgo.size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice, st));
+        }
         CHAFF_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
     }
 
@@ -1144,9 +1232,8 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
                                    std::min(GV, nv - i0), (const C*)W, s, wst, L.part, sh.nslot);
                 CHAFF_LAUNCH_CHECK();
             }
-            hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for((int64_t)nv * nsys)), dim3(256), 0, st,
-                               (const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, nv,
-                               s, L.h1);
+            chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, nv,
+                               s, L.h1, st);
             CHAFF_LAUNCH_CHECK();
             {
                 ProfScope p2("k_update", st, (double)(nv + 2) * vs * sizeof(C));
@@ -1161,9 +1248,8 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
                                    std::min(GV, nv - i0), (const C*)W, s, wst, L.part, sh.nslot);
                 CHAFF_LAUNCH_CHECK();
             }
-            hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for((int64_t)nv * nsys)), dim3(256), 0, st,
-                               (const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, nv,
-                               s, L.h2);
+            chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, nv,
+                               s, L.h2, st);
             CHAFF_LAUNCH_CHECK();
             {
                 ProfScope p3("k_update_norm", st, (double)(nv + 2) * vs * sizeof(C));
@@ -1172,8 +1258,8 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
                                    sh.nslot - 1);
             }
             CHAFF_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_chunk_sum, dim3(blocks_for(nsys)), dim3(256), 0, st, (const c128*)L.part,
-                               (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, sh.nslot - 1, 1, s, L.nrm);
+            chunk_sum((const c128*)L.part,
+                               (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, sh.nslot - 1, 1, s, L.nrm, st);
             CHAFF_LAUNCH_CHECK();
             }
             hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)L.counter, (int64_t)1);
