@@ -166,6 +166,7 @@ def main(argv=None) -> int:
     ap.add_argument("--method", default=None, choices=sorted(METHODS))
     ap.add_argument("--inner-tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (scale for HBM byte counters)")
@@ -210,12 +211,20 @@ def main(argv=None) -> int:
         Z, P = B.fill_Z(cl, prec)
         X, info = B.solve(cl, Z, P, kh, eh, opts)
         sig = B.rcs(cl, X, -kh, eh, monostatic=True)
-        return cl, X, info, sig
+        return cl, X, info, sig, Z
 
     print(f"[bench] config={a.config} N={wl.cloud.n} clouds={wl.cloud.n_clouds} R={R} warmup={a.warmup} "
           f"steps={a.steps}", file=sys.stderr, flush=True)
+    tuning = None
+    if not a.no_autotune:   # pick the product variant for this cloud and RHS count (outside the timed steps)
+        cl0 = B.build_cloud(geom)
+        Z0, _ = B.fill_Z(cl0, prec, with_pinv=False)
+        best, best_ms = B.autotune(cl0, Z0, R, prec)
+        tuning = {"best_variant": best, "best_ms": best_ms, "table": B.tune_report()}
+        del Z0, cl0
+        print(f"[bench] autotune: variant {best} ({best_ms:.3f} ms)", file=sys.stderr, flush=True)
     for w in range(a.warmup):
-        _, _, info, _ = step()
+        _, _, info, _, _ = step()
         print(f"[bench] warmup {w}: cycles={info['cycles']} iters={info['iterations']} "
               f"res={info['max_rel_residual']:.2e} solve={info['seconds']:.3f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -224,7 +233,7 @@ def main(argv=None) -> int:
     solved = 0
     infos = []
     for k in range(a.steps):
-        cl, X, info, sig = step()
+        cl, X, info, sig, _ = step()
         infos.append(info)
         solved += int((info["rel_res"] <= a.tol).sum())
     torch.cuda.synchronize()
@@ -281,6 +290,7 @@ def main(argv=None) -> int:
                    "max_rel_residual": infos[-1]["max_rel_residual"],
                    "systems_per_step": int(wl.cloud.n_clouds * R), "solved_total": solved},
         "roofline": roof,
+        "autotune": tuning,
         "kernels": kernels,
         "cpu_baseline": None,
     }

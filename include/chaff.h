@@ -149,7 +149,7 @@ typedef struct {
     int32_t max_cycles;       /* restart/refinement cycles (50) */
     int32_t use_x0;           /* 1: X holds an initial guess on entry */
     int32_t prec;             /* chaff_prec of Z, Pinv and the Krylov vectors */
-    int32_t spmm_variant;     /* -1: autotuned/heuristic choice; else a fixed kernel variant */
+    int32_t spmm_variant;     /* -1: tuned (chaff_autotune) or default choice; else variant 0..4 */
     int32_t method;           /* chaff_method */
 } chaff_solve_opts;
 
@@ -192,6 +192,22 @@ chaff_status chaff_excitation(chaff_cloud c, const double* k_hat, const double* 
  *   variant -1 = the tuned/heuristic choice. */
 chaff_status chaff_spmm(chaff_cloud c, chaff_prec prec, const void* Z, const void* X,
                         void* Y, int64_t s, int32_t variant, chaff_stream stream);
+
+/* ------------------------------------------------------------------ autotuning
+ * chaff_autotune times every block-sparse product variant (0: one output row
+ * per lane; 1: RHS tile per wave; 2: half-width tile; 3: tile in XCD-aware
+ * workgroup order; 4: XCD-aware half-width tile) for this cloud, precision
+ * and RHS count on the caller's Z and two [N*7][s] buffers (contents of Y are
+ * overwritten, X is read), and records the fastest in a process-wide table
+ * keyed by (N, nnzb, s, prec).  Every later call with variant -1 (chaff_spmm,
+ * and the products inside chaff_solve, including the COCG product's tile
+ * width and workgroup order) uses the recorded choice.
+ *   best_variant, best_ms [host out, optional].  Synchronises `stream`.
+ * chaff_tune_report writes the table as JSON text into buf [host] (at most len
+ * bytes, NUL-terminated) and returns the length needed including the NUL. */
+chaff_status chaff_autotune(chaff_cloud c, chaff_prec prec, const void* Z, void* X, void* Y, int64_t s,
+                            int32_t* best_variant, double* best_ms, chaff_stream stream);
+int32_t chaff_tune_report(char* buf, int32_t len);
 
 /* ------------------------------------------------------------------ rcs
  * Far field of the currents X (caller order, complex double [N*7][R]):

@@ -84,6 +84,9 @@ EXPORTS = {
     "chaff_rcs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                             C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "chaff_destroy": (None, [C.c_void_p]),
+    "chaff_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_void_p]),
+    "chaff_tune_report": (C.c_int32, [C.c_char_p, C.c_int32]),
     "chaff_profile_enable": (C.c_int, [C.c_int32]),
     "chaff_profile_read": (C.c_int32, [C.c_void_p, C.c_int32]),
     "chaff_last_error": (C.c_char_p, []),
@@ -343,6 +346,26 @@ def rcs(cl: Cloud, X, obs_dir, obs_pol, monostatic: bool):
     _check(lib().chaff_rcs(cl.handle, _ptr(X), R, _ptr(d), _ptr(p), M, int(monostatic), _ptr(sig),
                            _ptr(ws), need, _stream()))
     return sig
+
+
+def autotune(cl: Cloud, Z, s: int, prec: int = C64):
+    """Time every product variant for this cloud and RHS count; later variant -1 calls use the best."""
+    dt = torch.complex64 if prec == C64 else torch.complex128
+    X = torch.ones((cl.n * NB, s), dtype=dt, device=cl.device)
+    Y = torch.empty_like(X)
+    best = C.c_int32(-1)
+    ms = C.c_double(0.0)
+    _check(lib().chaff_autotune(cl.handle, prec, _ptr(Z), _ptr(X), _ptr(Y), s, C.byref(best), C.byref(ms),
+                                _stream()))
+    return int(best.value), float(ms.value)
+
+
+def tune_report() -> list:
+    import json
+    n = lib().chaff_tune_report(None, 0)
+    buf = C.create_string_buffer(n)
+    lib().chaff_tune_report(buf, n)
+    return json.loads(buf.value.decode())
 
 
 def destroy(cl: Cloud):

@@ -76,6 +76,9 @@ chaff_status spmm_public(Cloud* c, chaff_prec prec, const void* Z, const void* X
 size_t rcs_workspace_bytes(const Cloud* c, int64_t R, int64_t M, int32_t mono);
 chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const double* pol, int64_t M, int32_t mono,
                  double* sigma, void* ws, size_t ws_bytes, hipStream_t st);
+chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y, int64_t s, int32_t* best,
+                      double* best_ms, hipStream_t st);
+int32_t tune_report(char* buf, int32_t len);
 
 }  // namespace chaff
 
@@ -252,6 +255,18 @@ chaff_status chaff_rcs(chaff_cloud h, const void* X, int64_t n_rhs, const double
     return rcs(&h->c, X, n_rhs, obs_dir, obs_pol, n_dirs, monostatic, sigma, ws, ws_bytes, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
+
+chaff_status chaff_autotune(chaff_cloud h, chaff_prec prec, const void* Z, void* X, void* Y, int64_t s,
+                            int32_t* best_variant, double* best_ms, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !Z || !X || !Y) return fail(CHAFF_EINVAL, "NULL argument");
+    if (s < 1 || s > 65535) return fail(CHAFF_EINVAL, "s must be in [1, 65535]");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "bad prec");
+    return autotune(&h->c, prec, Z, X, Y, s, best_variant, best_ms, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+int32_t chaff_tune_report(char* buf, int32_t len) { return tune_report(buf, len); }
 
 void chaff_destroy(chaff_cloud h) { delete h; }
 

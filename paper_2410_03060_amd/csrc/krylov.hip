@@ -13,6 +13,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 
@@ -151,6 +153,38 @@ __global__ __launch_bounds__(256) void k_spmm_xcd(const int64_t* __restrict__ ro
     }
 }
 
+// ------------------------------------------------------------------ autotuning table
+// Process-wide record of the fastest block-sparse product variant per
+// (wires, stored blocks, RHS count, precision), filled by chaff_autotune and
+// consulted whenever a caller passes variant -1.
+struct TuneEntry {
+    int64_t n, nnzb, s;
+    int prec;
+    int best;
+    double ms[5];
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+
+static int tuned_variant(int64_t n, int64_t nnzb, int64_t s, int prec) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const TuneEntry& e : g_tune)
+        if (e.n == n && e.nnzb == nnzb && e.s == s && e.prec == prec) return e.best;
+    return -1;
+}
+static void record_tuning(const TuneEntry& t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (TuneEntry& e : g_tune)
+        if (e.n == t.n && e.nnzb == t.nnzb && e.s == t.s && e.prec == t.prec) {
+            e = t;
+            return;
+        }
+    g_tune.push_back(t);
+}
+// default when nothing was tuned: one row per lane for a single RHS, else the
+// XCD-aware tile order
+static int default_variant(int64_t s) { return s == 1 ? 0 : 3; }
+
 static int spmm_tile_width(int64_t s) {
     int st = 1;
     while (st < s && st < 64) st <<= 1;
@@ -169,7 +203,12 @@ static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, 
                            : ((double)sizeof(CZ) * NB2 + 4.0) * (double)nnzb + 8.0 * (n + 1);
     const double vb = 7.0 * n * s * ((double)sizeof(CX) + sizeof(CY) + (MODE == 0 ? 0.0 : (double)sizeof(CY)));
     ProfScope ps(tag, st, zb + vb, false);
-    if (variant < 0) variant = (s == 1) ? 0 : 1;
+    if (variant < 0) {
+        const int t = (!DIAG && MODE == 0 && std::is_same<CZ, CX>::value && std::is_same<CX, CY>::value)
+                          ? tuned_variant(n, nnzb, s, std::is_same<CZ, c64>::value ? CHAFF_C64 : CHAFF_C128)
+                          : -1;
+        variant = t >= 0 ? t : (DIAG ? (s == 1 ? 0 : 1) : default_variant(s));
+    }
     if (variant == 0) {
         dim3 grid((unsigned)((n * NB + 255) / 256), (unsigned)s);
         hipLaunchKernelGGL((k_spmm_rowq<CZ, CX, CY, MODE, DIAG>), grid, dim3(256), 0, st, row_ptr, col_idx,
@@ -626,6 +665,7 @@ __global__ void k_add_scaled(const int32_t* __restrict__ wire_cloud, const doubl
 // tiles per group and groups per cloud.
 template <typename CZ, typename C, int ST>
 __global__ __launch_bounds__(RB) void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles,
+                                                  int xcd_order,
                                                   const int64_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col_idx, const CZ* __restrict__ Z,
                                                   const C* __restrict__ P, C* __restrict__ Q, int64_t s,
@@ -633,11 +673,18 @@ __global__ __launch_bounds__(RB) void k_cocg_spmm(const Chunk* __restrict__ tile
     using R = typename real_of<C>::type;
     __shared__ c128 red[RB];
     const int64_t id = blockIdx.x;
-    const int xcd = (int)(id % NXCD);
-    const int64_t local = id / NXCD;
-    const int64_t per_xcd = (n_tiles + NXCD - 1) / NXCD;
-    const int64_t t = (int64_t)xcd * per_xcd + local / col_tiles;
-    const int ctile = (int)(local % col_tiles);
+    int64_t t, ctile_l;
+    if (xcd_order) {
+        const int xcd = (int)(id % NXCD);
+        const int64_t local = id / NXCD;
+        const int64_t per_xcd = (n_tiles + NXCD - 1) / NXCD;
+        t = (int64_t)xcd * per_xcd + local / col_tiles;
+        ctile_l = local % col_tiles;
+    } else {
+        t = id / col_tiles;
+        ctile_l = id % col_tiles;
+    }
+    const int ctile = (int)ctile_l;
     if (t >= n_tiles) return;   // uniform over the block
     const Chunk tl = tiles[t];
     const int sub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
@@ -837,6 +884,7 @@ struct SolveShape {
     int m, nslot, n_chunks, n_clouds;
     int method, nvec, mg;   // mg: Hessenberg width (GMRES m, COCG 1)
     int64_t n_tiles;        // COCG product tiles (cloud-aligned, tile_w wires)
+    int cocg_st, cocg_xcd;  // COCG product: RHS tile width, XCD-aware order
     int n_groups, tile_w;   // tile groups (cloud-aligned, TILE_GROUP tiles)
     size_t csize;
 };
@@ -862,7 +910,15 @@ static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec,
     sh.n_chunks = (int)nch;
     sh.n_tiles = 0;
     sh.n_groups = 0;
-    sh.tile_w = 256 / spmm_tile_width(s);
+    sh.cocg_st = spmm_tile_width(s);
+    sh.cocg_xcd = 1;
+    {   // the COCG product follows the tuned public variant: 1/3 full tile width, 2/4 half; 1/2 linear order
+        int v = tuned_variant(c->n, c->nnzb, s, prec);
+        if (v < 0) v = default_variant(s);
+        if ((v == 2 || v == 4) && sh.cocg_st > 1) sh.cocg_st >>= 1;
+        sh.cocg_xcd = (v == 1 || v == 2) ? 0 : 1;
+    }
+    sh.tile_w = 256 / sh.cocg_st;
     if (method != CHAFF_GMRES) {
         for (int k = 0; k < c->n_clouds; ++k) {
             const int64_t nw = c->cloud_off[k + 1] - c->cloud_off[k];
@@ -950,8 +1006,9 @@ static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& 
                              hipStream_t st) {
     const int ct = (int)((sh.s + ST - 1) / ST);
     const int64_t per_xcd = (sh.n_tiles + NXCD - 1) / NXCD;
-    hipLaunchKernelGGL((k_cocg_spmm<CZ, C, ST>), dim3((unsigned)(per_xcd * NXCD * ct)), dim3(RB), 0, st,
-                       (const Chunk*)L.tiles, sh.n_tiles, ct, (const int64_t*)c->row_ptr,
+    const int64_t nblk = sh.cocg_xcd ? per_xcd * NXCD * ct : sh.n_tiles * ct;
+    hipLaunchKernelGGL((k_cocg_spmm<CZ, C, ST>), dim3((unsigned)nblk), dim3(RB), 0, st,
+                       (const Chunk*)L.tiles, sh.n_tiles, ct, sh.cocg_xcd, (const int64_t*)c->row_ptr,
                        (const int32_t*)c->col_idx, Z, p, q, sh.s, L.tpart);
 }
 
@@ -1031,7 +1088,7 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         {   // q = Z p with per-tile p^T q
             ProfScope ps("spmm", st, ((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 8.0 * (c->n + 1) +
                                          3.0 * vs * sizeof(C));
-            switch (wst) {
+            switch (sh.cocg_st) {
                 case 1: launch_cocg_spmm<CZ, C, 1>(c, sh, L, Z, p, q, st); break;
                 case 2: launch_cocg_spmm<CZ, C, 2>(c, sh, L, Z, p, q, st); break;
                 case 4: launch_cocg_spmm<CZ, C, 4>(c, sh, L, Z, p, q, st); break;
@@ -1319,6 +1376,68 @@ chaff_status solve(Cloud* c, const chaff_solve_opts* o, const void* Z, const voi
                                     ws_bytes, st_out, rel_res, st);
     return solve_impl<c128, c128>(c, o, (const c128*)Z, (const c128*)Pinv, k_hat, e_hat, s, (c128*)X, ws,
                                   ws_bytes, st_out, rel_res, st);
+}
+
+// Time every product variant on the caller's Z, X, Y and record the fastest.
+chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y, int64_t s, int32_t* best,
+                      double* best_ms, hipStream_t st) {
+    TuneEntry t{};
+    t.n = c->n;
+    t.nnzb = c->nnzb;
+    t.s = s;
+    t.prec = prec;
+    hipEvent_t a, b;
+    CHAFF_HIP(hipEventCreate(&a));
+    CHAFF_HIP(hipEventCreate(&b));
+    double bms = 1e300;
+    int bv = default_variant(s);
+    for (int v = 0; v <= 4; ++v) {
+        for (int rep = 0; rep < 7; ++rep) {
+            if (rep == 2) CHAFF_HIP(hipEventRecord(a, st));
+            chaff_status r = spmm_public(c, prec, Z, X, Y, s, v, st);
+            if (r != CHAFF_OK) {
+                hipEventDestroy(a);
+                hipEventDestroy(b);
+                return r;
+            }
+        }
+        CHAFF_HIP(hipEventRecord(b, st));
+        CHAFF_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        CHAFF_HIP(hipEventElapsedTime(&ms, a, b));
+        t.ms[v] = ms / 5.0;
+        if (t.ms[v] < bms) {
+            bms = t.ms[v];
+            bv = v;
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    t.best = bv;
+    record_tuning(t);
+    if (best) *best = bv;
+    if (best_ms) *best_ms = bms;
+    return CHAFF_OK;
+}
+
+int32_t tune_report(char* buf, int32_t len) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::string out = "[";
+    for (size_t i = 0; i < g_tune.size(); ++i) {
+        const TuneEntry& e = g_tune[i];
+        char line[512];
+        std::snprintf(line, sizeof line,
+                      "%s{\"n\":%lld,\"nnzb\":%lld,\"s\":%lld,\"prec\":%d,\"best\":%d,\"ms\":[%.4f,%.4f,%.4f,%.4f,%.4f]}",
+                      i ? "," : "", (long long)e.n, (long long)e.nnzb, (long long)e.s, e.prec, e.best, e.ms[0],
+                      e.ms[1], e.ms[2], e.ms[3], e.ms[4]);
+        out += line;
+    }
+    out += "]";
+    if (buf && len > 0) {
+        std::strncpy(buf, out.c_str(), (size_t)len - 1);
+        buf[len - 1] = 0;
+    }
+    return (int32_t)out.size() + 1;
 }
 
 chaff_status excitation(Cloud* c, const double* k_hat, const double* e_hat, int64_t s, void* U, hipStream_t st) {

@@ -288,3 +288,24 @@ def test_tangent_validation_on_device(B):
     with pytest.raises(B.ChaffError) as ei:
         B.build_cloud(bad)
     assert ei.value.status == B.EINVAL
+
+
+def test_autotune_records_and_uses_the_fastest_variant(B):
+    import torch
+    wl = W.c2()
+    say("[autotune] c2, s=8")
+    cl = B.build_cloud(wl.cloud)
+    Z, _ = B.fill_Z(cl, B.C64, with_pinv=False)
+    best, ms = B.autotune(cl, Z, 8, B.C64)
+    assert 0 <= best <= 4 and ms > 0
+    table = B.tune_report()
+    ent = [e for e in table if e["n"] == cl.n and e["nnzb"] == cl.nnzb and e["s"] == 8 and e["prec"] == B.C64]
+    assert len(ent) == 1 and ent[0]["best"] == best
+    assert min(ent[0]["ms"]) == pytest.approx(ent[0]["ms"][best])
+    X = torch.randn(cl.n * 7, 8, dtype=torch.complex64, device="cuda")
+    y_tuned = _to_np(B.spmm(cl, Z, X, B.C64, -1))
+    y_best = _to_np(B.spmm(cl, Z, X, B.C64, best))
+    assert np.array_equal(y_tuned, y_best)
+    # a solve on the tuned table still meets the bar
+    X2, info = B.solve(cl, *B.fill_Z(cl, B.C64), wl.inc.k_hat, wl.inc.e_hat, B.solve_opts(tol=1e-6))
+    assert info["max_rel_residual"] <= 1e-6
