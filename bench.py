@@ -75,7 +75,7 @@ CONFIGS = {
     "c2": dict(prec="c64", method="gmres", restart=30, inner_tol=1e-4,
                desc="2,000 wires, Gaussian sigma=15 lambda, d_c=1.5 lambda, 1 incidence, "
                     "complex64 + FP64 refinement"),
-    "c3": dict(prec="c64", method="gmres", restart=20, inner_tol=1e-4,
+    "c3": dict(prec="c64", method="cocg", restart=2000, inner_tol=1e-5,
                desc="20,000-wire Gaussian cloud + 16 side clouds (500-5,000 wires), d_c=2 lambda, "
                     "360 azimuth incidences, one launch per stage for all 17 clouds"),
     "c4_eval": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5,

@@ -47,34 +47,35 @@ __device__ __forceinline__ c128 wire_term(const Wire& w, const c128* __restrict_
     return cscale(acc, env);
 }
 
-// partial[chunk][r] for monostatic pairs (dir r, rhs r); X caller order
+// partial[chunk][r] for monostatic pairs (dir r, rhs r); X caller order.
+// Lanes are RHS columns, so each wire row of X is one coalesced load; the four
+// waves take every fourth wire of the chunk and are combined in wave order.
 __global__ __launch_bounds__(256) void k_mono(const Wire* __restrict__ wires, const int32_t* __restrict__ perm,
                                               const int64_t* __restrict__ chunk_w0, int n_chunks, int64_t R,
                                               const c128* __restrict__ X, const double* __restrict__ dir,
                                               const double* __restrict__ pol, double k, c128* __restrict__ part) {
-    __shared__ double red_re[256], red_im[256];
+    __shared__ c128 red[4][64];
     const int ch = blockIdx.x;
-    const int64_t r = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
     const int64_t w0 = chunk_w0[ch], w1 = chunk_w0[ch + 1];
-    const double rx = dir[3 * r], ry = dir[3 * r + 1], rz = dir[3 * r + 2];
-    const double ex = pol[3 * r], ey = pol[3 * r + 1], ez = pol[3 * r + 2];
     c128 acc = {0, 0};
-    for (int64_t i = w0 + threadIdx.x; i < w1; i += blockDim.x) {
-        const Wire w = wires[i];
-        const c128* xp = X + (int64_t)perm[i] * NB * R + r;
-        acc = cadd(acc, wire_term(w, xp, R, k, rx, ry, rz, ex, ey, ez));
-    }
-    red_re[threadIdx.x] = acc.re;
-    red_im[threadIdx.x] = acc.im;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
-            red_re[threadIdx.x] += red_re[threadIdx.x + st];
-            red_im[threadIdx.x] += red_im[threadIdx.x + st];
+    if (r < R) {
+        const double rx = dir[3 * r], ry = dir[3 * r + 1], rz = dir[3 * r + 2];
+        const double ex = pol[3 * r], ey = pol[3 * r + 1], ez = pol[3 * r + 2];
+        for (int64_t i = w0 + w; i < w1; i += 4) {
+            const Wire wr = wires[i];
+            const c128* xp = X + (int64_t)perm[i] * NB * R + r;
+            acc = cadd(acc, wire_term(wr, xp, R, k, rx, ry, rz, ex, ey, ez));
         }
-        __syncthreads();
     }
-    if (threadIdx.x == 0) part[(int64_t)ch * R + r] = c128{red_re[0], red_im[0]};
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && r < R) {
+        c128 t = red[0][lane];
+        for (int q = 1; q < 4; ++q) t = cadd(t, red[q][lane]);
+        part[(int64_t)ch * R + r] = t;
+    }
 }
 
 // partial[chunk][r][m] for every (rhs r, direction m)
@@ -161,7 +162,7 @@ chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const d
         ProfScope ps(mono ? "rcs_mono" : "rcs_bistatic", st,
                      mono ? 16.0 * NB * (double)c->n * R + 64.0 * c->n : 55.0 * (double)c->n * R * M, !mono);
         if (mono) {
-            hipLaunchKernelGGL(k_mono, dim3(nch, (unsigned)R), dim3(256), 0, st, (const Wire*)c->wires,
+            hipLaunchKernelGGL(k_mono, dim3(nch, (unsigned)((R + 63) / 64)), dim3(256), 0, st, (const Wire*)c->wires,
                                (const int32_t*)c->perm, (const int64_t*)d_w0, nch, R, X, dir, pol, k, part);
         } else {
             dim3 grid((unsigned)((M + 255) / 256), nch, (unsigned)R);
