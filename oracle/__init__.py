@@ -23,4 +23,4 @@ reciprocity, the optical theorem, segment-refinement convergence, the
 orientation-averaged dipole RCS quoted in Sec. III-B, closed-form integrals
 checked by adaptive quadrature, and brute force on tiny inputs.
 """
-from . import mom, solve  # noqa: F401
+from . import mlp, mom, solve  # noqa: F401

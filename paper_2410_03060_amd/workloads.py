@@ -269,3 +269,25 @@ def random_cloud(seed: int, n: int, box_lam: float = 4.0, d_c_lam: float = math.
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4_eval": c4_eval, "c5": c5}
+
+
+# --------------------------------------------------------------------------- learned guess
+
+MLP_LAYERS = ((160, 128), (128, 128), (128, 128), (128, 14))   # (inputs, outputs) per layer
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial network parameters, flat float64: per layer W [n_in][n_out]
+    (Glorot-uniform draw), then b [n_out] (zeros)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n_in, n_out in MLP_LAYERS:
+        lim = math.sqrt(6.0 / (n_in + n_out))
+        parts.append(rng.uniform(-lim, lim, n_in * n_out))
+        parts.append(np.zeros(n_out))
+    return np.concatenate(parts)
+
+
+def shuffle_order(seed: int, n: int) -> np.ndarray:
+    """A seeded permutation of n training rows (int64)."""
+    return np.random.default_rng(seed).permutation(n).astype(np.int64)
