@@ -147,7 +147,8 @@ typedef struct {
     double  inner_tol;        /* relative reduction asked of one FP32 cycle (1e-4) */
     int32_t restart;          /* GMRES(m) cycle length, 1..200 (30) */
     int32_t max_cycles;       /* restart/refinement cycles (50) */
-    int32_t use_x0;           /* 1: X holds an initial guess on entry */
+    int32_t use_x0;           /* 0: x0 = 0; 1: X holds an initial guess on entry;
+                                 2: block-Jacobi guess x0 = Pinv u */
     int32_t prec;             /* chaff_prec of Z, Pinv and the Krylov vectors */
     int32_t spmm_variant;     /* -1: tuned (chaff_autotune) or default choice; else variant 0..4 */
     int32_t method;           /* chaff_method */
@@ -172,7 +173,7 @@ size_t chaff_solve_workspace_bytes(chaff_cloud c, const chaff_solve_opts* o, int
 /*   Z, Pinv  from chaff_fill_Z with the same prec (COCG needs both symmetric: they are).
  *   restart  GMRES cycle length, or the step cap of one COCG cycle.
  *   k_hat, e_hat [R][3] double: propagation direction and polarisation (unit).
- *   X        [N*7][R] complex double, caller order; input guess if use_x0.
+ *   X        [N*7][R] complex double, caller order; input guess if use_x0 == 1.
  *   ws       device workspace of chaff_solve_workspace_bytes.
  *   rel_res  [host out, optional] [n_clouds*R] final relative residuals (cloud-major).
  *   Host-synchronising: reads residual estimates once per Arnoldi step. */
@@ -222,6 +223,96 @@ size_t chaff_rcs_workspace_bytes(chaff_cloud c, int64_t n_rhs, int64_t n_dirs, i
 chaff_status chaff_rcs(chaff_cloud c, const void* X, int64_t n_rhs, const double* obs_dir,
                        const double* obs_pol, int64_t n_dirs, int32_t monostatic,
                        double* sigma, void* ws, size_t ws_bytes, chaff_stream stream);
+
+/* ------------------------------------------------------------------ learned initial guess
+ * Not part of the paper's method.  A small network predicts, for each wire p
+ * and incidence r, the wire's 7 currents from its neighbourhood; the result
+ * is the initial iterate of chaff_solve (use_x0 = 1).  The solver still
+ * drives the true residual of the S-NFC system to the requested tolerance,
+ * so the guess changes the iteration count, never the solution.
+ *
+ * Samples (rows): row = p*R + r, p in caller order.
+ * Canonical frame: s_p = +1 if t_p . e_r >= 0 else -1, tau_p = s_p t_p.
+ * Reversing a wire reverses its rooftop order and negates the coefficients,
+ * so the canonical currents are x~_{p,q} = s_p x_{p,q'}, q' = q if s_p = 1
+ * else 6 - q.  With k = 2 pi/wavelength, D_p = L_p/8, beta_p = k k_hat.tau_p,
+ * s_q = -L_p/2 + (q+1) D_p and sinc x = sin x / x, the 160 features of a row
+ * are
+ *   [0]        10 (L_p/wavelength - 1/2)
+ *   [1]        n_p/16, n_p = other wires of the cloud within d_c
+ *   [2+2q, 3+2q]  Re, Im of (tau_p.e) sinc^2(beta_p D_p/2) exp(-j beta_p s_q)
+ *              (the excitation of eq. (4) in the canonical frame, divided by
+ *              D_p, incident phase at c_p removed), q = 0..6
+ *   [16+9j .. 24+9j]  for the j-th nearest other wire p' within d_c
+ *              (ascending squared distance as in the near-set test, ties by
+ *              caller index; j < 16), d = c_p' - c_p:
+ *              |d|/d_c, tau_p.d/d_c, tau_p'.d/d_c, tau_p.tau_p',
+ *              Re, Im of (tau_p'.e) exp(-j k k_hat.d),
+ *              10 (L_p'/wavelength - 1/2), k_hat.tau_p', 1;  zeros if empty.
+ * Features are evaluated in FP64 and stored as BF16 bit patterns (uint16),
+ * rounded FP64 -> FP32 -> BF16, each step to nearest even.
+ *
+ * Network: 160 -> 128 -> 128 -> 128 -> 14, SiLU after the hidden layers.
+ * theta [CHAFF_MLP_NPARAM] float: W1 [160][128], b1 [128], W2 [128][128],
+ * b2, W3 [128][128], b3, W4 [128][14], b4 [14]; W[i][o] input-major.
+ * Products take BF16 weights and BF16 layer inputs with FP32 accumulation;
+ * biases, pre-activations and SiLU are FP32.
+ * Outputs / targets [rows][14] float: the departure of the currents from the
+ * wire's isolated response b_p = Pinv_p u_p (the block-Jacobi solution:
+ * Pinv_p the inverse self block of chaff_fill_Z, u_p the wire's excitation),
+ *   y[2q] + j y[2q+1] = (x~_{p,q} - b~_{p,q}) exp(+j k k_hat.c_p) / 0.5,
+ * b~ the canonical form of b.
+ * Loss: mean over rows and the 14 outputs of (y - t)^2.
+ * Buffers must be 16-byte aligned.  Requires a finite d_c > 0. */
+#define CHAFF_MLP_K 16
+#define CHAFF_MLP_NFEAT 160
+#define CHAFF_MLP_HIDDEN 128
+#define CHAFF_MLP_NOUT 14
+#define CHAFF_MLP_NPARAM 55438
+
+/* Features of rows [row0, row0 + n_rows) into feat [n_rows][160] (uint16 BF16). */
+chaff_status chaff_mlp_features(chaff_cloud c, const double* k_hat, const double* e_hat, int64_t n_rhs,
+                                int64_t row0, int64_t n_rows, uint16_t* feat, chaff_stream stream);
+
+/* Targets Y [N*R][14] float from currents X [N*7][R] complex double (caller
+ * order); Pinv [N][7][7] complex (prec) from chaff_fill_Z. */
+chaff_status chaff_mlp_targets(chaff_cloud c, chaff_prec prec, const void* Pinv, const double* k_hat,
+                               const double* e_hat, int64_t n_rhs, const void* X, float* Y,
+                               chaff_stream stream);
+
+/* Workspace of chaff_mlp_forward (train = 0) or chaff_mlp_grad / chaff_mlp_train_step
+ * (train = 1) for n_rows rows. */
+size_t chaff_mlp_workspace_bytes(int64_t n_rows, int32_t train);
+
+/* Network outputs Y [n_rows][14] of feat [n_rows][160]. */
+chaff_status chaff_mlp_forward(const float* theta, const uint16_t* feat, int64_t n_rows, float* Y,
+                               void* ws, size_t ws_bytes, chaff_stream stream);
+
+/* Loss and gradient over the rows idx[0..n_rows) of feat and T (idx NULL: rows
+ * 0..n_rows-1).  grad [CHAFF_MLP_NPARAM] float, loss [1] float (device; may be
+ * NULL).  Deterministic: every sum runs in a fixed order. */
+chaff_status chaff_mlp_grad(const float* theta, const uint16_t* feat, const float* T, const int64_t* idx,
+                            int64_t n_rows, float* grad, float* loss, void* ws, size_t ws_bytes,
+                            chaff_stream stream);
+
+/* One Adam step on theta with moments m, v (float [CHAFF_MLP_NPARAM]); step t >= 1. */
+chaff_status chaff_mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t t, float lr,
+                            float beta1, float beta2, float eps, chaff_stream stream);
+
+/* chaff_mlp_grad followed by chaff_mlp_adam (gradient kept in the workspace). */
+chaff_status chaff_mlp_train_step(float* theta, float* m, float* v, int32_t t, float lr, float beta1,
+                                  float beta2, float eps, const uint16_t* feat, const float* T,
+                                  const int64_t* idx, int64_t n_rows, float* loss, void* ws,
+                                  size_t ws_bytes, chaff_stream stream);
+
+/* Initial guess X [N*7][R] complex double (caller order) for chaff_solve with
+ * use_x0 = 1: features, network and the inverse of the target map (isolated
+ * response from Pinv plus the predicted departure), in chunks of at most
+ * 2^18 rows. */
+size_t chaff_mlp_guess_workspace_bytes(chaff_cloud c, int64_t n_rhs);
+chaff_status chaff_mlp_guess(chaff_cloud c, chaff_prec prec, const void* Pinv, const float* theta,
+                             const double* k_hat, const double* e_hat, int64_t n_rhs, void* X, void* ws,
+                             size_t ws_bytes, chaff_stream stream);
 
 /* ------------------------------------------------------------------ profiling
  * Per-kernel timing of the library's own launches with HIP events recorded

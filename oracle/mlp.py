@@ -15,8 +15,10 @@ This module is the plain definition of every step, in FP64 NumPy:
 * ``features``   -- 160 rotation- and translation-invariant numbers per
                     (wire, incidence), in the wire's canonical frame;
 * ``targets`` / ``currents_from_outputs`` -- the map between solved currents
-                    and the 14 network outputs (canonical frame, incident
-                    phase at the wire centre removed, fixed scale);
+                    and the 14 network outputs: the departure of the currents
+                    from the wire's isolated (block-Jacobi) response
+                    b_p = Z_pp^{-1} u_p, in the canonical frame, incident
+                    phase at the wire centre removed, fixed scale;
 * ``forward`` / ``loss_and_grad`` -- the 160-128-128-128-14 SiLU network,
                     optionally with the BF16 rounding points of the GPU
                     method emulated (BF16 weights and layer inputs, exact
@@ -46,7 +48,9 @@ and for neighbour slot j (j-th nearest p', d = c_p' - c_p), at 16 + 9 j:
 Own features 2..15 are the excitation of eq. (4) in the canonical frame,
 divided by Delta_p and with the incident phase at c_p removed.
 
-Targets: y[2q] + j y[2q+1] = x~_{p,q} exp(+j k k_hat . c_p) / 4.
+Targets: y[2q] + j y[2q+1] = (x~_{p,q} - b~_{p,q}) exp(+j k k_hat . c_p) / 0.5,
+where b~ is the canonical form of b_p = Z_pp^{-1} u_p (the currents the wire
+would carry alone) -- the network predicts only what the neighbours change.
 
 Rounding to BF16 (``bf16``): FP64 -> FP32 (nearest even) -> BF16 (nearest
 even on the FP32 bit pattern).
@@ -59,7 +63,7 @@ import math
 
 import numpy as np
 
-from .mom import _d2, near_pairs
+from .mom import _d2, excitation, near_pairs, self_blocks
 
 K_NB = 16
 F_OWN = 16
@@ -67,7 +71,7 @@ F_NB = 9
 N_FEAT = F_OWN + K_NB * F_NB       # 160
 HIDDEN = 128
 N_OUT = 14
-X_SCALE = 4.0
+X_SCALE = 0.5
 LAYERS = ((N_FEAT, HIDDEN), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN), (HIDDEN, N_OUT))
 
 
@@ -197,36 +201,55 @@ def features(cloud, k_hat: np.ndarray, e_hat: np.ndarray, nbrs=None) -> np.ndarr
     return out.reshape(n * R, N_FEAT)
 
 
-def targets(cloud, k_hat: np.ndarray, e_hat: np.ndarray, x: np.ndarray) -> np.ndarray:
+def self_inverse(cloud) -> np.ndarray:
+    """Z_pp^{-1} [N, 7, 7] (the block-Jacobi preconditioner of Sec. II-B)."""
+    k = 2.0 * math.pi / cloud.wavelength
+    return np.linalg.inv(self_blocks(cloud.length, cloud.radius, k))
+
+
+def isolated_response(cloud, k_hat: np.ndarray, e_hat: np.ndarray, dinv=None) -> np.ndarray:
+    """b [N, 7, R] = Z_pp^{-1} u_p exp(+j k k_hat . c_p) (raw rooftop order)."""
+    k_hat = np.atleast_2d(k_hat)
+    e_hat = np.atleast_2d(e_hat)
+    n, R = cloud.n, k_hat.shape[0]
+    k = 2.0 * math.pi / cloud.wavelength
+    dinv = self_inverse(cloud) if dinv is None else dinv
+    u = excitation(cloud, k_hat, e_hat).reshape(n, 7, R)
+    ph = np.exp(1j * k * (cloud.center @ k_hat.T))            # [N,R]
+    return np.einsum("nij,njr->nir", dinv, u) * ph[:, None, :]
+
+
+def targets(cloud, k_hat: np.ndarray, e_hat: np.ndarray, x: np.ndarray, dinv=None) -> np.ndarray:
     """Y [N*R, 14] from currents x [N*7, R] (caller order)."""
     k_hat = np.atleast_2d(k_hat)
     e_hat = np.atleast_2d(e_hat)
     n, R = cloud.n, k_hat.shape[0]
     k = 2.0 * math.pi / cloud.wavelength
-    xb = np.asarray(x).reshape(n, 7, R)
-    s = canonical_sign(cloud.tangent, e_hat)                  # [N,R]
     ph = np.exp(1j * k * (cloud.center @ k_hat.T))            # [N,R]
-    xc = np.where((s > 0)[:, None, :], xb, xb[:, ::-1, :])    # canonical order
-    xc = s[:, None, :] * xc * ph[:, None, :] / X_SCALE        # [N,7,R]
+    d = np.asarray(x).reshape(n, 7, R) * ph[:, None, :] - isolated_response(cloud, k_hat, e_hat, dinv)
+    s = canonical_sign(cloud.tangent, e_hat)                  # [N,R]
+    dc = np.where((s > 0)[:, None, :], d, d[:, ::-1, :])      # canonical order
+    dc = s[:, None, :] * dc / X_SCALE                         # [N,7,R]
     y = np.empty((n, R, N_OUT))
-    y[:, :, 0::2] = xc.real.transpose(0, 2, 1)
-    y[:, :, 1::2] = xc.imag.transpose(0, 2, 1)
+    y[:, :, 0::2] = dc.real.transpose(0, 2, 1)
+    y[:, :, 1::2] = dc.imag.transpose(0, 2, 1)
     return y.reshape(n * R, N_OUT)
 
 
-def currents_from_outputs(cloud, k_hat: np.ndarray, e_hat: np.ndarray, y: np.ndarray) -> np.ndarray:
+def currents_from_outputs(cloud, k_hat: np.ndarray, e_hat: np.ndarray, y: np.ndarray, dinv=None) -> np.ndarray:
     """x [N*7, R] (caller order) from network outputs Y [N*R, 14]; inverse of ``targets``."""
     k_hat = np.atleast_2d(k_hat)
     e_hat = np.atleast_2d(e_hat)
     n, R = cloud.n, k_hat.shape[0]
     k = 2.0 * math.pi / cloud.wavelength
     yr = np.asarray(y, dtype=np.float64).reshape(n, R, N_OUT)
-    xc = (yr[:, :, 0::2] + 1j * yr[:, :, 1::2]).transpose(0, 2, 1)   # [N,7,R]
+    dc = (yr[:, :, 0::2] + 1j * yr[:, :, 1::2]).transpose(0, 2, 1)   # [N,7,R] canonical
     s = canonical_sign(cloud.tangent, e_hat)
+    dc = X_SCALE * s[:, None, :] * dc
+    d = np.where((s > 0)[:, None, :], dc, dc[:, ::-1, :])
     ph = np.exp(-1j * k * (cloud.center @ k_hat.T))
-    xc = X_SCALE * s[:, None, :] * xc * ph[:, None, :]
-    xb = np.where((s > 0)[:, None, :], xc, xc[:, ::-1, :])
-    return xb.reshape(n * 7, R)
+    x = (d + isolated_response(cloud, k_hat, e_hat, dinv)) * ph[:, None, :]
+    return x.reshape(n * 7, R)
 
 
 # ----------------------------------------------------------------------------
@@ -309,10 +332,10 @@ def adam(theta, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: float = 0
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def guess(cloud, k_hat, e_hat, theta, emulate_bf16: bool = True):
-    """Initial currents x0 [N*7, R] predicted by the network."""
+def guess(cloud, k_hat, e_hat, theta, emulate_bf16: bool = True, dinv=None):
+    """Initial currents x0 [N*7, R]: isolated response plus the network's correction."""
     X = features(cloud, k_hat, e_hat)
     if emulate_bf16:
         X = bf16(X)
     Y, _ = forward(theta, X, emulate_bf16)
-    return currents_from_outputs(cloud, k_hat, e_hat, Y)
+    return currents_from_outputs(cloud, k_hat, e_hat, Y, dinv)

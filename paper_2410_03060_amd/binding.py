@@ -89,6 +89,23 @@ EXPORTS = {
     "chaff_tune_report": (C.c_int32, [C.c_char_p, C.c_int32]),
     "chaff_profile_enable": (C.c_int, [C.c_int32]),
     "chaff_profile_read": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "chaff_mlp_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                                     C.c_void_p, C.c_void_p]),
+    "chaff_mlp_targets": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chaff_mlp_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32]),
+    "chaff_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t,
+                                    C.c_void_p]),
+    "chaff_mlp_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "chaff_mlp_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                 C.c_float, C.c_float, C.c_float, C.c_void_p]),
+    "chaff_mlp_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float,
+                                       C.c_float, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "chaff_mlp_guess_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int64]),
+    "chaff_mlp_guess": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "chaff_last_error": (C.c_char_p, []),
     "chaff_version": (C.c_char_p, []),
 }
@@ -280,7 +297,7 @@ def fill_Z(cl: Cloud, prec: int = C64, with_pinv: bool = True):
 GMRES, COCG, COCG_RR = 0, 1, 2
 
 
-def solve_opts(tol=1e-6, inner_tol=1e-4, restart=30, max_cycles=50, use_x0=False, prec=C64,
+def solve_opts(tol=1e-6, inner_tol=1e-4, restart=30, max_cycles=50, use_x0=0, prec=C64,
                spmm_variant=-1, method=GMRES) -> SolveOpts:
     return SolveOpts(tol, inner_tol, restart, max_cycles, int(use_x0), prec, spmm_variant, method)
 
@@ -386,6 +403,103 @@ def profile_read() -> dict:
                                        min_ms=buf[i].min_ms, max_ms=buf[i].max_ms, work=buf[i].work,
                                        unit="flop" if buf[i].work_is_flops else "B")
             for i in range(n)}
+
+
+# ------------------------------------------------------------------ learned initial guess
+
+MLP_NFEAT, MLP_HIDDEN, MLP_NOUT, MLP_NPARAM = 160, 128, 14, 55438
+
+
+def mlp_features(cl: Cloud, k_hat, e_hat, row0: int = 0, n_rows: int | None = None):
+    """BF16 feature bit patterns [n_rows, 160] (int16) of rows row0.. (row = p*R + r)."""
+    kh = _dev_f64(_2d(k_hat), cl.device)
+    eh = _dev_f64(_2d(e_hat), cl.device)
+    R = kh.shape[0]
+    if n_rows is None:
+        n_rows = cl.n * R - row0
+    feat = torch.empty((max(n_rows, 1), MLP_NFEAT), dtype=torch.int16, device=cl.device)
+    _check(lib().chaff_mlp_features(cl.handle, _ptr(kh), _ptr(eh), R, row0, n_rows, _ptr(feat), _stream()))
+    return feat[:n_rows]
+
+
+def mlp_targets(cl: Cloud, Pinv, k_hat, e_hat, X, prec: int = C64):
+    """Network targets [N*R, 14] float32 from currents X [N*7, R] complex128 (caller order)."""
+    kh = _dev_f64(_2d(k_hat), cl.device)
+    eh = _dev_f64(_2d(e_hat), cl.device)
+    R = kh.shape[0]
+    X = X.to(device=cl.device, dtype=torch.complex128).contiguous()
+    Y = torch.empty((cl.n * R, MLP_NOUT), dtype=torch.float32, device=cl.device)
+    _check(lib().chaff_mlp_targets(cl.handle, prec, _ptr(Pinv), _ptr(kh), _ptr(eh), R, _ptr(X), _ptr(Y),
+                                   _stream()))
+    return Y
+
+
+def mlp_forward(theta, feat):
+    """Network outputs [rows, 14] float32 of BF16 features [rows, 160] (int16 bit patterns)."""
+    rows = feat.shape[0]
+    need = lib().chaff_mlp_workspace_bytes(rows, 0)
+    ws = torch.empty(need, dtype=torch.uint8, device=feat.device)
+    Y = torch.empty((rows, MLP_NOUT), dtype=torch.float32, device=feat.device)
+    _check(lib().chaff_mlp_forward(_ptr(theta), _ptr(feat), rows, _ptr(Y), _ptr(ws), need, _stream()))
+    return Y
+
+
+def mlp_grad(theta, feat, T, idx=None, n_rows: int | None = None):
+    """(gradient [55438] float32, loss [1] float32) over rows idx (or all rows)."""
+    rows = n_rows if n_rows is not None else (idx.shape[0] if idx is not None else feat.shape[0])
+    need = lib().chaff_mlp_workspace_bytes(rows, 1)
+    ws = torch.empty(need, dtype=torch.uint8, device=feat.device)
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=feat.device)
+    loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+    _check(lib().chaff_mlp_grad(_ptr(theta), _ptr(feat), _ptr(T), _ptr(idx), rows, _ptr(g), _ptr(loss),
+                                _ptr(ws), need, _stream()))
+    return g, loss
+
+
+def mlp_adam(theta, m, v, grad, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One in-place Adam step on theta, m, v."""
+    _check(lib().chaff_mlp_adam(_ptr(theta), _ptr(m), _ptr(v), _ptr(grad), t, lr, beta1, beta2, eps, _stream()))
+
+
+class MlpTrainer:
+    """FP32 master parameters, Adam moments and the training workspace for one batch size."""
+
+    def __init__(self, theta0, batch: int, device="cuda", beta1=0.9, beta2=0.999, eps=1e-8):
+        self.theta = torch.as_tensor(np.asarray(theta0, dtype=np.float32), device=device).contiguous()
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.t = 0
+        self.batch = batch
+        self.betas = (beta1, beta2)
+        self.eps = eps
+        self.need = lib().chaff_mlp_workspace_bytes(batch, 1)
+        self.ws = torch.empty(self.need, dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def step(self, feat, T, idx, lr: float):
+        """One Adam step on the rows idx [<= batch] (int64, device) of feat / T; loss stays on the device."""
+        rows = idx.shape[0]
+        if rows > self.batch:
+            raise ValueError("more rows than the trainer's batch size")
+        self.t += 1
+        _check(lib().chaff_mlp_train_step(_ptr(self.theta), _ptr(self.m), _ptr(self.v), self.t, lr,
+                                          self.betas[0], self.betas[1], self.eps, _ptr(feat), _ptr(T),
+                                          _ptr(idx), rows, _ptr(self.loss), _ptr(self.ws), self.need,
+                                          _stream()))
+        return self.loss
+
+
+def mlp_guess(cl: Cloud, Pinv, theta, k_hat, e_hat, prec: int = C64):
+    """Initial currents X [N*7, R] complex128 (caller order): isolated response + network correction."""
+    kh = _dev_f64(_2d(k_hat), cl.device)
+    eh = _dev_f64(_2d(e_hat), cl.device)
+    R = kh.shape[0]
+    need = lib().chaff_mlp_guess_workspace_bytes(cl.handle, R)
+    ws = torch.empty(need, dtype=torch.uint8, device=cl.device)
+    X = torch.empty((cl.n * NB, R), dtype=torch.complex128, device=cl.device)
+    _check(lib().chaff_mlp_guess(cl.handle, prec, _ptr(Pinv), _ptr(theta), _ptr(kh), _ptr(eh), R, _ptr(X),
+                                 _ptr(ws), need, _stream()))
+    return X
 
 
 def version() -> str:

@@ -79,6 +79,23 @@ chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const d
 chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y, int64_t s, int32_t* best,
                       double* best_ms, hipStream_t st);
 int32_t tune_report(char* buf, int32_t len);
+size_t mlp_workspace_bytes(int64_t rows, int32_t train);
+chaff_status mlp_forward(const float* theta, const uint16_t* feat, int64_t M, float* Y, void* ws, size_t ws_bytes,
+                         hipStream_t st);
+chaff_status mlp_grad(const float* theta, const uint16_t* feat, const float* T, const int64_t* idx, int64_t M,
+                      float* grad, float* loss, void* ws, size_t ws_bytes, hipStream_t st);
+chaff_status mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t t, float lr, float b1, float b2,
+                      float eps, hipStream_t st);
+chaff_status mlp_train_step(float* theta, float* m, float* v, int32_t t, float lr, float b1, float b2, float eps,
+                            const uint16_t* feat, const float* T, const int64_t* idx, int64_t M, float* loss, void* ws,
+                            size_t ws_bytes, hipStream_t st);
+chaff_status mlp_features(Cloud* c, const double* k_hat, const double* e_hat, int64_t R, int64_t row0, int64_t n_rows,
+                          uint16_t* feat, hipStream_t st);
+chaff_status mlp_targets(Cloud* c, chaff_prec prec, const void* Pinv, const double* k_hat, const double* e_hat,
+                         int64_t R, const void* X, float* Y, hipStream_t st);
+size_t mlp_guess_workspace_bytes(const Cloud* c, int64_t R);
+chaff_status mlp_guess(Cloud* c, chaff_prec prec, const void* Pinv, const float* theta, const double* k_hat,
+                       const double* e_hat, int64_t R, void* X, void* ws, size_t ws_bytes, hipStream_t st);
 
 }  // namespace chaff
 
@@ -121,6 +138,119 @@ static chaff_status check_params(const chaff_params* p, const int64_t* cloud_off
 }
 
 extern "C" {
+
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+static chaff_status check_mlp_cloud(chaff_cloud h, const double* k_hat, const double* e_hat, int64_t n_rhs) {
+    if (!h || !k_hat || !e_hat) return fail(CHAFF_EINVAL, "NULL argument");
+    if (n_rhs < 1) return fail(CHAFF_EINVAL, "n_rhs must be >= 1");
+    if (!(h->c.d_c > 0) || !std::isfinite(h->c.d_c))
+        return fail(CHAFF_EINVAL, "the learned guess needs a finite d_c > 0");
+    if (h->c.n > INT64_MAX / n_rhs / CHAFF_MLP_NFEAT) return fail(CHAFF_EINVAL, "n_wires * n_rhs too large");
+    return CHAFF_OK;
+}
+
+chaff_status chaff_mlp_features(chaff_cloud h, const double* k_hat, const double* e_hat, int64_t n_rhs, int64_t row0,
+                                int64_t n_rows, uint16_t* feat, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    chaff_status s = check_mlp_cloud(h, k_hat, e_hat, n_rhs);
+    if (s != CHAFF_OK) return s;
+    if (!feat || !aligned16(feat)) return fail(CHAFF_EINVAL, "feat must be a 16-byte aligned device pointer");
+    if (row0 < 0 || n_rows < 0 || row0 + n_rows > h->c.n * n_rhs)
+        return fail(CHAFF_EINVAL, "rows out of range [0, n_wires * n_rhs)");
+    return mlp_features(&h->c, k_hat, e_hat, n_rhs, row0, n_rows, feat, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_mlp_targets(chaff_cloud h, chaff_prec prec, const void* Pinv, const double* k_hat,
+                               const double* e_hat, int64_t n_rhs, const void* X, float* Y, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    chaff_status s = check_mlp_cloud(h, k_hat, e_hat, n_rhs);
+    if (s != CHAFF_OK) return s;
+    if (!X || !Y || !Pinv) return fail(CHAFF_EINVAL, "NULL argument");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "bad prec");
+    return mlp_targets(&h->c, prec, Pinv, k_hat, e_hat, n_rhs, X, Y, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+size_t chaff_mlp_workspace_bytes(int64_t n_rows, int32_t train) {
+    if (n_rows < 1 || n_rows > ((int64_t)1 << 40)) return 0;
+    return mlp_workspace_bytes(n_rows, train);
+}
+
+chaff_status chaff_mlp_forward(const float* theta, const uint16_t* feat, int64_t n_rows, float* Y, void* ws,
+                               size_t ws_bytes, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!theta || !feat || !Y || !ws) return fail(CHAFF_EINVAL, "NULL argument");
+    if (!aligned16(feat)) return fail(CHAFF_EINVAL, "feat must be 16-byte aligned");
+    if (n_rows < 1 || n_rows > ((int64_t)1 << 40)) return fail(CHAFF_EINVAL, "n_rows out of range");
+    if (ws_bytes < mlp_workspace_bytes(n_rows, 0)) return fail(CHAFF_EWORKSPACE, "mlp workspace too small");
+    return mlp_forward(theta, feat, n_rows, Y, ws, ws_bytes, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_mlp_grad(const float* theta, const uint16_t* feat, const float* T, const int64_t* idx,
+                            int64_t n_rows, float* grad, float* loss, void* ws, size_t ws_bytes, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!theta || !feat || !T || !grad || !ws) return fail(CHAFF_EINVAL, "NULL argument");
+    if (!aligned16(feat)) return fail(CHAFF_EINVAL, "feat must be 16-byte aligned");
+    if (n_rows < 1 || n_rows > ((int64_t)1 << 40)) return fail(CHAFF_EINVAL, "n_rows out of range");
+    if (ws_bytes < mlp_workspace_bytes(n_rows, 1)) return fail(CHAFF_EWORKSPACE, "mlp workspace too small");
+    return mlp_grad(theta, feat, T, idx, n_rows, grad, loss, ws, ws_bytes, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+static chaff_status check_adam(int32_t t, float lr, float b1, float b2, float eps) {
+    if (t < 1) return fail(CHAFF_EINVAL, "Adam step t must be >= 1");
+    if (!(lr >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+        return fail(CHAFF_EINVAL, "bad Adam hyper-parameters");
+    return CHAFF_OK;
+}
+
+chaff_status chaff_mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t t, float lr, float beta1,
+                            float beta2, float eps, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!theta || !m || !v || !grad) return fail(CHAFF_EINVAL, "NULL argument");
+    chaff_status s = check_adam(t, lr, beta1, beta2, eps);
+    if (s != CHAFF_OK) return s;
+    return mlp_adam(theta, m, v, grad, t, lr, beta1, beta2, eps, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_mlp_train_step(float* theta, float* m, float* v, int32_t t, float lr, float beta1, float beta2,
+                                  float eps, const uint16_t* feat, const float* T, const int64_t* idx, int64_t n_rows,
+                                  float* loss, void* ws, size_t ws_bytes, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!theta || !m || !v || !feat || !T || !ws) return fail(CHAFF_EINVAL, "NULL argument");
+    if (!aligned16(feat)) return fail(CHAFF_EINVAL, "feat must be 16-byte aligned");
+    if (n_rows < 1 || n_rows > ((int64_t)1 << 40)) return fail(CHAFF_EINVAL, "n_rows out of range");
+    chaff_status s = check_adam(t, lr, beta1, beta2, eps);
+    if (s != CHAFF_OK) return s;
+    if (ws_bytes < mlp_workspace_bytes(n_rows, 1)) return fail(CHAFF_EWORKSPACE, "mlp workspace too small");
+    return mlp_train_step(theta, m, v, t, lr, beta1, beta2, eps, feat, T, idx, n_rows, loss, ws, ws_bytes,
+                          (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+size_t chaff_mlp_guess_workspace_bytes(chaff_cloud h, int64_t n_rhs) {
+    if (!h || n_rhs < 1) return 0;
+    return mlp_guess_workspace_bytes(&h->c, n_rhs);
+}
+
+chaff_status chaff_mlp_guess(chaff_cloud h, chaff_prec prec, const void* Pinv, const float* theta,
+                             const double* k_hat, const double* e_hat, int64_t n_rhs, void* X, void* ws,
+                             size_t ws_bytes, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    chaff_status s = check_mlp_cloud(h, k_hat, e_hat, n_rhs);
+    if (s != CHAFF_OK) return s;
+    if (!theta || !X || !ws || !Pinv) return fail(CHAFF_EINVAL, "NULL argument");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "bad prec");
+    if (ws_bytes < mlp_guess_workspace_bytes(&h->c, n_rhs))
+        return fail(CHAFF_EWORKSPACE, "mlp guess workspace too small");
+    return mlp_guess(&h->c, prec, Pinv, theta, k_hat, e_hat, n_rhs, X, ws, ws_bytes, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
 
 const char* chaff_last_error(void) { return g_last_error.c_str(); }
 const char* chaff_version(void) { return "chaff-gfx950 1.0"; }
@@ -188,6 +318,7 @@ static chaff_status check_opts(const chaff_solve_opts* o) {
     if (o->restart < 1 || (o->method == CHAFF_GMRES && o->restart > 200))
         return fail(CHAFF_EINVAL, "restart must be in [1, 200] (GMRES) or >= 1 (COCG)");
     if (o->max_cycles < 1) return fail(CHAFF_EINVAL, "max_cycles must be >= 1");
+    if (o->use_x0 < 0 || o->use_x0 > 2) return fail(CHAFF_EINVAL, "use_x0 must be 0, 1 or 2");
     if (o->prec != CHAFF_C64 && o->prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
     if (o->spmm_variant < -1 || o->spmm_variant > 4) return fail(CHAFF_EINVAL, "spmm_variant must be in [-1, 4]");
     if (o->method != CHAFF_GMRES && o->method != CHAFF_COCG && o->method != CHAFF_COCG_RR)

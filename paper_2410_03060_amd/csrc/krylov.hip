@@ -1169,13 +1169,19 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     }
 
     // --- excitation and initial guess (internal order, FP64)
+    chaff_status sst0 = CHAFF_OK;
     const double k = 2.0 * PI_K / c->wavelength;
     hipLaunchKernelGGL(k_excitation, dim3(blocks_for(c->n * s)), dim3(256), 0, st, (const Wire*)c->wires,
                        (const int32_t*)nullptr, c->n, k_hat, e_hat, s, k, L.b);
     CHAFF_LAUNCH_CHECK();
-    if (o->use_x0) {
+    if (o->use_x0 == 1) {
         hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)Xout,
                            (const int32_t*)c->perm, c->n, s, L.x, 0);
+    } else if (o->use_x0 == 2) {
+        // block-Jacobi guess x0 = Pinv u (FP64 vectors, stored Pinv)
+        sst0 = spmm_launch<CZ, c128, c128, 0, true>(nullptr, nullptr, Pinv, (const c128*)L.b, (const c128*)nullptr,
+                                                    L.x, c->n, c->n, s, -1, st, "guess_block_jacobi");
+        if (sst0 != CHAFF_OK) return sst0;
     } else {
         hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(vs * 4, 256)), dim3(256), 0, st, (uint32_t*)L.x,
                            vs * 4);
@@ -1196,7 +1202,7 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     std::vector<SysState> hsys(nsys);
     for (;;) {
         // true residual r = b - Z x (FP64 accumulation over the stored Z)
-        if (cycles == 0 && !o->use_x0) {
+        if (cycles == 0 && o->use_x0 == 0) {
             hipLaunchKernelGGL(k_copy_c128, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.b, vs, L.r);
             CHAFF_LAUNCH_CHECK();
         } else {

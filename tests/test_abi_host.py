@@ -125,3 +125,37 @@ def test_calls_on_null_handle_fail_cleanly(B):
 
 def test_version_string(B):
     assert B.version().startswith("chaff-gfx950")
+
+
+def test_mlp_entry_points_validate_before_any_launch(B):
+    L = B.lib()
+    P = C.c_void_p(0x1000)          # never dereferenced: every call below fails validation
+    a = L.chaff_mlp_workspace_bytes(1000, 1)
+    b = L.chaff_mlp_workspace_bytes(100000, 1)
+    f = L.chaff_mlp_workspace_bytes(100000, 0)
+    assert 0 < a < b and 0 < f < b
+    assert L.chaff_mlp_workspace_bytes(0, 1) == 0
+    # Adam: bad step / hyper-parameters
+    assert L.chaff_mlp_adam(P, P, P, P, 0, 1e-3, 0.9, 0.999, 1e-8, None) == B.EINVAL
+    assert "step" in B.last_error()
+    assert L.chaff_mlp_adam(P, P, P, P, 1, 1e-3, 1.0, 0.999, 1e-8, None) == B.EINVAL
+    assert L.chaff_mlp_adam(None, P, P, P, 1, 1e-3, 0.9, 0.999, 1e-8, None) == B.EINVAL
+    # misaligned features, too small a workspace, empty batch
+    assert L.chaff_mlp_forward(P, C.c_void_p(0x1002), 10, P, P, 1 << 30, None) == B.EINVAL
+    assert "aligned" in B.last_error()
+    assert L.chaff_mlp_forward(P, P, 10, P, P, 16, None) == B.EWORKSPACE
+    assert L.chaff_mlp_grad(P, P, P, None, 0, P, None, P, 1 << 30, None) == B.EINVAL
+    assert L.chaff_mlp_train_step(P, P, P, 1, 1e-3, 0.9, 0.999, 1e-8, P, P, None, 100, None, P, 16,
+                                  None) == B.EWORKSPACE
+    # cloud-based calls need a handle
+    assert L.chaff_mlp_features(None, P, P, 1, 0, 1, P, None) == B.EINVAL
+    assert L.chaff_mlp_targets(None, B.C64, P, P, P, 1, P, P, None) == B.EINVAL
+    assert L.chaff_mlp_guess(None, B.C64, P, P, P, P, 1, P, P, 1 << 30, None) == B.EINVAL
+    assert L.chaff_mlp_guess_workspace_bytes(None, 1) == 0
+
+
+def test_solve_rejects_bad_initial_guess_mode(B):
+    L = B.lib()
+    o = B.solve_opts(use_x0=3)
+    assert L.chaff_solve_workspace_bytes(C.c_void_p(0x1000), C.byref(o), 1) == 0
+    assert "use_x0" in B.last_error()

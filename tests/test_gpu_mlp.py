@@ -1,0 +1,238 @@
+"""GPU parity of the learned initial guess against the oracle (oracle.mlp).
+
+All calls go through the C ABI.  Inputs of the oracle never come from the
+GPU: features, targets and parameters are computed or drawn on the host.
+
+Tolerances:
+  * features: BF16 bit patterns; every value within one BF16 ulp (2^-7
+    relative) or 1e-12 absolute, and >= 99 % bit-identical -- both sides
+    evaluate in FP64 and round once, so only FP64 last-bit differences (sine
+    and cosine implementations, operation order) at a rounding boundary can
+    move a value; the neighbour order is an exact FP64 decision on both sides,
+    so a wrong slot would show as a difference far beyond one ulp;
+  * targets: FP32 rounding of an FP64 map, <= 1e-6 of the largest target
+    with the FP64 inverse self blocks, <= 2e-5 with the FP32 ones;
+  * network outputs vs the oracle with the same BF16 rounding points:
+    relative L2 <= 2e-3 (FP32 accumulation order; an activation that lands
+    next to a BF16 rounding boundary may round the other way);
+  * gradients: per tensor cosine >= 0.9999 and relative L2 <= 1e-2 against
+    the BF16-emulating oracle, and cosine >= 0.999, relative L2 <= 2e-2
+    against the exact FP64 gradient;
+  * Adam: FP32 update vs FP64, <= 1e-5 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from paper_2410_03060_amd import workloads as W
+from parity_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_03060_amd import binding
+    binding.lib()
+    return binding
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _theta(seed):
+    th = W.mlp_init(seed)
+    lay, _ = omlp.param_layout()
+    rng = np.random.default_rng(seed + 1)
+    for _, b, _, o in lay:
+        th[b:b + o] = 0.1 * rng.standard_normal(o)
+    return th
+
+
+def _bits_to_float(b):
+    return omlp.from_bf16_bits(np.asarray(b).view(np.uint16))
+
+
+def _feature_check(fg_bits, fo):
+    """fg_bits: GPU int16 patterns; fo: oracle FP64 features (unrounded)."""
+    want = omlp.bf16_bits(fo)
+    got = np.asarray(fg_bits).view(np.uint16)
+    same = np.mean(got == want)
+    g = _bits_to_float(got)
+    o = omlp.bf16(fo)
+    bad = np.abs(g - o) > 2.0 ** -7 * np.abs(o) + 1e-12
+    return same, int(bad.sum())
+
+
+def _dense_scene(seed=31):
+    # crowded enough that many wires have more than 16 neighbours within d_c
+    return W.random_cloud(seed, 900, box_lam=4.0, d_c_lam=1.0)
+
+
+@pytest.mark.parametrize("case", ["c4_like", "crowded", "two_clouds"])
+def test_features_match_oracle(B, case):
+    import torch
+    if case == "c4_like":
+        cloud = W.c4_train_cloud(0).cloud
+        inc = W.c4_train_cloud(0).inc
+    elif case == "crowded":
+        cloud = _dense_scene()
+        inc = W.random_incidences(np.random.default_rng(5), 3)
+    else:
+        a = W.random_cloud(41, 300, box_lam=3.0, d_c_lam=1.2)
+        b = W.random_cloud(42, 200, box_lam=3.0, d_c_lam=1.2)
+        cloud = W.concat_clouds([a, b])
+        inc = W.random_incidences(np.random.default_rng(6), 4)
+    say(f"[mlp features] {case}: N={cloud.n} R={inc.k_hat.shape[0]} d_c={cloud.d_c}")
+    cl = B.build_cloud(cloud)
+    fg = _np(B.mlp_features(cl, inc.k_hat, inc.e_hat))
+    fo = omlp.features(cloud, inc.k_hat, inc.e_hat)
+    same, bad = _feature_check(fg, fo)
+    say(f"   identical {same:.6f}, beyond one ulp {bad}")
+    assert same >= 0.99 and bad == 0
+    if case == "crowded":
+        _, count = omlp.knn(cloud)
+        assert count.max() > 16
+    # a ragged sub-range equals the slice of the full array
+    R = inc.k_hat.shape[0]
+    r0, nr = 3 * R + 1, 777
+    sub = _np(B.mlp_features(cl, inc.k_hat, inc.e_hat, r0, nr))
+    np.testing.assert_array_equal(sub, fg[r0:r0 + nr])
+    B.destroy(cl)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_targets_match_oracle(B, prec):
+    import torch
+    cloud = W.random_cloud(51, 700, box_lam=5.0, d_c_lam=1.5)
+    inc = W.random_incidences(np.random.default_rng(52), 5)
+    say(f"[mlp targets] N={cloud.n} R=5 Pinv {prec}")
+    rng = np.random.default_rng(53)
+    x = rng.standard_normal((cloud.n * 7, 5)) + 1j * rng.standard_normal((cloud.n * 7, 5))
+    cl = B.build_cloud(cloud)
+    pr = B.C128 if prec == "c128" else B.C64
+    _, P = B.fill_Z(cl, pr)
+    Yg = _np(B.mlp_targets(cl, P, inc.k_hat, inc.e_hat, torch.from_numpy(x), prec=pr))
+    Yo = omlp.targets(cloud, inc.k_hat, inc.e_hat, x)
+    err = np.max(np.abs(Yg - Yo)) / np.max(np.abs(Yo))
+    say(f"   max error / max |y| = {err:.2e}")
+    # c128: FP32 rounding of the outputs; c64: plus the FP32 inverse self blocks
+    assert err <= (1e-6 if prec == "c128" else 2e-5)
+    B.destroy(cl)
+
+
+def test_forward_matches_oracle(B):
+    import torch
+    say("[mlp forward] 3000 oracle-feature rows of a C4-like cloud + 333 random rows")
+    wl = W.c4_train_cloud(3)
+    fo = omlp.features(wl.cloud, wl.inc.k_hat, wl.inc.e_hat)[:3000]
+    rnd = np.random.default_rng(54).standard_normal((333, omlp.N_FEAT))
+    X = omlp.bf16(np.concatenate([fo, rnd]))
+    th = _theta(55)
+    bits = omlp.bf16_bits(X).view(np.int16)
+    Yg = _np(B.mlp_forward(torch.from_numpy(th.astype(np.float32)).cuda(), torch.from_numpy(bits).cuda()))
+    Ye, _ = omlp.forward(th.astype(np.float32).astype(np.float64), X, emulate_bf16=True)
+    Yx, _ = omlp.forward(th, X)
+    e_emul = np.linalg.norm(Yg - Ye) / np.linalg.norm(Ye)
+    e_exact = np.linalg.norm(Yg - Yx) / np.linalg.norm(Yx)
+    say(f"   rel L2 vs BF16-emulating oracle {e_emul:.2e}, vs exact FP64 {e_exact:.2e}")
+    assert e_emul <= 2e-3
+    assert e_exact <= 5e-2
+
+
+@pytest.mark.parametrize("rows,gather", [(1000, True), (512, False), (77, True)])
+def test_gradient_matches_oracle(B, rows, gather):
+    import torch
+    say(f"[mlp grad] rows={rows} gather={gather}")
+    rng = np.random.default_rng(60 + rows)
+    pool = 2500
+    X = omlp.bf16(rng.standard_normal((pool, omlp.N_FEAT)))
+    T = rng.standard_normal((pool, omlp.N_OUT)).astype(np.float32).astype(np.float64)
+    idx = rng.permutation(pool)[:rows] if gather else np.arange(rows)
+    th = _theta(61).astype(np.float32).astype(np.float64)
+    dev = torch.device("cuda")
+    g, loss = B.mlp_grad(torch.from_numpy(th.astype(np.float32)).to(dev),
+                         torch.from_numpy(omlp.bf16_bits(X).view(np.int16)).to(dev),
+                         torch.from_numpy(T.astype(np.float32)).to(dev),
+                         torch.from_numpy(idx.astype(np.int64)).to(dev) if gather else None,
+                         n_rows=rows)
+    g = _np(g).astype(np.float64)
+    le, ge = omlp.loss_and_grad(th, X[idx], T[idx], emulate_bf16=True)
+    lx, gx = omlp.loss_and_grad(th, X[idx], T[idx])
+    assert abs(float(_np(loss)[0]) - le) <= 1e-3 * le
+    lay, _ = omlp.param_layout()
+    for li, (w, b, i, o) in enumerate(lay):
+        for name, sl in (("W", slice(w, w + i * o)), ("b", slice(b, b + o))):
+            a, e, x = g[sl], ge[sl], gx[sl]
+            cos_e = a @ e / (np.linalg.norm(a) * np.linalg.norm(e))
+            rel_e = np.linalg.norm(a - e) / np.linalg.norm(e)
+            cos_x = a @ x / (np.linalg.norm(a) * np.linalg.norm(x))
+            rel_x = np.linalg.norm(a - x) / np.linalg.norm(x)
+            say(f"   {name}{li + 1}: emulated cos {cos_e:.6f} rel {rel_e:.2e} | exact cos {cos_x:.6f} rel {rel_x:.2e}")
+            assert cos_e >= 0.9999 and rel_e <= 1e-2
+            assert cos_x >= 0.999 and rel_x <= 2e-2
+
+
+def test_adam_matches_oracle(B):
+    import torch
+    say("[mlp adam] 3 steps")
+    rng = np.random.default_rng(70)
+    n = omlp.param_layout()[1]
+    th = rng.standard_normal(n).astype(np.float32)
+    dev = torch.device("cuda")
+    t_th = torch.from_numpy(th.copy()).to(dev)
+    t_m = torch.zeros(n, dtype=torch.float32, device=dev)
+    t_v = torch.zeros(n, dtype=torch.float32, device=dev)
+    o_th, o_m, o_v = th.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in range(1, 4):
+        g = rng.standard_normal(n).astype(np.float32)
+        B.mlp_adam(t_th, t_m, t_v, torch.from_numpy(g).to(dev), t, 1e-3)
+        o_th, o_m, o_v = omlp.adam(o_th, o_m, o_v, g.astype(np.float64), t, 1e-3)
+    err = np.abs(_np(t_th) - o_th)
+    assert np.max(err) <= 1e-5 * max(1.0, np.max(np.abs(o_th)))
+
+
+def test_guess_matches_oracle(B):
+    import torch
+    cloud = W.random_cloud(80, 600, box_lam=5.0, d_c_lam=1.5)
+    inc = W.random_incidences(np.random.default_rng(81), 3)
+    th = _theta(82)
+    say(f"[mlp guess] N={cloud.n} R=3")
+    cl = B.build_cloud(cloud)
+    _, P = B.fill_Z(cl, B.C64)
+    xg = _np(B.mlp_guess(cl, P, torch.from_numpy(th.astype(np.float32)).cuda(), inc.k_hat, inc.e_hat))
+    xo = omlp.guess(cloud, inc.k_hat, inc.e_hat, th.astype(np.float32).astype(np.float64), emulate_bf16=True)
+    e = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    say(f"   rel L2 {e:.2e}")
+    assert e <= 2e-3
+    B.destroy(cl)
+
+
+def test_solution_does_not_depend_on_the_initial_guess(B):
+    """Zero, block-Jacobi and network guesses all end at the same solution."""
+    import torch
+    cloud = W.random_cloud(90, 1500, box_lam=12.0, d_c_lam=1.5)
+    inc = W.random_incidences(np.random.default_rng(91), 4)
+    say(f"[mlp solve] N={cloud.n} R=4: zero / block-Jacobi / network guesses")
+    cl = B.build_cloud(cloud)
+    Z, P = B.fill_Z(cl, B.C64)
+    out = {}
+    for name in ("zero", "bj", "mlp"):
+        o = B.solve_opts(tol=1e-8, inner_tol=1e-5, restart=5000, prec=B.C64, method=B.COCG,
+                         use_x0=2 if name == "bj" else 0)
+        x0 = B.mlp_guess(cl, P, torch.from_numpy(_theta(92).astype(np.float32)).cuda(), inc.k_hat,
+                         inc.e_hat) if name == "mlp" else None
+        X, info = B.solve(cl, Z, P, inc.k_hat, inc.e_hat, o, x0=x0)
+        assert info["max_rel_residual"] <= 1e-8
+        out[name] = _np(X)
+        say(f"   {name}: iterations {info['iterations']} cycles {info['cycles']}")
+    for name in ("bj", "mlp"):
+        assert np.linalg.norm(out[name] - out["zero"]) <= 1e-6 * np.linalg.norm(out["zero"])
+    B.destroy(cl)

@@ -320,3 +320,18 @@ def test_features_of_a_hand_built_three_wire_scene():
     d = math.sqrt(0.34)
     np.testing.assert_allclose(b[16:25], [0.5, -0.5, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0], atol=1e-14)
     np.testing.assert_allclose(b[25:34], [d, -0.5, 0.3, 0.0, 1.0, 0.0, 0.5, 0.0, 1.0], atol=1e-14)
+
+
+def test_targets_vanish_for_uncoupled_wires():
+    """With d_c below every spacing the S-NFC matrix is block diagonal, each wire
+    carries its isolated response, and the network has nothing to predict."""
+    cl = W.random_cloud(25, 30, box_lam=4.0, d_c_lam=0.05)
+    inc = W.random_incidences(np.random.default_rng(26), 2)
+    assert mom.near_pairs(cl.center, cl.cloud_off, cl.d_c)[0].size == 0
+    x = _solve_dense(cl, inc)
+    Y = mlp.targets(cl, inc.k_hat, inc.e_hat, x)
+    assert np.max(np.abs(Y)) < 1e-10 * np.max(np.abs(x))
+    # with coupling the targets do not vanish
+    cl2 = W.single_cloud(cl.center, cl.tangent, cl.length, LAM, 2.0 * LAM)
+    Y2 = mlp.targets(cl2, inc.k_hat, inc.e_hat, _solve_dense(cl2, inc))
+    assert np.max(np.abs(Y2)) > 1e-3
