@@ -78,12 +78,16 @@ CONFIGS = {
     "c3": dict(prec="c64", method="cocg", restart=2000, inner_tol=1e-5,
                desc="20,000-wire Gaussian cloud + 16 side clouds (500-5,000 wires), d_c=2 lambda, "
                     "360 azimuth incidences, one launch per stage for all 17 clouds"),
-    "c4_eval": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5,
-                    desc="100,000 wires, uniform sphere R=40 lambda, d_c=1.5 lambda, 8 incidences"),
-    "c5": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5,
+    "c4_eval": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="mlp",
+                    desc="100,000 wires, uniform sphere R=40 lambda, d_c=1.5 lambda, 8 incidences, "
+                         "learned initial guess (3x128 MLP, BF16, trained on 200 solved clouds)"),
+    "c5": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="mlp",
                desc="1,000,000 wires (7M unknowns), uniform sphere R=50 lambda, d_c=1 lambda, "
-                    "64 azimuth incidences, complex64 + FP64 refinement"),
+                    "64 azimuth incidences, complex64 + FP64 refinement, learned initial guess"),
 }
+GUESSES = {"zero": 0, "bj": 2, "mlp": 1}
+# training recipe of the learned guess per evaluation workload: (generator, clouds, epochs)
+MLP_TRAINING = {"c4_eval": ("c4_train_cloud", 200, 12), "c5": ("c5_train_cloud", 64, 12)}
 METHODS = {"gmres": 0, "cocg": 1, "cocg_rr": 2}
 
 
@@ -155,6 +159,80 @@ def cpu_baseline(wl, n_sample: int = 2000, r_sample: int = 8):
                       f"by the wire ratio {scale:.1f}; full workload estimated at {t_full:.1f} s"}
 
 
+def train_guess(config, B):
+    """Train the learned guess for this workload on clouds solved by the library (untimed)."""
+    import numpy as np
+
+    from paper_2410_03060_amd import learned, workloads as W
+    gen, n_clouds, epochs = MLP_TRAINING[config]
+    make = getattr(W, gen)
+    samples = learned.solved_samples([make(j) for j in range(n_clouds)])
+    print(f"[bench] mlp: {samples.feat.shape[0]} samples from {n_clouds} solved clouds in "
+          f"{samples.solve_seconds:.1f} s", file=sys.stderr, flush=True)
+    res = learned.train(samples, W.mlp_init(0), epochs=epochs, batch=4096, seed=0)
+    err = learned.relative_target_error(res.theta, samples)
+    print(f"[bench] mlp: {res.steps} Adam steps in {res.seconds:.1f} s, final epoch loss {res.losses[-1]:.4f}, "
+          f"relative error of the predicted departure {err:.3f}", file=sys.stderr, flush=True)
+    report = {"train_clouds": f"{gen}(0..{n_clouds - 1})", "samples": int(samples.feat.shape[0]),
+              "data_seconds": samples.solve_seconds, "epochs": epochs, "batch": 4096, "adam_steps": res.steps,
+              "train_seconds": res.seconds, "ms_per_adam_step": res.seconds / res.steps * 1e3,
+              "epoch_losses": [round(x, 5) for x in res.losses], "train_relative_error": err,
+              "excluded_from_timing": True}
+    del samples
+    return res.theta, report
+
+
+def compare_guesses(step, kinds):
+    """Iterations and wall time of one full step with each initial guess (untimed region)."""
+    import torch
+    out = {}
+    for g in kinds:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cl, X, info, sig, Z = step(g)
+        torch.cuda.synchronize()
+        out[g] = {"iterations": info["iterations"], "cycles": info["cycles"],
+                  "max_rel_residual": info["max_rel_residual"], "step_seconds": time.perf_counter() - t0}
+        del cl, X, sig, Z
+        print(f"[bench] guess {g}: iterations {info['iterations']} step {out[g]['step_seconds']:.3f} s",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def fp64_comparator(B, geom, wl, kh, eh, tol, config, r_sample=4):
+    """The plain FP64 GPU solver: complex128 fill and COCG, zero initial guess,
+    one incidence per solve.  Setup (neighbour search + fill) is timed once,
+    r_sample incidences are solved one by one; the workload's cost is then
+    setup + R x the mean per-incidence solve (+ RCS)."""
+    import torch
+    R = kh.shape[0]
+    r_s = min(R, r_sample)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cl = B.build_cloud(geom)
+    Z, P = B.fill_Z(cl, B.C128)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    o = B.solve_opts(tol=tol, inner_tol=1e-5, restart=5000, max_cycles=60, prec=B.C128, method=B.COCG)
+    iters = []
+    for r in range(r_s):
+        X, info = B.solve(cl, Z, P, kh[r:r + 1], eh[r:r + 1], o)
+        B.rcs(cl, X, -kh[r:r + 1], eh[r:r + 1], monostatic=True)
+        iters.append(info["iterations"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    per = (t2 - t1) / r_s
+    total = (t1 - t0) + R * per
+    systems = wl.cloud.n_clouds * R
+    del Z, P, cl
+    print(f"[bench] FP64 comparator: setup {t1 - t0:.3f} s, {per:.3f} s per incidence, "
+          f"iterations {iters}", file=sys.stderr, flush=True)
+    return {"kind": "plain FP64 GPU solver: complex128 fill and COCG, zero initial guess, one incidence per solve",
+            "value": systems / total, "unit": "solved angles/s", "setup_seconds": t1 - t0,
+            "seconds_per_incidence": per, "incidences_sampled": r_s, "iterations": iters,
+            "speedup_of_value": None}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +246,12 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
+    ap.add_argument("--guess", default=None, choices=sorted(GUESSES),
+                    help="initial guess: zero, bj (block-Jacobi) or mlp (learned; trained before timing)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the untimed zero / block-Jacobi / learned guess comparison")
+    ap.add_argument("--no-comparator", action="store_true",
+                    help="skip the plain FP64 one-RHS-at-a-time solver comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     a = ap.parse_args(argv)
@@ -206,10 +290,19 @@ def main(argv=None) -> int:
                         inner_tol=a.inner_tol or cfg["inner_tol"])
     torch.cuda.synchronize()
 
-    def step():
+    guess = a.guess or cfg.get("guess", "zero")
+    mlp_report = None
+    theta = None
+    if guess == "mlp":
+        theta, mlp_report = train_guess(a.config, B)
+
+    def step(guess_kind=None):
+        gk = guess_kind or guess
         cl = B.build_cloud(geom)
         Z, P = B.fill_Z(cl, prec)
-        X, info = B.solve(cl, Z, P, kh, eh, opts)
+        x0 = B.mlp_guess(cl, P, theta, kh, eh, prec=prec) if gk == "mlp" else None
+        opts.use_x0 = GUESSES[gk]
+        X, info = B.solve(cl, Z, P, kh, eh, opts, x0=x0)
         sig = B.rcs(cl, X, -kh, eh, monostatic=True)
         return cl, X, info, sig, Z
 
@@ -228,6 +321,7 @@ def main(argv=None) -> int:
         print(f"[bench] warmup {w}: cycles={info['cycles']} iters={info['iterations']} "
               f"res={info['max_rel_residual']:.2e} solve={info['seconds']:.3f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
     B.profile_enable(True)
     t0 = time.perf_counter()
     solved = 0
@@ -241,6 +335,9 @@ def main(argv=None) -> int:
     B.profile_enable(False)
     prof = B.profile_read()
     dt = t1 - t0
+    free_b, total_b = torch.cuda.mem_get_info()
+    memory = {"torch_peak_allocated_GB": torch.cuda.max_memory_allocated() / 1e9,
+              "device_used_GB_after_steps": (total_b - free_b) / 1e9, "device_total_GB": total_b / 1e9}
     sig_np = sig.cpu().numpy()
     assert np.all(np.isfinite(sig_np))
 
@@ -285,17 +382,28 @@ def main(argv=None) -> int:
         "config": {"workload": a.config, "description": cfg["desc"], "wires": int(wl.cloud.n),
                    "clouds": int(wl.cloud.n_clouds), "rhs": int(R), "unknowns": int(wl.cloud.n * 7),
                    "nnzb": int(cl.nnzb), "pairs": int(cl.n_pairs), "method": method, "restart": restart,
-                   "tol": a.tol},
+                   "tol": a.tol, "initial_guess": guess},
         "solver": {"cycles": infos[-1]["cycles"], "iterations": infos[-1]["iterations"],
                    "max_rel_residual": infos[-1]["max_rel_residual"],
                    "systems_per_step": int(wl.cloud.n_clouds * R), "solved_total": solved},
         "roofline": roof,
         "autotune": tuning,
         "kernels": kernels,
+        "memory": memory,
+        "mlp": mlp_report,
+        "guess_comparison": None,
+        "comparator": None,
         "cpu_baseline": None,
     }
+    del X, sig, cl
+    if not a.no_compare and a.config in MLP_TRAINING:
+        out["guess_comparison"] = compare_guesses(step, ["zero", "bj"] + (["mlp"] if theta is not None else []))
+    if not a.no_comparator:
+        out["comparator"] = fp64_comparator(B, geom, wl, kh, eh, a.tol, a.config)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
+    if out["comparator"]:
+        out["comparator"]["speedup_of_value"] = out["value"] / out["comparator"]["value"]
     print(json.dumps(out))
     return 0
 

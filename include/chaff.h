@@ -236,24 +236,25 @@ chaff_status chaff_rcs(chaff_cloud c, const void* X, int64_t n_rhs, const double
  * Reversing a wire reverses its rooftop order and negates the coefficients,
  * so the canonical currents are x~_{p,q} = s_p x_{p,q'}, q' = q if s_p = 1
  * else 6 - q.  With k = 2 pi/wavelength, D_p = L_p/8, beta_p = k k_hat.tau_p,
- * s_q = -L_p/2 + (q+1) D_p and sinc x = sin x / x, the 160 features of a row
+ * s_q = -L_p/2 + (q+1) D_p and sinc x = sin x / x, the 192 features of a row
  * are
  *   [0]        10 (L_p/wavelength - 1/2)
  *   [1]        n_p/16, n_p = other wires of the cloud within d_c
  *   [2+2q, 3+2q]  Re, Im of (tau_p.e) sinc^2(beta_p D_p/2) exp(-j beta_p s_q)
  *              (the excitation of eq. (4) in the canonical frame, divided by
  *              D_p, incident phase at c_p removed), q = 0..6
- *   [16+9j .. 24+9j]  for the j-th nearest other wire p' within d_c
+ *   [16+11j .. 26+11j]  for the j-th nearest other wire p' within d_c
  *              (ascending squared distance as in the near-set test, ties by
  *              caller index; j < 16), d = c_p' - c_p:
  *              |d|/d_c, tau_p.d/d_c, tau_p'.d/d_c, tau_p.tau_p',
  *              Re, Im of (tau_p'.e) exp(-j k k_hat.d),
- *              10 (L_p'/wavelength - 1/2), k_hat.tau_p', 1;  zeros if empty.
+ *              10 (L_p'/wavelength - 1/2), k_hat.tau_p',
+ *              Re, Im of exp(-j k |d|), 1;  zeros if empty.
  * Features are evaluated in FP64 and stored as BF16 bit patterns (uint16),
  * rounded FP64 -> FP32 -> BF16, each step to nearest even.
  *
- * Network: 160 -> 128 -> 128 -> 128 -> 14, SiLU after the hidden layers.
- * theta [CHAFF_MLP_NPARAM] float: W1 [160][128], b1 [128], W2 [128][128],
+ * Network: 192 -> 128 -> 128 -> 128 -> 14, SiLU after the hidden layers.
+ * theta [CHAFF_MLP_NPARAM] float: W1 [192][128], b1 [128], W2 [128][128],
  * b2, W3 [128][128], b3, W4 [128][14], b4 [14]; W[i][o] input-major.
  * Products take BF16 weights and BF16 layer inputs with FP32 accumulation;
  * biases, pre-activations and SiLU are FP32.
@@ -265,12 +266,12 @@ chaff_status chaff_rcs(chaff_cloud c, const void* X, int64_t n_rhs, const double
  * Loss: mean over rows and the 14 outputs of (y - t)^2.
  * Buffers must be 16-byte aligned.  Requires a finite d_c > 0. */
 #define CHAFF_MLP_K 16
-#define CHAFF_MLP_NFEAT 160
+#define CHAFF_MLP_NFEAT 192
 #define CHAFF_MLP_HIDDEN 128
 #define CHAFF_MLP_NOUT 14
-#define CHAFF_MLP_NPARAM 55438
+#define CHAFF_MLP_NPARAM 59534
 
-/* Features of rows [row0, row0 + n_rows) into feat [n_rows][160] (uint16 BF16). */
+/* Features of rows [row0, row0 + n_rows) into feat [n_rows][192] (uint16 BF16). */
 chaff_status chaff_mlp_features(chaff_cloud c, const double* k_hat, const double* e_hat, int64_t n_rhs,
                                 int64_t row0, int64_t n_rows, uint16_t* feat, chaff_stream stream);
 
@@ -284,7 +285,7 @@ chaff_status chaff_mlp_targets(chaff_cloud c, chaff_prec prec, const void* Pinv,
  * (train = 1) for n_rows rows. */
 size_t chaff_mlp_workspace_bytes(int64_t n_rows, int32_t train);
 
-/* Network outputs Y [n_rows][14] of feat [n_rows][160]. */
+/* Network outputs Y [n_rows][14] of feat [n_rows][192]. */
 chaff_status chaff_mlp_forward(const float* theta, const uint16_t* feat, int64_t n_rows, float* Y,
                                void* ws, size_t ws_bytes, chaff_stream stream);
 

@@ -12,14 +12,14 @@ This module is the plain definition of every step, in FP64 NumPy:
                     within d_c, ascending in (squared distance, caller index),
                     squared distance formed exactly as in the near-set test
                     of eq. (9);
-* ``features``   -- 160 rotation- and translation-invariant numbers per
+* ``features``   -- 192 rotation- and translation-invariant numbers per
                     (wire, incidence), in the wire's canonical frame;
 * ``targets`` / ``currents_from_outputs`` -- the map between solved currents
                     and the 14 network outputs: the departure of the currents
                     from the wire's isolated (block-Jacobi) response
                     b_p = Z_pp^{-1} u_p, in the canonical frame, incident
                     phase at the wire centre removed, fixed scale;
-* ``forward`` / ``loss_and_grad`` -- the 160-128-128-128-14 SiLU network,
+* ``forward`` / ``loss_and_grad`` -- the 192-128-128-128-14 SiLU network,
                     optionally with the BF16 rounding points of the GPU
                     method emulated (BF16 weights and layer inputs, exact
                     accumulation, FP32 biases);
@@ -38,11 +38,12 @@ Delta_p = L_p/8, beta_p = k (k_hat . tau_p), s_q = -L_p/2 + (q+1) Delta_p:
   own[2+2q], [3+2q] = Re, Im of (tau_p . e) sinc^2(beta_p Delta_p / 2)
                        exp(-j beta_p s_q)            (q = 0..6; sinc x = sin x/x)
 
-and for neighbour slot j (j-th nearest p', d = c_p' - c_p), at 16 + 9 j:
+and for neighbour slot j (j-th nearest p', d = c_p' - c_p), at 16 + 11 j:
 
   |d|/d_c, (tau_p . d)/d_c, (tau_p' . d)/d_c, tau_p . tau_p',
   Re, Im of (tau_p' . e) exp(-j k (k_hat . d)), 10 (L_p'/lambda - 1/2),
-  k_hat . tau_p', 1
+  k_hat . tau_p', Re, Im of exp(-j k |d|) (the retardation of the coupling
+  between the two centres), 1
   (all zero for an empty slot).
 
 Own features 2..15 are the excitation of eq. (4) in the canonical frame,
@@ -67,8 +68,8 @@ from .mom import _d2, excitation, near_pairs, self_blocks
 
 K_NB = 16
 F_OWN = 16
-F_NB = 9
-N_FEAT = F_OWN + K_NB * F_NB       # 160
+F_NB = 11
+N_FEAT = F_OWN + K_NB * F_NB       # 192
 HIDDEN = 128
 N_OUT = 14
 X_SCALE = 0.5
@@ -76,7 +77,7 @@ LAYERS = ((N_FEAT, HIDDEN), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN), (HIDDEN, N_OUT))
 
 
 # ----------------------------------------------------------------------------
-# parameters: W1 [160][128], b1 [128], W2, b2, W3, b3, W4 [128][14], b4 [14]
+# parameters: W1 [192][128], b1 [128], W2, b2, W3, b3, W4 [128][14], b4 [14]
 # (each W stored input-major: W[i][o] at offset + i*n_out + o)
 # ----------------------------------------------------------------------------
 
@@ -152,7 +153,7 @@ def _sinc(x):
 
 
 def features(cloud, k_hat: np.ndarray, e_hat: np.ndarray, nbrs=None) -> np.ndarray:
-    """F [N*R, 160] in FP64 (unrounded), row = p*R + r."""
+    """F [N*R, 192] in FP64 (unrounded), row = p*R + r."""
     k_hat = np.atleast_2d(k_hat)
     e_hat = np.atleast_2d(e_hat)
     R = k_hat.shape[0]
@@ -197,7 +198,10 @@ def features(cloud, k_hat: np.ndarray, e_hat: np.ndarray, nbrs=None) -> np.ndarr
         out[p, :, base + 5] = drive.imag
         out[p, :, base + 6] = (10.0 * (L[q] / lam - 0.5))[:, None]
         out[p, :, base + 7] = np.einsum("mrc,rc->mr", tq, k_hat)
-        out[p, :, base + 8] = 1.0
+        ret = np.exp(-1j * k * dist)
+        out[p, :, base + 8] = ret.real[:, None]
+        out[p, :, base + 9] = ret.imag[:, None]
+        out[p, :, base + 10] = 1.0
     return out.reshape(n * R, N_FEAT)
 
 

@@ -407,11 +407,11 @@ def profile_read() -> dict:
 
 # ------------------------------------------------------------------ learned initial guess
 
-MLP_NFEAT, MLP_HIDDEN, MLP_NOUT, MLP_NPARAM = 160, 128, 14, 55438
+MLP_NFEAT, MLP_HIDDEN, MLP_NOUT, MLP_NPARAM = 192, 128, 14, 59534
 
 
 def mlp_features(cl: Cloud, k_hat, e_hat, row0: int = 0, n_rows: int | None = None):
-    """BF16 feature bit patterns [n_rows, 160] (int16) of rows row0.. (row = p*R + r)."""
+    """BF16 feature bit patterns [n_rows, 192] (int16) of rows row0.. (row = p*R + r)."""
     kh = _dev_f64(_2d(k_hat), cl.device)
     eh = _dev_f64(_2d(e_hat), cl.device)
     R = kh.shape[0]
@@ -435,7 +435,7 @@ def mlp_targets(cl: Cloud, Pinv, k_hat, e_hat, X, prec: int = C64):
 
 
 def mlp_forward(theta, feat):
-    """Network outputs [rows, 14] float32 of BF16 features [rows, 160] (int16 bit patterns)."""
+    """Network outputs [rows, 14] float32 of BF16 features [rows, 192] (int16 bit patterns)."""
     rows = feat.shape[0]
     need = lib().chaff_mlp_workspace_bytes(rows, 0)
     ws = torch.empty(need, dtype=torch.uint8, device=feat.device)
@@ -445,7 +445,7 @@ def mlp_forward(theta, feat):
 
 
 def mlp_grad(theta, feat, T, idx=None, n_rows: int | None = None):
-    """(gradient [55438] float32, loss [1] float32) over rows idx (or all rows)."""
+    """(gradient [59534] float32, loss [1] float32) over rows idx (or all rows)."""
     rows = n_rows if n_rows is not None else (idx.shape[0] if idx is not None else feat.shape[0])
     need = lib().chaff_mlp_workspace_bytes(rows, 1)
     ws = torch.empty(need, dtype=torch.uint8, device=feat.device)

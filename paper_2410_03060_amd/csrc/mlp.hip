@@ -1,5 +1,5 @@
 // Learned initial guess for the Krylov solve: per-(wire, incidence) features,
-// a 160-128-128-128-14 SiLU network on BF16 matrix cores with FP32
+// a 192-128-128-128-14 SiLU network on BF16 matrix cores with FP32
 // accumulation (forward, backward, Adam), and the maps between solved
 // currents and network outputs.  Not part of the paper's method: the solver
 // still drives the true residual of the S-NFC system (eq. 9) to the same
@@ -21,7 +21,7 @@
 namespace chaff {
 namespace {
 
-constexpr int KNB = 16, FOWN = 16, FNB = 9, NF = FOWN + KNB * FNB, NH = 128, NO = 14;
+constexpr int KNB = 16, FOWN = 16, FNB = 11, NF = FOWN + KNB * FNB, NH = 128, NO = 14;
 constexpr int OW1 = 0, OB1 = OW1 + NF * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
               OB3 = OW3 + NH * NH, OW4 = OB3 + NH, OB4 = OW4 + NH * NO, NPARAM = OB4 + NO;
 static_assert(NF == CHAFF_MLP_NFEAT && NH == CHAFF_MLP_HIDDEN && NO == CHAFF_MLP_NOUT, "header sizes");
@@ -442,7 +442,11 @@ __global__ __launch_bounds__(FT_THREADS) void k_features(const Wire* __restrict_
             f[5] = d2bf(-ue * sn);
             f[6] = d2bf(10.0 * (v.len / lam - 0.5));
             f[7] = d2bf(kx * ux + ky * uy + kz * uz);
-            f[8] = d2bf(1.0);
+            const double dist = sqrt(bd2);
+            sincos(k * dist, &sn, &cs);
+            f[8] = d2bf(cs);
+            f[9] = d2bf(-sn);
+            f[10] = d2bf(1.0);
         }
     }
     __syncthreads();
@@ -608,7 +612,7 @@ chaff_status launch_pack(const float* theta, const Packed& pk, hipStream_t st) {
 
 double layer_flops(int64_t m, int k, int n) { return 2.0 * (double)m * k * n; }
 
-// Forward of rows [0, M) of feat (BF16 [*][160]) into Y [M][14]; h0/h1 ping-pong.
+// Forward of rows [0, M) of feat (BF16 [*][192]) into Y [M][14]; h0/h1 ping-pong.
 chaff_status forward_rows(const float* theta, const FwdBufs& b, const uint16_t* feat, int64_t M, float* Y,
                           hipStream_t st) {
     const int64_t Mpad = pad_rows(M, ROWS_WG);

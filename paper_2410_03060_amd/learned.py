@@ -22,7 +22,7 @@ from . import workloads as W
 
 @dataclass
 class SampleSet:
-    feat: torch.Tensor            # [rows, 160] int16 (BF16 bit patterns)
+    feat: torch.Tensor            # [rows, 192] int16 (BF16 bit patterns)
     target: torch.Tensor          # [rows, 14] float32
     clouds: int = 0
     solve_seconds: float = 0.0

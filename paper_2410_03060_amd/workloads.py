@@ -250,6 +250,17 @@ def c4_eval(n: int = 100000) -> Workload:
     return Workload("c4_eval", cloud, inc)
 
 
+def c5_train_cloud(j: int) -> Workload:
+    """Training cloud j for the learned guess at the 10^6-wire cloud's density
+    (1.91 wires per cubic wavelength) and d_c = 1 wavelength: N ~ U{5000..20000},
+    uniform sphere of radius 50 lambda (N/10^6)^(1/3), 8 random incidences."""
+    rng = np.random.default_rng(5000 + j)
+    n = int(rng.integers(5000, 20001))
+    cloud = _sphere_cloud(50000 + j, n, 50.0 * (n / 1e6) ** (1.0 / 3.0), 1.0)
+    inc = random_incidences(np.random.default_rng(51000 + j), 8)
+    return Workload(f"c5_train_{j}", cloud, inc)
+
+
 def c5(n: int = 1_000_000, n_angles: int = 64) -> Workload:
     """10^6 wires uniform in a sphere of radius 50 wavelengths, d_c = 1 wavelength."""
     radius = 50.0 * (n / 1e6) ** (1.0 / 3.0)
@@ -273,7 +284,7 @@ CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4_eval": c4_eval, "c5": c5}
 
 # --------------------------------------------------------------------------- learned guess
 
-MLP_LAYERS = ((160, 128), (128, 128), (128, 128), (128, 14))   # (inputs, outputs) per layer
+MLP_LAYERS = ((192, 128), (128, 128), (128, 128), (128, 14))   # (inputs, outputs) per layer
 
 
 def mlp_init(seed: int) -> np.ndarray:

@@ -55,7 +55,7 @@ def _theta(seed):
 
 def test_param_layout_count():
     _, n = mlp.param_layout()
-    assert n == 160 * 128 + 128 + 2 * (128 * 128 + 128) + 128 * 14 + 14
+    assert n == 192 * 128 + 128 + 2 * (128 * 128 + 128) + 128 * 14 + 14
     assert W.mlp_init(0).shape == (n,)
 
 
@@ -170,7 +170,7 @@ def test_features_invariant_under_rigid_motion_of_the_scene():
     cl2 = W.single_cloud(cl.center @ Q.T + shift, cl.tangent @ Q.T, cl.length, LAM, cl.d_c)
     F1 = mlp.features(cl2, inc.k_hat @ Q.T, inc.e_hat @ Q.T, nbrs=mlp.knn(cl))
     np.testing.assert_allclose(F1, F0, atol=1e-9)
-    assert np.count_nonzero(F0[:, 16::9]) > 0            # neighbours present
+    assert np.count_nonzero(F0[:, 16::11]) > 0           # neighbours present
 
 
 def test_features_invariant_under_tangent_reversal():
@@ -213,11 +213,13 @@ def test_neighbour_drive_features_match_the_neighbours_excitation():
                 beta = K * (cl.tangent[q] @ inc.k_hat[r])
                 env = D[q] * np.sinc(beta * D[q] / (2 * math.pi)) ** 2
                 want = s[q, r] * u[q, 3, r] / env * np.exp(1j * K * (cl.center[p] @ inc.k_hat[r]))
-                b = 16 + 9 * j
+                b = 16 + 11 * j
                 assert abs(F[p, r, b + 4] + 1j * F[p, r, b + 5] - want) < 1e-11
                 d = cl.center[q] - cl.center[p]
                 assert abs(F[p, r, b] - np.linalg.norm(d) / cl.d_c) < 1e-14
-                assert F[p, r, b + 8] == 1.0
+                assert F[p, r, b + 10] == 1.0
+                kd = K * np.linalg.norm(d)
+                assert abs(F[p, r, b + 8] + 1j * F[p, r, b + 9] - np.exp(-1j * kd)) < 1e-12
                 checked += 1
     assert checked > 50
 
@@ -279,12 +281,13 @@ def test_neighbour_features_swap_consistently_between_the_two_wires_of_a_pair():
             if q < 0 or p not in list(nbr[q]):
                 continue
             jq = list(nbr[q]).index(p)
-            a = F[p, :, 16 + 9 * j:16 + 9 * j + 9]
-            b = F[q, :, 16 + 9 * jq:16 + 9 * jq + 9]
+            a = F[p, :, 16 + 11 * j:16 + 11 * j + 11]
+            b = F[q, :, 16 + 11 * jq:16 + 11 * jq + 11]
             np.testing.assert_allclose(b[:, 0], a[:, 0], atol=1e-15)
             np.testing.assert_allclose(b[:, 1], -a[:, 2], atol=1e-13)
             np.testing.assert_allclose(b[:, 2], -a[:, 1], atol=1e-13)
             np.testing.assert_allclose(b[:, 3], a[:, 3], atol=1e-15)
+            np.testing.assert_allclose(b[:, 8:11], a[:, 8:11], atol=1e-15)
             np.testing.assert_allclose(a[:, 6], F[q, :, 0], atol=1e-13)
             np.testing.assert_allclose(b[:, 6], F[p, :, 0], atol=1e-13)
             # k_hat . tau_q from the phase slope of q's own drive features
@@ -310,16 +313,19 @@ def test_features_of_a_hand_built_three_wire_scene():
     # broadside incidence: no phase along A, drive (tau.e) sinc^2(0) = 1 on every rooftop
     np.testing.assert_allclose(a[2:16:2], 1.0, atol=1e-15)
     np.testing.assert_allclose(a[3:16:2], 0.0, atol=1e-15)
+    # retardation exp(-j 2 pi |d|/lambda): 0.3 lambda -> angle -108 deg, 0.5 lambda -> -1
+    c3, s3 = math.cos(0.6 * math.pi), -math.sin(0.6 * math.pi)
     # nearest: C (0.3 lambda), canonical tangent +x (its raw -x is flipped)
-    np.testing.assert_allclose(a[16:25], [0.3, 0.3, 0.3, 1.0, 1.0, 0.0, 0.5, 0.0, 1.0], atol=1e-14)
+    np.testing.assert_allclose(a[16:27], [0.3, 0.3, 0.3, 1.0, 1.0, 0.0, 0.5, 0.0, c3, s3, 1.0], atol=1e-14)
     # then B (0.5 lambda), tangent y: perpendicular and undriven
-    np.testing.assert_allclose(a[25:34], [0.5, 0.0, 0.5, 0.0, 0.0, 0.0, -0.5, 0.0, 1.0], atol=1e-14)
-    assert np.all(a[34:] == 0.0)
+    np.testing.assert_allclose(a[27:38], [0.5, 0.0, 0.5, 0.0, 0.0, 0.0, -0.5, 0.0, -1.0, 0.0, 1.0], atol=1e-14)
+    assert np.all(a[38:] == 0.0)
     b = F[1]      # B sees A (0.5) then C (sqrt(0.34)); B itself is undriven
     assert abs(b[0] - (-0.5)) < 1e-14 and np.all(np.abs(b[2:16]) < 1e-15)
     d = math.sqrt(0.34)
-    np.testing.assert_allclose(b[16:25], [0.5, -0.5, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0], atol=1e-14)
-    np.testing.assert_allclose(b[25:34], [d, -0.5, 0.3, 0.0, 1.0, 0.0, 0.5, 0.0, 1.0], atol=1e-14)
+    cd, sd = math.cos(2 * math.pi * d), -math.sin(2 * math.pi * d)
+    np.testing.assert_allclose(b[16:27], [0.5, -0.5, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, -1.0, 0.0, 1.0], atol=1e-14)
+    np.testing.assert_allclose(b[27:38], [d, -0.5, 0.3, 0.0, 1.0, 0.0, 0.5, 0.0, cd, sd, 1.0], atol=1e-14)
 
 
 def test_targets_vanish_for_uncoupled_wires():
