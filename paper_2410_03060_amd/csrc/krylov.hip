@@ -641,16 +641,40 @@ __global__ void k_cg_alpha(int64_t nsys, const c128* __restrict__ pq, CgState* _
     cg[t] = S;
 }
 
-// x64 += scale(system) * xc
+// x64[:, colmap[c]] += scale(system) * xc[:, c] for the s_cur current columns,
+// then xc = 0 (the correction restarts from zero).
 template <typename C>
-__global__ void k_add_scaled(const int32_t* __restrict__ wire_cloud, const double* __restrict__ scale, int64_t n_rows,
-                             int64_t s, const C* __restrict__ xc, c128* __restrict__ x) {
+__global__ void k_add_scaled(const int32_t* __restrict__ wire_cloud, const double* __restrict__ scale,
+                             const int32_t* __restrict__ colmap, int64_t n_rows, int64_t s_cur, int64_t s_full,
+                             C* __restrict__ xc, c128* __restrict__ x) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_rows * s) return;
-    const int64_t row = t / s, rr = t - (t / s) * s;
-    const double f = scale[(int64_t)wire_cloud[row / NB] * s + rr];
+    if (t >= n_rows * s_cur) return;
+    const int64_t row = t / s_cur, rr = t - (t / s_cur) * s_cur;
+    const int64_t col = colmap[rr];
+    const double f = scale[(int64_t)wire_cloud[row / NB] * s_full + col];
     const c128 v = ccast<c128>(xc[t]);
-    x[t] = c128{x[t].re + f * v.re, x[t].im + f * v.im};
+    c128& xo = x[row * s_full + col];
+    xo = c128{xo.re + f * v.re, xo.im + f * v.im};
+    xc[t] = C{0, 0};
+}
+
+// dst[row][j] = src[row][keep[j]] (column compaction of a row-major [rows][s] block)
+template <typename C>
+__global__ void k_gather_cols(const C* __restrict__ src, int64_t n_rows, int64_t s_src,
+                              const int32_t* __restrict__ keep, int64_t s_dst, C* __restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s_dst) return;
+    const int64_t row = t / s_dst, j = t - (t / s_dst) * s_dst;
+    dst[t] = src[row * s_src + keep[j]];
+}
+
+template <typename T>
+__global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_src, const int32_t* __restrict__ keep,
+                             int64_t s_dst, T* __restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_clouds * s_dst) return;
+    const int64_t cl = t / s_dst, j = t - (t / s_dst) * s_dst;
+    dst[t] = src[cl * s_src + keep[j]];
 }
 
 // Fused COCG kernels (chunk-structured so that the bilinear forms reduce per
@@ -795,7 +819,7 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
 // mode 1: ordinary step; mode 2: step right after a residual replacement
 // (rho_prev is kept as the denominator).
 __global__ void k_cg_step(int64_t nsys, const c128* __restrict__ rz, const c128* __restrict__ rr, int mode,
-                          CgState* __restrict__ cg, int32_t* __restrict__ n_active) {
+                          CgState* __restrict__ cg, int32_t* __restrict__ n_active, int32_t* __restrict__ flags) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nsys) return;
     CgState S = cg[t];
@@ -822,7 +846,9 @@ __global__ void k_cg_step(int64_t nsys, const c128* __restrict__ rz, const c128*
     S.rho = rho_new.re;
     S.rho_im = rho_new.im;
     cg[t] = S;
-    if (!S.done && rn > S.ckpt) atomicAdd(n_active, 1);
+    const int above = (!S.done && rn > S.ckpt) ? 1 : 0;
+    flags[t] = above;
+    if (above) atomicAdd(n_active, 1);
 }
 
 // start of a cycle: targets, checkpoint, alpha = 0 (the update kernel then only forms z)
@@ -841,6 +867,7 @@ __global__ void k_cg_cycle_start(int64_t nsys, const double* __restrict__ target
 // ------------------------------------------------------------------ host driver
 
 // CHAFF_VERBOSE=1 in the environment prints one line per refinement cycle
+// (and the COCG progress every 50 steps)
 static const bool g_verbose = [] {
     const char* v = std::getenv("CHAFF_VERBOSE");
     return v && v[0] == '1';
@@ -872,6 +899,13 @@ struct SolveLayout {
     int32_t* cloud_group_off;  // [n_clouds+1] group ranges of the clouds
     c128* tpart;               // [n_tiles][s]
     c128* gpart;               // [n_groups][s]
+    // COCG column compaction: tile set of the narrower width, column maps
+    Chunk* ctiles;
+    int32_t* cgroup_tile_off;
+    int32_t* ccloud_group_off;
+    int32_t* colmap;           // [s] current column -> caller RHS column
+    int32_t* keep;             // [s] kept columns of a compaction
+    CgState* cg2;              // [nsys] staging of the compacted states
 };
 
 // Wires per reduction chunk (about 2048 chunks in total): streaming kernels
@@ -967,6 +1001,13 @@ static SolveLayout carve_solve(void* ws, size_t ws_bytes, const SolveShape& sh) 
     L.cloud_group_off = cv.take<int32_t>((size_t)sh.n_clouds + 1);
     L.tpart = cv.take<c128>((size_t)std::max<int64_t>(sh.n_tiles, 1) * sh.s);
     L.gpart = cv.take<c128>((size_t)std::max(sh.n_groups, 1) * sh.s);
+    // a narrower RHS tile means wider (never more) tiles and groups
+    L.ctiles = cv.take<Chunk>((size_t)std::max<int64_t>(sh.n_tiles, 1));
+    L.cgroup_tile_off = cv.take<int32_t>((size_t)sh.n_groups + 1);
+    L.ccloud_group_off = cv.take<int32_t>((size_t)sh.n_clouds + 1);
+    L.colmap = cv.take<int32_t>((size_t)sh.s);
+    L.keep = cv.take<int32_t>((size_t)sh.s);
+    L.cg2 = cv.take<CgState>((size_t)sh.nsys);
     L.bytes = cv.off + 256;
     return L;
 }
@@ -975,6 +1016,25 @@ size_t solve_workspace_bytes(const Cloud* c, const chaff_solve_opts* o, int64_t 
     const int m = o->restart;
     SolveShape sh = solve_shape(c, m, s, (chaff_prec)o->prec, o->method);
     return carve_solve(nullptr, 0, sh).bytes;
+}
+
+// COCG product tiles of tile_w wires (cloud-aligned) and their groups of
+// TILE_GROUP tiles (cloud-aligned): tl, group -> first tile (gto, + end),
+// cloud -> first group (cgo, + end).
+static void build_tiles(const Cloud* c, int64_t tile_w, std::vector<Chunk>& tl, std::vector<int32_t>& gto,
+                        std::vector<int32_t>& cgo) {
+    tl.clear();
+    gto.clear();
+    cgo.assign(c->n_clouds + 1, 0);
+    for (int k = 0; k < c->n_clouds; ++k) {
+        cgo[k] = (int32_t)gto.size();
+        const int64_t t0 = (int64_t)tl.size();
+        for (int64_t w0 = c->cloud_off[k]; w0 < c->cloud_off[k + 1]; w0 += tile_w)
+            tl.push_back(Chunk{w0, std::min<int64_t>(w0 + tile_w, c->cloud_off[k + 1]), k, 0});
+        for (int64_t g = t0; g < (int64_t)tl.size(); g += TILE_GROUP) gto.push_back((int32_t)g);
+    }
+    cgo[c->n_clouds] = (int32_t)gto.size();
+    gto.push_back((int32_t)tl.size());
 }
 
 // per-system squared norms of an FP64 block into host vector (sync)
@@ -1018,20 +1078,85 @@ static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& 
 // updates"): no Krylov information is thrown away at a refinement checkpoint.
 // The cycle ends once every active system's recursive residual fell below its
 // checkpoint (or its final target); then x += scale * (accumulated correction).
+// Column compaction inside a COCG cycle: once at most half of the current
+// RHS tile width still has a system above its checkpoint, the finished
+// columns are dropped -- their accumulated corrections are flushed into the
+// FP64 solution, the live columns of r, z, p and their recurrence states are
+// packed into a narrower row-major block, and the product switches to the
+// matching tile width.  Systems below their checkpoint would only keep
+// improving, so dropping them does not change what the cycle guarantees.
+template <typename C>
+static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc, const SolveLayout& L,
+                                 std::vector<int32_t>& colmap, const std::vector<int32_t>& keep, int64_t s_full,
+                                 C* xc, C* r, C* z, C* p, C* q, hipStream_t st) {
+    const int64_t rows = cs.rows, s_old = cs.s, s_new = (int64_t)keep.size();
+    ProfScope ps("cocg_compact", st, (double)rows * s_old * sizeof(C) * 2 + 3.0 * rows * s_new * sizeof(C) * 3);
+    hipLaunchKernelGGL((k_add_scaled<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
+                       (const int32_t*)c->wire_cloud, (const double*)L.rn, (const int32_t*)L.colmap, rows, s_old,
+                       s_full, xc, L.x);
+    CHAFF_LAUNCH_CHECK();
+    CHAFF_HIP(hipMemcpyAsync(L.keep, keep.data(), s_new * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    for (C* v : {r, z, p}) {
+        hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)v, rows,
+                           s_old, (const int32_t*)L.keep, s_new, q);
+        CHAFF_LAUNCH_CHECK();
+        CHAFF_HIP(hipMemcpyAsync(v, q, (size_t)rows * s_new * sizeof(C), hipMemcpyDeviceToDevice, st));
+    }
+    hipLaunchKernelGGL((k_gather_sys<CgState>), dim3(blocks_for((int64_t)cs.n_clouds * s_new, 64)), dim3(64), 0, st,
+                       (const CgState*)L.cg, cs.n_clouds, s_old, (const int32_t*)L.keep, s_new, L.cg2);
+    CHAFF_LAUNCH_CHECK();
+    CHAFF_HIP(hipMemcpyAsync(L.cg, L.cg2, (size_t)cs.n_clouds * s_new * sizeof(CgState), hipMemcpyDeviceToDevice, st));
+    std::vector<int32_t> cm(s_new);
+    for (int64_t j = 0; j < s_new; ++j) cm[j] = colmap[keep[j]];
+    colmap = cm;
+    CHAFF_HIP(hipMemcpyAsync(L.colmap, colmap.data(), s_new * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    cs.s = s_new;
+    cs.nsys = (int64_t)cs.n_clouds * s_new;
+    cs.cocg_st = spmm_tile_width(s_new);
+    cs.tile_w = 256 / cs.cocg_st;
+    std::vector<Chunk> tl;
+    std::vector<int32_t> gto, cgo;
+    build_tiles(c, cs.tile_w, tl, gto, cgo);
+    cs.n_tiles = (int64_t)tl.size();
+    cs.n_groups = (int)gto.size() - 1;
+    if (!tl.empty())
+        CHAFF_HIP(hipMemcpyAsync(L.ctiles, tl.data(), tl.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
+    CHAFF_HIP(hipMemcpyAsync(L.cgroup_tile_off, gto.data(), gto.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    CHAFF_HIP(hipMemcpyAsync(L.ccloud_group_off, cgo.data(), cgo.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             st));
+    Lc.tiles = L.ctiles;
+    Lc.group_tile_off = L.cgroup_tile_off;
+    Lc.cloud_group_off = L.ccloud_group_off;
+    CHAFF_HIP(hipStreamSynchronize(st));   // host staging vectors leave scope
+    return CHAFF_OK;
+}
+
+// One COCG refinement cycle.  L.r holds the FP64 true residual; it replaces the
+// recursive residual (in units of the run's fixed per-system scale).  With
+// CHAFF_COCG the recurrence restarts from it; with CHAFF_COCG_RR the search
+// direction p and r^T z carry over from the previous cycle ("reliable
+// updates").  The cycle ends once every active system's recursive residual
+// fell below its checkpoint (or its final target); then x += scale *
+// (accumulated correction).
 template <typename C, typename CZ>
 static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveShape& sh, SolveLayout& L,
                                const CZ* Z, const CZ* Pinv, const std::vector<double>& target,
                                const std::vector<double>& ckpt, const std::vector<int32_t>& act, bool first,
                                int& iters, hipStream_t st) {
     const int64_t rows = sh.rows, s = sh.s, vs = rows * s, nsys = sh.nsys;
-    C* V = static_cast<C*>(L.V);   // [x_c | r | z | p | q]
+    C* V = static_cast<C*>(L.V);   // [x_c | r | z | p | q], each with room for [rows][s]
     C* xc = V;
     C* r = V + vs;
     C* z = V + 2 * vs;
     C* p = V + 3 * vs;
     C* q = V + 4 * vs;
-    const int wst = spmm_tile_width(s);
     const bool use_rr = o->method == CHAFF_COCG_RR;
+    const bool compact = !use_rr && s > 1;
+    SolveShape cs = sh;            // current shape (columns shrink under compaction)
+    SolveLayout Lc = L;            // current tile set
+    std::vector<int32_t> colmap(s);
+    for (int64_t j = 0; j < s; ++j) colmap[j] = (int32_t)j;
+    CHAFF_HIP(hipMemcpyAsync(L.colmap, colmap.data(), s * sizeof(int32_t), hipMemcpyHostToDevice, st));
     CHAFF_HIP(hipMemcpyAsync(L.target, target.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
     CHAFF_HIP(hipMemcpyAsync(L.h2, ckpt.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
     CHAFF_HIP(hipMemcpyAsync(L.active, act.data(), nsys * sizeof(int32_t), hipMemcpyHostToDevice, st));
@@ -1050,65 +1175,91 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     }
     CHAFF_HIP(hipStreamSynchronize(st));   // host staging vectors may leave scope
     int mode = (first || !use_rr) ? 0 : 2;
+    int32_t last_checked = -1;
+    std::vector<int32_t> flags;
     for (int k = 0; k <= o->restart; ++k) {
+        const int wst = spmm_tile_width(cs.s);
         {   // x += alpha p, r -= alpha q, z = P r, r^T z, ||r||^2 (alpha = 0 on entry)
-            ProfScope pu("k_cg_update", st, (7.0 * vs + 0.0) * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
+            ProfScope pu("k_cg_update", st, (7.0 * rows * cs.s) * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
             const C* pc = p;
             switch (wst) {
-                case 1: launch_cg_update<CZ, C, 1>(sh, L, Pinv, V, pc, vs, st); break;
-                case 2: launch_cg_update<CZ, C, 2>(sh, L, Pinv, V, pc, vs, st); break;
-                case 4: launch_cg_update<CZ, C, 4>(sh, L, Pinv, V, pc, vs, st); break;
-                case 8: launch_cg_update<CZ, C, 8>(sh, L, Pinv, V, pc, vs, st); break;
-                case 16: launch_cg_update<CZ, C, 16>(sh, L, Pinv, V, pc, vs, st); break;
-                case 32: launch_cg_update<CZ, C, 32>(sh, L, Pinv, V, pc, vs, st); break;
-                default: launch_cg_update<CZ, C, 64>(sh, L, Pinv, V, pc, vs, st); break;
+                case 1: launch_cg_update<CZ, C, 1>(cs, Lc, Pinv, V, pc, vs, st); break;
+                case 2: launch_cg_update<CZ, C, 2>(cs, Lc, Pinv, V, pc, vs, st); break;
+                case 4: launch_cg_update<CZ, C, 4>(cs, Lc, Pinv, V, pc, vs, st); break;
+                case 8: launch_cg_update<CZ, C, 8>(cs, Lc, Pinv, V, pc, vs, st); break;
+                case 16: launch_cg_update<CZ, C, 16>(cs, Lc, Pinv, V, pc, vs, st); break;
+                case 32: launch_cg_update<CZ, C, 32>(cs, Lc, Pinv, V, pc, vs, st); break;
+                default: launch_cg_update<CZ, C, 64>(cs, Lc, Pinv, V, pc, vs, st); break;
             }
         }
         CHAFF_LAUNCH_CHECK();
-        chunk_sum((const c128*)L.part,
-                           (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, 2, s, L.h1, st);
+        chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, cs.n_clouds, cs.nslot, 0, 2, cs.s, L.h1,
+                  st);
         CHAFF_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)L.counter, (int64_t)1);
         CHAFF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_cg_step, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const c128*)L.h1,
-                           (const c128*)(L.h1 + nsys), mode, L.cg, L.counter);
+        hipLaunchKernelGGL(k_cg_step, dim3(blocks_for(cs.nsys, 64)), dim3(64), 0, st, cs.nsys, (const c128*)L.h1,
+                           (const c128*)(L.h1 + cs.nsys), mode, L.cg, L.counter, L.active);
         CHAFF_LAUNCH_CHECK();
         int32_t n_act = 0;
         CHAFF_HIP(hipMemcpyAsync(&n_act, L.counter, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         CHAFF_HIP(hipStreamSynchronize(st));
+        if (g_verbose && k % 50 == 0)
+            std::fprintf(stderr, "[chaff] cocg step %d: %d of %lld systems above their checkpoint (%lld columns)\n",
+                         k, n_act, (long long)cs.nsys, (long long)cs.s);
         if (n_act == 0 || k == o->restart) break;
+        if (compact && cs.s > 1 && n_act != last_checked && n_act <= (int64_t)cs.n_clouds * (wst / 2)) {
+            last_checked = n_act;
+            flags.resize(cs.nsys);
+            CHAFF_HIP(hipMemcpyAsync(flags.data(), L.active, cs.nsys * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            CHAFF_HIP(hipStreamSynchronize(st));
+            std::vector<int32_t> keep;
+            for (int64_t j = 0; j < cs.s; ++j) {
+                bool live = false;
+                for (int cl = 0; cl < cs.n_clouds && !live; ++cl) live = flags[(int64_t)cl * cs.s + j] != 0;
+                if (live) keep.push_back((int32_t)j);
+            }
+            if (!keep.empty() && (int64_t)keep.size() <= wst / 2) {
+                chaff_status cst = cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, z, p, q, st);
+                if (cst != CHAFF_OK) return cst;
+                if (g_verbose)
+                    std::fprintf(stderr, "[chaff] cocg step %d: compacted to %lld columns\n", k, (long long)cs.s);
+            }
+        }
         mode = 1;
         ++iters;
         {
-            ProfScope pp("k_cg_p", st, 3.0 * vs * sizeof(C));
-            hipLaunchKernelGGL((k_cg_p<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const int32_t*)c->wire_cloud,
-                               (const CgState*)L.cg, rows, s, (const C*)z, p);
+            ProfScope pp("k_cg_p", st, 3.0 * rows * cs.s * sizeof(C));
+            hipLaunchKernelGGL((k_cg_p<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
+                               (const int32_t*)c->wire_cloud, (const CgState*)L.cg, rows, cs.s, (const C*)z, p);
         }
         CHAFF_LAUNCH_CHECK();
         {   // q = Z p with per-tile p^T q
             ProfScope ps("spmm", st, ((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 8.0 * (c->n + 1) +
-                                         3.0 * vs * sizeof(C));
-            switch (sh.cocg_st) {
-                case 1: launch_cocg_spmm<CZ, C, 1>(c, sh, L, Z, p, q, st); break;
-                case 2: launch_cocg_spmm<CZ, C, 2>(c, sh, L, Z, p, q, st); break;
-                case 4: launch_cocg_spmm<CZ, C, 4>(c, sh, L, Z, p, q, st); break;
-                case 8: launch_cocg_spmm<CZ, C, 8>(c, sh, L, Z, p, q, st); break;
-                case 16: launch_cocg_spmm<CZ, C, 16>(c, sh, L, Z, p, q, st); break;
-                case 32: launch_cocg_spmm<CZ, C, 32>(c, sh, L, Z, p, q, st); break;
-                default: launch_cocg_spmm<CZ, C, 64>(c, sh, L, Z, p, q, st); break;
+                                         3.0 * rows * cs.s * sizeof(C));
+            switch (cs.cocg_st) {
+                case 1: launch_cocg_spmm<CZ, C, 1>(c, cs, Lc, Z, p, q, st); break;
+                case 2: launch_cocg_spmm<CZ, C, 2>(c, cs, Lc, Z, p, q, st); break;
+                case 4: launch_cocg_spmm<CZ, C, 4>(c, cs, Lc, Z, p, q, st); break;
+                case 8: launch_cocg_spmm<CZ, C, 8>(c, cs, Lc, Z, p, q, st); break;
+                case 16: launch_cocg_spmm<CZ, C, 16>(c, cs, Lc, Z, p, q, st); break;
+                case 32: launch_cocg_spmm<CZ, C, 32>(c, cs, Lc, Z, p, q, st); break;
+                default: launch_cocg_spmm<CZ, C, 64>(c, cs, Lc, Z, p, q, st); break;
             }
         }
         CHAFF_LAUNCH_CHECK();
         // sigma: tiles -> groups -> clouds, fixed order
-        group_sum(L.tpart, s, 0, 0, 1, L.group_tile_off, sh.n_groups, s, L.gpart, st);
+        group_sum(L.tpart, cs.s, 0, 0, 1, Lc.group_tile_off, cs.n_groups, cs.s, L.gpart, st);
         CHAFF_LAUNCH_CHECK();
-        group_sum(L.gpart, s, 0, 0, 1, L.cloud_group_off, sh.n_clouds, s, L.nrm, st);
+        group_sum(L.gpart, cs.s, 0, 0, 1, Lc.cloud_group_off, cs.n_clouds, cs.s, L.nrm, st);
         CHAFF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_cg_alpha, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const c128*)L.nrm, L.cg);
+        hipLaunchKernelGGL(k_cg_alpha, dim3(blocks_for(cs.nsys, 64)), dim3(64), 0, st, cs.nsys, (const c128*)L.nrm,
+                           L.cg);
         CHAFF_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL((k_add_scaled<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const int32_t*)c->wire_cloud,
-                       (const double*)L.rn, rows, s, (const C*)xc, L.x);
+    hipLaunchKernelGGL((k_add_scaled<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
+                       (const int32_t*)c->wire_cloud, (const double*)L.rn, (const int32_t*)L.colmap, rows, cs.s, s,
+                       xc, L.x);
     CHAFF_LAUNCH_CHECK();
     return CHAFF_OK;
 }
@@ -1149,15 +1300,7 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         std::vector<Chunk> tl;
         std::vector<int32_t> gto, cgo(sh.n_clouds + 1, 0);
         if (sh.method != CHAFF_GMRES) {
-            for (int k = 0; k < sh.n_clouds; ++k) {
-                cgo[k] = (int32_t)gto.size();
-                const int64_t t0 = (int64_t)tl.size();
-                for (int64_t w0 = c->cloud_off[k]; w0 < c->cloud_off[k + 1]; w0 += sh.tile_w)
-                    tl.push_back(Chunk{w0, std::min<int64_t>(w0 + sh.tile_w, c->cloud_off[k + 1]), k, 0});
-                for (int64_t g = t0; g < (int64_t)tl.size(); g += TILE_GROUP) gto.push_back((int32_t)g);
-            }
-            cgo[sh.n_clouds] = (int32_t)gto.size();
-            gto.push_back((int32_t)tl.size());
+            build_tiles(c, sh.tile_w, tl, gto, cgo);
             if (!tl.empty())
                 CHAFF_HIP(hipMemcpyAsync(L.tiles, tl.data(), tl.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
             CHAFF_HIP(hipMemcpyAsync(L.group_tile_off, gto.data(), gto.size() * sizeof(int32_t),

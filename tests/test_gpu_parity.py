@@ -309,3 +309,33 @@ def test_autotune_records_and_uses_the_fastest_variant(B):
     # a solve on the tuned table still meets the bar
     X2, info = B.solve(cl, *B.fill_Z(cl, B.C64), wl.inc.k_hat, wl.inc.e_hat, B.solve_opts(tol=1e-6))
     assert info["max_rel_residual"] <= 1e-6
+
+
+@pytest.mark.parametrize("n_clouds", [1, 2])
+def test_cocg_column_compaction(B, n_clouds):
+    """Incidences that converge at different speeds: once few columns are left
+    above their checkpoint the COCG cycle packs them into a narrower block;
+    every column must still reach the oracle's solution."""
+    parts = [W.random_cloud(12, 1500, box_lam=10.0, d_c_lam=1.5)]
+    if n_clouds == 2:
+        parts.append(W.random_cloud(14, 600, box_lam=6.0, d_c_lam=1.5))
+    cloud = W.concat_clouds(parts) if n_clouds > 1 else parts[0]
+    inc = W.random_incidences(np.random.default_rng(13), 24)
+    say(f"[solve] COCG column compaction: N={cloud.n} clouds={n_clouds} R=24")
+    cl = B.build_cloud(cloud)
+    Z, P = B.fill_Z(cl, B.C64)
+    B.profile_enable(True)
+    X, info = B.solve(cl, Z, P, inc.k_hat, inc.e_hat,
+                      B.solve_opts(tol=1e-6, method=B.COCG, restart=500, inner_tol=1e-3))
+    B.profile_enable(False)
+    prof = B.profile_read()
+    say(f"  cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e} "
+        f"compactions {prof.get('cocg_compact', {}).get('launches', 0)}")
+    assert "cocg_compact" in prof
+    assert np.all(info["rel_res"] <= 1e-6)
+    Zs, _ = mom.snfc_matrix(cloud)
+    u = mom.excitation(cloud, inc.k_hat, inc.e_hat)
+    xo = osolve.sparse_solve(Zs, u)
+    e = current_err(_to_np(X), xo)
+    say(f"  current err {e.max():.3e}")
+    assert e.max() <= 1e-4
