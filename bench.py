@@ -159,6 +159,24 @@ def cpu_baseline(wl, n_sample: int = 2000, r_sample: int = 8):
                       f"by the wire ratio {scale:.1f}; full workload estimated at {t_full:.1f} s"}
 
 
+def fill_summary(prof):
+    """Fill rate in the timed steps: algorithmic flop (24 per Green sample) over kernel time."""
+    out = {}
+    tot_w = tot_ms = 0.0
+    for name in ("fill_mutual", "fill_self"):
+        k = prof.get(name)
+        if not k or k["total_ms"] <= 0:
+            continue
+        tf = k["work"] / (k["total_ms"] * 1e-3) / 1e12
+        out[name] = {"TFLOP/s": tf, "frac": tf / FP32_PEAK_TFLOPS, "ms_per_launch": k["total_ms"] / k["launches"]}
+        tot_w += k["work"]
+        tot_ms += k["total_ms"]
+    if tot_ms > 0:
+        tf = tot_w / (tot_ms * 1e-3) / 1e12
+        out["combined"] = {"TFLOP/s": tf, "frac": tf / FP32_PEAK_TFLOPS, "GFLOP/s": tf * 1e3}
+    return out
+
+
 def train_guess(config, B):
     """Train the learned guess for this workload on clouds solved by the library (untimed)."""
     import numpy as np
@@ -180,6 +198,29 @@ def train_guess(config, B):
               "excluded_from_timing": True}
     del samples
     return res.theta, report
+
+
+def spmm_sweep(B, geom, prec, sizes=(1, 4, 8, 16, 32, 64)):
+    """Block-sparse product alone (chaff_spmm, autotuned per RHS count) on the
+    workload's matrix: algorithmic bytes (Z once with its indices, X and Y
+    once) over the best variant's time, against 8 TB/s; and flop rate."""
+    cl = B.build_cloud(geom)
+    Z, _ = B.fill_Z(cl, prec, with_pinv=False)
+    zsz = 8 if prec == B.C64 else 16
+    out = {}
+    for s_ in sizes:
+        best, ms = B.autotune(cl, Z, s_, prec)
+        byt = (zsz * 49 + 4.0) * cl.nnzb + 8.0 * (cl.n + 1) + 2.0 * zsz * 7 * cl.n * s_
+        fl = 8.0 * 49 * cl.nnzb * s_
+        row = [e for e in B.tune_report() if e["n"] == cl.n and e["nnzb"] == cl.nnzb and e["s"] == s_]
+        out[f"s={s_}"] = {"variant": best, "ms": ms, "GB/s": byt / (ms * 1e-3) / 1e9,
+                          "variant_ms": row[0]["ms"] if row else None,
+                          "frac_hbm": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "TFLOP/s": fl / (ms * 1e-3) / 1e12}
+        print(f"[bench] spmm s={s_}: variant {best} {ms:.3f} ms {out[f's={s_}']['GB/s']:.0f} GB/s",
+              file=sys.stderr, flush=True)
+    del Z, cl
+    return out
 
 
 def compare_guesses(step, kinds):
@@ -250,6 +291,7 @@ def main(argv=None) -> int:
                     help="initial guess: zero, bj (block-Jacobi) or mlp (learned; trained before timing)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the untimed zero / block-Jacobi / learned guess comparison")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the product sweep over RHS counts")
     ap.add_argument("--no-comparator", action="store_true",
                     help="skip the plain FP64 one-RHS-at-a-time solver comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -389,6 +431,8 @@ def main(argv=None) -> int:
         "roofline": roof,
         "autotune": tuning,
         "kernels": kernels,
+        "fill": fill_summary(prof),
+        "spmm_sweep": None,
         "memory": memory,
         "mlp": mlp_report,
         "guess_comparison": None,
@@ -396,6 +440,8 @@ def main(argv=None) -> int:
         "cpu_baseline": None,
     }
     del X, sig, cl
+    if not a.no_sweep:
+        out["spmm_sweep"] = spmm_sweep(B, geom, prec)
     if not a.no_compare and a.config in MLP_TRAINING:
         out["guess_comparison"] = compare_guesses(step, ["zero", "bj"] + (["mlp"] if theta is not None else []))
     if not a.no_comparator:

@@ -150,7 +150,7 @@ typedef struct {
     int32_t use_x0;           /* 0: x0 = 0; 1: X holds an initial guess on entry;
                                  2: block-Jacobi guess x0 = Pinv u */
     int32_t prec;             /* chaff_prec of Z, Pinv and the Krylov vectors */
-    int32_t spmm_variant;     /* -1: tuned (chaff_autotune) or default choice; else variant 0..4 */
+    int32_t spmm_variant;     /* -1: tuned (chaff_autotune) or default choice; else variant 0..7 */
     int32_t method;           /* chaff_method */
 } chaff_solve_opts;
 
@@ -197,7 +197,9 @@ chaff_status chaff_spmm(chaff_cloud c, chaff_prec prec, const void* Z, const voi
 /* ------------------------------------------------------------------ autotuning
  * chaff_autotune times every block-sparse product variant (0: one output row
  * per lane; 1: RHS tile per wave; 2: half-width tile; 3: tile in XCD-aware
- * workgroup order; 4: XCD-aware half-width tile) for this cloud, precision
+ * workgroup order; 4: XCD-aware half-width tile; 5: one lane per output row
+ * accumulating up to 16 RHS columns, every Z row loaded once; 6: one wave per
+ * block row, the block staged in LDS; 7: 6 in XCD-aware order) for this cloud, precision
  * and RHS count on the caller's Z and two [N*7][s] buffers (contents of Y are
  * overwritten, X is read), and records the fastest in a process-wide table
  * keyed by (N, nnzb, s, prec).  Every later call with variant -1 (chaff_spmm,

@@ -320,7 +320,7 @@ static chaff_status check_opts(const chaff_solve_opts* o) {
     if (o->max_cycles < 1) return fail(CHAFF_EINVAL, "max_cycles must be >= 1");
     if (o->use_x0 < 0 || o->use_x0 > 2) return fail(CHAFF_EINVAL, "use_x0 must be 0, 1 or 2");
     if (o->prec != CHAFF_C64 && o->prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
-    if (o->spmm_variant < -1 || o->spmm_variant > 4) return fail(CHAFF_EINVAL, "spmm_variant must be in [-1, 4]");
+    if (o->spmm_variant < -1 || o->spmm_variant > 7) return fail(CHAFF_EINVAL, "spmm_variant must be in [-1, 7]");
     if (o->method != CHAFF_GMRES && o->method != CHAFF_COCG && o->method != CHAFF_COCG_RR)
         return fail(CHAFF_EINVAL, "method must be CHAFF_GMRES, CHAFF_COCG or CHAFF_COCG_RR");
     if (o->method != CHAFF_GMRES && o->restart > 1000000) return fail(CHAFF_EINVAL, "restart too large");
@@ -363,7 +363,7 @@ chaff_status chaff_spmm(chaff_cloud h, chaff_prec prec, const void* Z, const voi
     if (!h || !Z || !X || !Y) return fail(CHAFF_EINVAL, "NULL argument");
     if (s < 1 || s > 65535) return fail(CHAFF_EINVAL, "s must be in [1, 65535]");
     if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "bad prec");
-    if (variant < -1 || variant > 4) return fail(CHAFF_EINVAL, "variant must be in [-1, 4]");
+    if (variant < -1 || variant > 7) return fail(CHAFF_EINVAL, "variant must be in [-1, 7]");
     return spmm_public(&h->c, prec, Z, X, Y, s, variant, (hipStream_t)stream);
     CHAFF_GUARD_END
 }

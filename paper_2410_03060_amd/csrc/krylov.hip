@@ -21,6 +21,7 @@
 namespace chaff {
 
 constexpr double PI_K = 3.14159265358979323846;
+constexpr int NXCD = 8;   // XCDs per MI355X; workgroup ids are dealt to them round-robin
 
 // ------------------------------------------------------------------ SpMM
 // MODE 0: Y = Z X    MODE 1: Y = B - Z X    MODE 2: Y += Z X
@@ -59,6 +60,173 @@ __global__ __launch_bounds__(256) void k_spmm_rowq(const int64_t* __restrict__ r
     if (MODE == 0) Y[o] = ccast<CY>(acc);
     if (MODE == 1) Y[o] = ccast<CY>(csub(ccast<cplx<R>>(B[o]), acc));
     if (MODE == 2) Y[o] = ccast<CY>(cadd(ccast<cplx<R>>(Y[o]), acc));
+}
+
+// Variant 5: seven lanes per block row (lane = output row q), each lane
+// accumulating SC RHS columns.  Every row of Z is loaded by exactly one lane
+// once per product (the tile variants load each block once per column lane),
+// and the seven lanes of a block row share the gathered X slab through L1.
+// For small RHS counts the product then streams Z once, at full width.
+template <typename CZ, typename CX, typename CY, int MODE, int SC, bool VEC>
+__global__ __launch_bounds__(256) void k_spmm_rowq_multi(const int64_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col_idx,
+                                                         const CZ* __restrict__ Z, const CX* __restrict__ X,
+                                                         const CY* __restrict__ B, CY* __restrict__ Y,
+                                                         int64_t n, int64_t s) {
+    using R = typename real_of<CY>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / NB;
+    const int q = (int)(t - i * NB);
+    const int64_t r0 = (int64_t)blockIdx.y * SC;
+    if (i >= n) return;
+    const int nc = (int)(s - r0 < SC ? s - r0 : SC);
+    cplx<R> acc[SC];
+#pragma unroll
+    for (int c = 0; c < SC; ++c) acc[c] = {0, 0};
+    const int64_t e1 = row_ptr[i + 1];
+    for (int64_t e = row_ptr[i]; e < e1; ++e) {
+        const int64_t col = col_idx[e];
+        const CZ* zr = Z + e * NB2 + q * NB;
+        cplx<R> z[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) z[k] = ccast<cplx<R>>(zr[k]);
+        const CX* xb = X + col * NB * s + r0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            bool done = false;
+            if constexpr (VEC && SC >= 2) {   // pairs of columns in one 16-byte load (s and r0 even)
+                if (nc == SC) {
+                    const float4* xv = reinterpret_cast<const float4*>(xb + k * s);
+#pragma unroll
+                    for (int c = 0; c < SC; c += 2) {
+                        const float4 v = xv[c / 2];
+                        cfma(acc[c], z[k], cplx<R>{(R)v.x, (R)v.y});
+                        cfma(acc[c + 1], z[k], cplx<R>{(R)v.z, (R)v.w});
+                    }
+                    done = true;
+                }
+            }
+            if (done) {
+            } else if (nc == SC) {
+#pragma unroll
+                for (int c = 0; c < SC; ++c) cfma(acc[c], z[k], ccast<cplx<R>>(xb[k * s + c]));
+            } else {
+#pragma unroll
+                for (int c = 0; c < SC; ++c)
+                    if (c < nc) cfma(acc[c], z[k], ccast<cplx<R>>(xb[k * s + c]));
+            }
+        }
+    }
+    const int64_t o = (i * NB + q) * s + r0;
+#pragma unroll
+    for (int c = 0; c < SC; ++c) {
+        if (c >= nc) break;
+        if (MODE == 0) Y[o + c] = ccast<CY>(acc[c]);
+        if (MODE == 1) Y[o + c] = ccast<CY>(csub(ccast<cplx<R>>(B[o + c]), acc[c]));
+        if (MODE == 2) Y[o + c] = ccast<CY>(cadd(ccast<cplx<R>>(Y[o + c]), acc[c]));
+    }
+}
+
+// Variant 6: one wave per NR block rows and RHS tile of S columns.  The wave
+// stages each 7x7 block in LDS with one coalesced load (prefetched one block
+// ahead so the HBM latency overlaps the arithmetic of the previous block),
+// lane (row sub, group g, column c) applies the block columns k = g, g + G,
+// ... (G = 64/(NR S)) to its RHS column, and the G partial sums of a column
+// are combined with cross-lane adds.  Z is read once per product.
+// With XCD set, consecutive workgroup ids (dealt round-robin to the eight XCDs)
+// are mapped so that XCD x walks the contiguous Morton range of row groups
+// [x G/8, (x+1) G/8): the neighbour slabs a row gathers then stay in that
+// XCD's L2.
+template <typename CZ, typename CX, typename CY, int MODE, int S, int NR, bool XCD>
+__global__ __launch_bounds__(64) void k_spmm_wave_row(const int64_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col_idx,
+                                                      const CZ* __restrict__ Z, const CX* __restrict__ X,
+                                                      const CY* __restrict__ B, CY* __restrict__ Y,
+                                                      int64_t n, int64_t s) {
+    using R = typename real_of<CY>::type;
+    constexpr int G = 64 / (S * NR);
+    constexpr int KK = (NB + G - 1) / G;
+    __shared__ CZ zs[2][NR][NB2];
+    const int lane = threadIdx.x;
+    const int sub = lane / (S * G), g = (lane / S) % G, c = lane % S;
+    int64_t grp = blockIdx.x;
+    if (XCD) {
+        const int64_t n_grp = (n + NR - 1) / NR;
+        const int64_t per_xcd = (n_grp + NXCD - 1) / NXCD;
+        grp = (int64_t)(blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
+        if (grp >= n_grp) return;   // uniform over the (single-wave) workgroup
+    }
+    const int64_t i = grp * NR + sub;
+    const int64_t r = (int64_t)blockIdx.y * S + c;
+    const bool live = r < s && i < n;
+    const int64_t rc = r < s ? r : 0;
+    // per row sub: edge range (wave-uniform loop over the longest row)
+    int64_t eb[NR], ee[NR];
+    int64_t len = 0;
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int64_t iu = grp * NR + u;
+        eb[u] = iu < n ? row_ptr[iu] : 0;
+        ee[u] = iu < n ? row_ptr[iu + 1] : 0;
+        len = ee[u] - eb[u] > len ? ee[u] - eb[u] : len;
+    }
+    cplx<R> acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
+    // lane l < 49 loads entry l of the current block of every row sub
+    CZ zn[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) zn[u] = (lane < NB2 && len > 0 && eb[u] < ee[u]) ? Z[eb[u] * NB2 + lane] : CZ{0, 0};
+    for (int64_t t = 0; t < len; ++t) {
+        const int buf = (int)(t & 1);
+        if (lane < NB2) {
+#pragma unroll
+            for (int u = 0; u < NR; ++u) zs[buf][u][lane] = zn[u];
+        }
+        if (t + 1 < len && lane < NB2) {
+#pragma unroll
+            for (int u = 0; u < NR; ++u)
+                if (eb[u] + t + 1 < ee[u]) zn[u] = Z[(eb[u] + t + 1) * NB2 + lane];
+        }
+        const int64_t e = eb[sub] + t;
+        const bool have = e < ee[sub];
+        cplx<R> x[KK];
+        if (have) {
+            const CX* xb = X + (int64_t)col_idx[e] * NB * s + rc;
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                const int k = g + kk * G;
+                x[kk] = k < NB ? ccast<cplx<R>>(xb[k * s]) : cplx<R>{0, 0};
+            }
+        }
+        __syncthreads();
+        if (have) {
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                const int k = g + kk * G;
+                if (k < NB) {
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) cfma(acc[q], ccast<cplx<R>>(zs[buf][sub][q * NB + k]), x[kk]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int off = S; off < S * G; off <<= 1)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            acc[q].re += __shfl_xor(acc[q].re, off, 64);
+            acc[q].im += __shfl_xor(acc[q].im, off, 64);
+        }
+    if (g == 0 && live) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int64_t o = (i * NB + q) * s + r;
+            if (MODE == 0) Y[o] = ccast<CY>(acc[q]);
+            if (MODE == 1) Y[o] = ccast<CY>(csub(ccast<cplx<R>>(B[o]), acc[q]));
+            if (MODE == 2) Y[o] = ccast<CY>(cadd(ccast<cplx<R>>(Y[o]), acc[q]));
+        }
+    }
 }
 
 // Variant 1: lanes -> (block row sub-index, RHS column); ST columns per row,
@@ -105,7 +273,6 @@ __global__ __launch_bounds__(256) void k_spmm_tile(const int64_t* __restrict__ r
 // remapping id -> (row tile, column tile) so that XCD x walks rows
 // [x*n/8, (x+1)*n/8) in Morton order keeps the neighbour slabs a row gathers
 // inside that XCD's L2 while its neighbours are being processed.
-constexpr int NXCD = 8;
 template <typename CZ, typename CX, typename CY, int MODE, int ST>
 __global__ __launch_bounds__(256) void k_spmm_xcd(const int64_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col_idx,
@@ -161,7 +328,7 @@ struct TuneEntry {
     int64_t n, nnzb, s;
     int prec;
     int best;
-    double ms[5];
+    double ms[8];
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
@@ -190,9 +357,13 @@ static int spmm_tile_width(int64_t s) {
     while (st < s && st < 64) st <<= 1;
     return st;
 }
+// RHS columns per wave of the COCG product (at least 8: at most 8 groups of block columns)
+static int cocg_width(int64_t s) { return spmm_tile_width(s) < 8 ? 8 : spmm_tile_width(s); }
 
 // variant: 0 = rowq, 1 = tile (ST from s), 2 = tile with ST halved (more rows per wave),
-// 3 = tile in XCD-aware order, 4 = XCD-aware with ST halved
+// 3 = tile in XCD-aware order, 4 = XCD-aware with ST halved, 5 = rowq with up to 16
+// columns per lane, 6 = one wave per block row with the block staged in LDS, 7 = 6 in
+// XCD-aware order
 template <typename CZ, typename CX, typename CY, int MODE, bool DIAG>
 static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, const CZ* Z, const CX* X,
                                 const CY* B, CY* Y, int64_t n, int64_t nnzb, int64_t s, int variant,
@@ -213,6 +384,52 @@ static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, 
         dim3 grid((unsigned)((n * NB + 255) / 256), (unsigned)s);
         hipLaunchKernelGGL((k_spmm_rowq<CZ, CX, CY, MODE, DIAG>), grid, dim3(256), 0, st, row_ptr, col_idx,
                            Z, X, B, Y, n, s);
+        CHAFF_LAUNCH_CHECK();
+        return CHAFF_OK;
+    }
+    if ((variant == 6 || variant == 7) && !DIAG) {
+        // S columns per tile; S <= 4 packs two block rows into one wave; 7 = XCD-aware order
+        const int sw = spmm_tile_width(s) < 4 ? 4 : spmm_tile_width(s);
+        const int64_t nr = sw <= 4 ? 2 : 1;
+        const int64_t n_grp = (n + nr - 1) / nr;
+        const int64_t nblk = variant == 7 ? (n_grp + NXCD - 1) / NXCD * NXCD : n_grp;
+        dim3 grid((unsigned)nblk, (unsigned)((s + sw - 1) / sw));
+#define CHAFF_WR(SW, NRW)                                                                                   \
+    case SW:                                                                                                \
+        if (variant == 7)                                                                                   \
+            hipLaunchKernelGGL((k_spmm_wave_row<CZ, CX, CY, MODE, SW, NRW, true>), grid, dim3(64), 0, st,   \
+                               row_ptr, col_idx, Z, X, B, Y, n, s);                                         \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_spmm_wave_row<CZ, CX, CY, MODE, SW, NRW, false>), grid, dim3(64), 0, st,  \
+                               row_ptr, col_idx, Z, X, B, Y, n, s);                                         \
+        break;
+        switch (sw) {
+            CHAFF_WR(4, 2) CHAFF_WR(8, 1) CHAFF_WR(16, 1) CHAFF_WR(32, 1) CHAFF_WR(64, 1)
+            default: return fail(CHAFF_EINVAL, "bad tile width");
+        }
+#undef CHAFF_WR
+        CHAFF_LAUNCH_CHECK();
+        return CHAFF_OK;
+    }
+    if (variant == 5 && !DIAG) {
+        const int sc = s <= 1 ? 1 : s <= 2 ? 2 : s <= 4 ? 4 : s <= 8 ? 8 : 16;
+        dim3 grid((unsigned)((n * NB + 255) / 256), (unsigned)((s + sc - 1) / sc));
+        const bool vec = std::is_same<CX, c64>::value && (s % 2 == 0) && sc >= 2 &&
+                         (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+#define CHAFF_RQM(SC)                                                                                        \
+    case SC:                                                                                                 \
+        if (vec)                                                                                             \
+            hipLaunchKernelGGL((k_spmm_rowq_multi<CZ, CX, CY, MODE, SC, true>), grid, dim3(256), 0, st, row_ptr, \
+                               col_idx, Z, X, B, Y, n, s);                                                  \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_spmm_rowq_multi<CZ, CX, CY, MODE, SC, false>), grid, dim3(256), 0, st,     \
+                               row_ptr, col_idx, Z, X, B, Y, n, s);                                          \
+        break;
+        switch (sc) {
+            CHAFF_RQM(1) CHAFF_RQM(2) CHAFF_RQM(4) CHAFF_RQM(8) CHAFF_RQM(16)
+            default: return fail(CHAFF_EINVAL, "bad column count");
+        }
+#undef CHAFF_RQM
         CHAFF_LAUNCH_CHECK();
         return CHAFF_OK;
     }
@@ -681,13 +898,18 @@ __global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_
 // cloud in a fixed order).  Thread (rsub, r): RHS column r of wire rows
 // i = w0 + rsub, w0 + rsub + 256/ST, ... of the block's chunk.
 //
-// COCG product q = Z p over small cloud-aligned tiles (256/ST wires, one
-// block row per thread row) in XCD-aware order: XCD x walks tiles
-// [x*T/8, (x+1)*T/8) in Morton order, so the neighbour slabs a row gathers
-// stay in that XCD's L2 while its neighbours are processed.  sigma = p^T q is
+// COCG product q = Z p.  A tile is four block rows of one cloud, one row per
+// wave; tiles are walked in XCD-aware order (XCD x takes tiles
+// [x T/8, (x+1) T/8) in Morton order, so the neighbour slabs a row gathers
+// stay in that XCD's L2).  Each wave stages the 7x7 blocks of its row in its
+// own LDS slot with one coalesced load, prefetched one block ahead so the
+// HBM latency of the Z stream overlaps the arithmetic; lane (group g, column
+// c) applies block columns k = g, g + G, ... (G = 64/S) to RHS column c, and
+// the G partial sums are combined with cross-lane adds.  sigma = p^T q is
 // reduced per tile in FP64 (tpart[tile][r]); two fixed-order passes then sum
 // tiles per group and groups per cloud.
-template <typename CZ, typename C, int ST>
+constexpr int COCG_TILE_ROWS = RB / 64;
+template <typename CZ, typename C, int S>
 __global__ __launch_bounds__(RB) void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles,
                                                   int xcd_order,
                                                   const int64_t* __restrict__ row_ptr,
@@ -695,6 +917,9 @@ __global__ __launch_bounds__(RB) void k_cocg_spmm(const Chunk* __restrict__ tile
                                                   const C* __restrict__ P, C* __restrict__ Q, int64_t s,
                                                   c128* __restrict__ tpart) {
     using R = typename real_of<C>::type;
+    constexpr int G = 64 / S;
+    constexpr int KK = (NB + G - 1) / G;
+    __shared__ CZ zs[COCG_TILE_ROWS][2][NB2];
     __shared__ c128 red[RB];
     const int64_t id = blockIdx.x;
     int64_t t, ctile_l;
@@ -708,65 +933,128 @@ __global__ __launch_bounds__(RB) void k_cocg_spmm(const Chunk* __restrict__ tile
         t = id / col_tiles;
         ctile_l = id % col_tiles;
     }
-    const int ctile = (int)ctile_l;
     if (t >= n_tiles) return;   // uniform over the block
     const Chunk tl = tiles[t];
-    const int sub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
-    const int64_t i = tl.w0 + sub;
-    const int64_t r = (int64_t)ctile * ST + threadIdx.x % ST;
-    const bool live = r < s && i < tl.w1;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int g = lane / S, c = lane % S;
+    const int64_t i = tl.w0 + w;
+    const int64_t r = ctile_l * S + c;
     const int64_t rc = r < s ? r : 0;
     c128 dot = {0, 0};
-    if (i < tl.w1) {
+    if (i < tl.w1) {   // wave-uniform
         cplx<R> acc[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
-        const int64_t e1 = row_ptr[i + 1];
-        for (int64_t e = row_ptr[i]; e < e1; ++e) {
-            const int64_t col = col_idx[e];
-            const CZ* zb = Z + e * NB2;
-            const C* xb = P + col * NB * s + rc;
-            cplx<R> x[NB];
+        const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+        CZ zn = (lane < NB2 && e0 < e1) ? Z[e0 * NB2 + lane] : CZ{0, 0};
+        for (int64_t e = e0; e < e1; ++e) {
+            const int buf = (int)((e - e0) & 1);
+            if (lane < NB2) zs[w][buf][lane] = zn;
+            if (e + 1 < e1 && lane < NB2) zn = Z[(e + 1) * NB2 + lane];
+            const C* xb = P + (int64_t)col_idx[e] * NB * s + rc;
+            cplx<R> x[KK];
 #pragma unroll
-            for (int k = 0; k < NB; ++k) x[k] = xb[k * s];
+            for (int kk = 0; kk < KK; ++kk) {
+                const int k = g + kk * G;
+                x[kk] = k < NB ? ccast<cplx<R>>(xb[k * s]) : cplx<R>{0, 0};
+            }
+            // the block written above by this wave's lanes is visible to all of its lanes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
+            for (int kk = 0; kk < KK; ++kk) {
+                const int k = g + kk * G;
+                if (k < NB) {
 #pragma unroll
-                for (int k = 0; k < NB; ++k) cfma(acc[q], ccast<cplx<R>>(zb[q * NB + k]), x[k]);
+                    for (int q = 0; q < NB; ++q) cfma(acc[q], ccast<cplx<R>>(zs[w][buf][q * NB + k]), x[kk]);
+                }
+            }
         }
-        if (live) {
+#pragma unroll
+        for (int off = S; off < 64; off <<= 1)
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
+                acc[q].re += __shfl_xor(acc[q].re, off, 64);
+                acc[q].im += __shfl_xor(acc[q].im, off, 64);
+            }
+        if (r < s) {   // lane g writes rows q = g, g + G, ... and their part of p^T q
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (q % G != g) continue;
                 const int64_t o = (i * NB + q) * s + r;
-                Q[o] = acc[q];
+                Q[o] = ccast<C>(acc[q]);
                 cfma(dot, ccast<c128>(P[o]), ccast<c128>(acc[q]));
             }
         }
     }
-    c128 v = block_col_reduce(dot, ST, red);
-    if (threadIdx.x < ST && r < s) tpart[t * s + r] = v;
+    // columns: lanes with equal c across waves and groups
+    c128 v = block_col_reduce(dot, S, red);
+    if (threadIdx.x < S && r < s) tpart[t * s + r] = v;
 }
 
-// p = z + beta p
+// Search direction and deferred solution update, one pass per step:
+//   x += alpha p_old (the step whose residual update ran last; skipped with
+//   pend = 0 when that update was already applied), z = P_i r, p = z + beta p_old.
+// z is recomputed here from r instead of being stored by the update kernel.
+template <typename CZ, typename C, int ST>
+__global__ __launch_bounds__(RB) void k_cg_pdir(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
+                                                const CZ* __restrict__ Pinv, const C* __restrict__ rv,
+                                                C* __restrict__ p, C* __restrict__ x, int64_t s, int pend) {
+    using R = typename real_of<C>::type;
+    const Chunk ch = chunks[blockIdx.x];
+    const int rsub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
+    const int64_t r = (int64_t)blockIdx.y * ST + threadIdx.x % ST;
+    if (r >= s) return;
+    const CgState& S = cg[(int64_t)ch.cloud * s + r];
+    const cplx<R> a = {pend ? (R)S.alpha_re : (R)0, pend ? (R)S.alpha_im : (R)0};
+    const cplx<R> b = {(R)S.beta_re, (R)S.beta_im};
+    for (int64_t i = ch.w0 + rsub; i < ch.w1; i += RB / ST) {
+        cplx<R> res[NB], pv[NB], xv[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int64_t o = (i * NB + k) * s + r;
+            res[k] = rv[o];
+            pv[k] = p[o];
+            if (pend) xv[k] = x[o];
+        }
+        const CZ* pb = Pinv + i * NB2;
+#pragma unroll
+        for (int qq = 0; qq < NB; ++qq) {
+            const int64_t o = (i * NB + qq) * s + r;
+            cplx<R> z = {0, 0};
+#pragma unroll
+            for (int k = 0; k < NB; ++k) cfma(z, ccast<cplx<R>>(pb[qq * NB + k]), res[k]);
+            if (pend) {
+                cfma(xv[qq], a, pv[qq]);
+                x[o] = xv[qq];
+            }
+            cfma(z, b, pv[qq]);
+            p[o] = z;
+        }
+    }
+}
+
+// x += alpha p (the deferred update of the last step, before a flush)
 template <typename C>
-__global__ void k_cg_p(const int32_t* __restrict__ wire_cloud, const CgState* __restrict__ cg, int64_t n_rows,
-                       int64_t s, const C* __restrict__ z, C* __restrict__ p) {
+__global__ void k_cg_xpend(const int32_t* __restrict__ wire_cloud, const CgState* __restrict__ cg, int64_t n_rows,
+                           int64_t s, const C* __restrict__ p, C* __restrict__ x) {
     using R = typename real_of<C>::type;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_rows * s) return;
     const int64_t row = t / s, rr = t - (t / s) * s;
     const CgState& S = cg[(int64_t)wire_cloud[row / NB] * s + rr];
-    cplx<R> pv = z[t];
-    cfma(pv, cplx<R>{(R)S.beta_re, (R)S.beta_im}, p[t]);
-    p[t] = pv;
+    cplx<R> xv = x[t];
+    cfma(xv, cplx<R>{(R)S.alpha_re, (R)S.alpha_im}, p[t]);
+    x[t] = xv;
 }
 
-// x += alpha p ; r -= alpha q ; z = P_i r ; partial r^T z and ||r||^2
+// r -= alpha q ; z = P_i r (not stored) ; partial r^T z and ||r||^2
 template <typename CZ, typename C, int ST>
 __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
-                                                  const CZ* __restrict__ Pinv, const C* __restrict__ p,
-                                                  const C* __restrict__ q, C* __restrict__ x, C* __restrict__ rv,
-                                                  C* __restrict__ z, int64_t s, c128* __restrict__ part, int nslot,
+                                                  const CZ* __restrict__ Pinv, const C* __restrict__ q,
+                                                  C* __restrict__ rv, int64_t s, c128* __restrict__ part, int nslot,
                                                   int slot0) {
     using R = typename real_of<C>::type;
     __shared__ c128 red[RB];
@@ -776,25 +1064,19 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
     c128 rz = {0, 0}, rr = {0, 0};
     if (r < s) {
         const CgState& S = cg[(int64_t)ch.cloud * s + r];
-        const cplx<R> a = {(R)S.alpha_re, (R)S.alpha_im};
-        const cplx<R> na = {-a.re, -a.im};
+        const cplx<R> na = {-(R)S.alpha_re, -(R)S.alpha_im};
         for (int64_t i = ch.w0 + rsub; i < ch.w1; i += RB / ST) {
-            cplx<R> res[NB], xv[NB], pv[NB], qv[NB];
+            cplx<R> res[NB], qv[NB];
 #pragma unroll
-            for (int k = 0; k < NB; ++k) {   // issue all 28 loads before any arithmetic
+            for (int k = 0; k < NB; ++k) {   // issue all loads before any arithmetic
                 const int64_t o = (i * NB + k) * s + r;
-                xv[k] = x[o];
-                pv[k] = p[o];
                 res[k] = rv[o];
                 qv[k] = q[o];
             }
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
-                const int64_t o = (i * NB + k) * s + r;
-                cfma(xv[k], a, pv[k]);
                 cfma(res[k], na, qv[k]);
-                x[o] = xv[k];
-                rv[o] = res[k];
+                rv[(i * NB + k) * s + r] = res[k];
             }
             const CZ* pb = Pinv + i * NB2;
 #pragma unroll
@@ -802,7 +1084,6 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
                 cplx<R> acc = {0, 0};
 #pragma unroll
                 for (int k = 0; k < NB; ++k) cfma(acc, ccast<cplx<R>>(pb[qq * NB + k]), res[k]);
-                z[(i * NB + qq) * s + r] = acc;
                 cfma(rz, ccast<c128>(res[qq]), ccast<c128>(acc));
                 rr.re += (double)res[qq].re * res[qq].re + (double)res[qq].im * res[qq].im;
             }
@@ -829,9 +1110,8 @@ __global__ void k_cg_step(int64_t nsys, const c128* __restrict__ rz, const c128*
     if (!S.done && (rn <= S.target || !isfinite(rn))) S.done = 1;
     const c128 den = (mode == 1) ? c128{S.rho, S.rho_im} : c128{S.rho_prev, S.rho_prev_im};
     const double dd = den.re * den.re + den.im * den.im;
-    if (S.done) {
+    if (S.done) {   // alpha stays: the deferred x update of this step is still to be applied
         S.beta_re = S.beta_im = 0.0;
-        S.alpha_re = S.alpha_im = 0.0;
     } else if (mode == 0 || !(dd > 0.0)) {
         S.beta_re = S.beta_im = 0.0;
     } else {
@@ -944,15 +1224,14 @@ static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec,
     sh.n_chunks = (int)nch;
     sh.n_tiles = 0;
     sh.n_groups = 0;
-    sh.cocg_st = spmm_tile_width(s);
+    sh.cocg_st = cocg_width(s);
     sh.cocg_xcd = 1;
-    {   // the COCG product follows the tuned public variant: 1/3 full tile width, 2/4 half; 1/2 linear order
+    {   // the COCG product follows the tuned public variant's workgroup order (1, 2, 6: linear)
         int v = tuned_variant(c->n, c->nnzb, s, prec);
         if (v < 0) v = default_variant(s);
-        if ((v == 2 || v == 4) && sh.cocg_st > 1) sh.cocg_st >>= 1;
-        sh.cocg_xcd = (v == 1 || v == 2) ? 0 : 1;
+        sh.cocg_xcd = (v == 1 || v == 2 || v == 6) ? 0 : 1;
     }
-    sh.tile_w = 256 / sh.cocg_st;
+    sh.tile_w = COCG_TILE_ROWS;
     if (method != CHAFF_GMRES) {
         for (int k = 0; k < c->n_clouds; ++k) {
             const int64_t nw = c->cloud_off[k + 1] - c->cloud_off[k];
@@ -1055,11 +1334,18 @@ static chaff_status norms_to(const SolveShape& sh, SolveLayout& L, const C* v, c
 
 
 template <typename CZ, typename C, int ST>
-static void launch_cg_update(const SolveShape& sh, SolveLayout& L, const CZ* Pinv, C* V, const C* p, int64_t vs,
+static void launch_cg_update(const SolveShape& sh, SolveLayout& L, const CZ* Pinv, const C* q, C* r,
                              hipStream_t st) {
     const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
     hipLaunchKernelGGL((k_cg_update<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const CgState*)L.cg,
-                       Pinv, p, (const C*)(V + 4 * vs), V, V + vs, V + 2 * vs, sh.s, L.part, sh.nslot, 0);
+                       Pinv, q, r, sh.s, L.part, sh.nslot, 0);
+}
+template <typename CZ, typename C, int ST>
+static void launch_cg_pdir(const SolveShape& sh, SolveLayout& L, const CZ* Pinv, const C* r, C* p, C* x, int pend,
+                           hipStream_t st) {
+    const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
+    hipLaunchKernelGGL((k_cg_pdir<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const CgState*)L.cg,
+                       Pinv, r, p, x, sh.s, pend);
 }
 template <typename CZ, typename C, int ST>
 static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& L, const CZ* Z, const C* p, C* q,
@@ -1090,13 +1376,17 @@ static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc
                                  std::vector<int32_t>& colmap, const std::vector<int32_t>& keep, int64_t s_full,
                                  C* xc, C* r, C* z, C* p, C* q, hipStream_t st) {
     const int64_t rows = cs.rows, s_old = cs.s, s_new = (int64_t)keep.size();
-    ProfScope ps("cocg_compact", st, (double)rows * s_old * sizeof(C) * 2 + 3.0 * rows * s_new * sizeof(C) * 3);
+    ProfScope ps("cocg_compact", st, (double)rows * s_old * sizeof(C) * 5 + 2.0 * rows * s_new * sizeof(C) * 3);
+    hipLaunchKernelGGL((k_cg_xpend<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
+                       (const int32_t*)c->wire_cloud, (const CgState*)L.cg, rows, s_old, (const C*)p, xc);
+    CHAFF_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_add_scaled<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
                        (const int32_t*)c->wire_cloud, (const double*)L.rn, (const int32_t*)L.colmap, rows, s_old,
                        s_full, xc, L.x);
     CHAFF_LAUNCH_CHECK();
     CHAFF_HIP(hipMemcpyAsync(L.keep, keep.data(), s_new * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    for (C* v : {r, z, p}) {
+    (void)z;
+    for (C* v : {r, p}) {
         hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)v, rows,
                            s_old, (const int32_t*)L.keep, s_new, q);
         CHAFF_LAUNCH_CHECK();
@@ -1112,8 +1402,8 @@ static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc
     CHAFF_HIP(hipMemcpyAsync(L.colmap, colmap.data(), s_new * sizeof(int32_t), hipMemcpyHostToDevice, st));
     cs.s = s_new;
     cs.nsys = (int64_t)cs.n_clouds * s_new;
-    cs.cocg_st = spmm_tile_width(s_new);
-    cs.tile_w = 256 / cs.cocg_st;
+    cs.cocg_st = cocg_width(s_new);
+    cs.tile_w = COCG_TILE_ROWS;
     std::vector<Chunk> tl;
     std::vector<int32_t> gto, cgo;
     build_tiles(c, cs.tile_w, tl, gto, cgo);
@@ -1144,7 +1434,7 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
                                const std::vector<double>& ckpt, const std::vector<int32_t>& act, bool first,
                                int& iters, hipStream_t st) {
     const int64_t rows = sh.rows, s = sh.s, vs = rows * s, nsys = sh.nsys;
-    C* V = static_cast<C*>(L.V);   // [x_c | r | z | p | q], each with room for [rows][s]
+    C* V = static_cast<C*>(L.V);   // [x_c | r | (spare) | p | q], each with room for [rows][s]
     C* xc = V;
     C* r = V + vs;
     C* z = V + 2 * vs;
@@ -1176,20 +1466,21 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     CHAFF_HIP(hipStreamSynchronize(st));   // host staging vectors may leave scope
     int mode = (first || !use_rr) ? 0 : 2;
     int32_t last_checked = -1;
+    bool pending_applied = false;   // set by a compaction, which applies the deferred x update itself
     std::vector<int32_t> flags;
     for (int k = 0; k <= o->restart; ++k) {
         const int wst = spmm_tile_width(cs.s);
-        {   // x += alpha p, r -= alpha q, z = P r, r^T z, ||r||^2 (alpha = 0 on entry)
-            ProfScope pu("k_cg_update", st, (7.0 * rows * cs.s) * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
-            const C* pc = p;
+        {   // r -= alpha q, r^T (P r), ||r||^2 (alpha = 0 on entry)
+            ProfScope pu("k_cg_update", st, (3.0 * rows * cs.s) * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
+            const C* qc = q;
             switch (wst) {
-                case 1: launch_cg_update<CZ, C, 1>(cs, Lc, Pinv, V, pc, vs, st); break;
-                case 2: launch_cg_update<CZ, C, 2>(cs, Lc, Pinv, V, pc, vs, st); break;
-                case 4: launch_cg_update<CZ, C, 4>(cs, Lc, Pinv, V, pc, vs, st); break;
-                case 8: launch_cg_update<CZ, C, 8>(cs, Lc, Pinv, V, pc, vs, st); break;
-                case 16: launch_cg_update<CZ, C, 16>(cs, Lc, Pinv, V, pc, vs, st); break;
-                case 32: launch_cg_update<CZ, C, 32>(cs, Lc, Pinv, V, pc, vs, st); break;
-                default: launch_cg_update<CZ, C, 64>(cs, Lc, Pinv, V, pc, vs, st); break;
+                case 1: launch_cg_update<CZ, C, 1>(cs, Lc, Pinv, qc, r, st); break;
+                case 2: launch_cg_update<CZ, C, 2>(cs, Lc, Pinv, qc, r, st); break;
+                case 4: launch_cg_update<CZ, C, 4>(cs, Lc, Pinv, qc, r, st); break;
+                case 8: launch_cg_update<CZ, C, 8>(cs, Lc, Pinv, qc, r, st); break;
+                case 16: launch_cg_update<CZ, C, 16>(cs, Lc, Pinv, qc, r, st); break;
+                case 32: launch_cg_update<CZ, C, 32>(cs, Lc, Pinv, qc, r, st); break;
+                default: launch_cg_update<CZ, C, 64>(cs, Lc, Pinv, qc, r, st); break;
             }
         }
         CHAFF_LAUNCH_CHECK();
@@ -1222,25 +1513,34 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
             if (!keep.empty() && (int64_t)keep.size() <= wst / 2) {
                 chaff_status cst = cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, z, p, q, st);
                 if (cst != CHAFF_OK) return cst;
+                pending_applied = true;
                 if (g_verbose)
                     std::fprintf(stderr, "[chaff] cocg step %d: compacted to %lld columns\n", k, (long long)cs.s);
             }
         }
         mode = 1;
         ++iters;
-        {
-            ProfScope pp("k_cg_p", st, 3.0 * rows * cs.s * sizeof(C));
-            hipLaunchKernelGGL((k_cg_p<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
-                               (const int32_t*)c->wire_cloud, (const CgState*)L.cg, rows, cs.s, (const C*)z, p);
+        {   // x += alpha p_old (deferred), p = P r + beta p_old
+            const int pend = pending_applied ? 0 : 1;
+            pending_applied = false;
+            ProfScope pp("k_cg_p", st, (3.0 + 2.0 * pend) * rows * cs.s * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
+            const int ws2 = spmm_tile_width(cs.s);
+            const C* rc_ = r;
+            switch (ws2) {
+                case 1: launch_cg_pdir<CZ, C, 1>(cs, Lc, Pinv, rc_, p, xc, pend, st); break;
+                case 2: launch_cg_pdir<CZ, C, 2>(cs, Lc, Pinv, rc_, p, xc, pend, st); break;
+                case 4: launch_cg_pdir<CZ, C, 4>(cs, Lc, Pinv, rc_, p, xc, pend, st); break;
+                case 8: launch_cg_pdir<CZ, C, 8>(cs, Lc, Pinv, rc_, p, xc, pend, st); break;
+                case 16: launch_cg_pdir<CZ, C, 16>(cs, Lc, Pinv, rc_, p, xc, pend, st); break;
+                case 32: launch_cg_pdir<CZ, C, 32>(cs, Lc, Pinv, rc_, p, xc, pend, st); break;
+                default: launch_cg_pdir<CZ, C, 64>(cs, Lc, Pinv, rc_, p, xc, pend, st); break;
+            }
         }
         CHAFF_LAUNCH_CHECK();
         {   // q = Z p with per-tile p^T q
             ProfScope ps("spmm", st, ((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 8.0 * (c->n + 1) +
                                          3.0 * rows * cs.s * sizeof(C));
             switch (cs.cocg_st) {
-                case 1: launch_cocg_spmm<CZ, C, 1>(c, cs, Lc, Z, p, q, st); break;
-                case 2: launch_cocg_spmm<CZ, C, 2>(c, cs, Lc, Z, p, q, st); break;
-                case 4: launch_cocg_spmm<CZ, C, 4>(c, cs, Lc, Z, p, q, st); break;
                 case 8: launch_cocg_spmm<CZ, C, 8>(c, cs, Lc, Z, p, q, st); break;
                 case 16: launch_cocg_spmm<CZ, C, 16>(c, cs, Lc, Z, p, q, st); break;
                 case 32: launch_cocg_spmm<CZ, C, 32>(c, cs, Lc, Z, p, q, st); break;
@@ -1257,6 +1557,10 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
                            L.cg);
         CHAFF_LAUNCH_CHECK();
     }
+    // the deferred x update of the last step, then x64 += scale * xc
+    hipLaunchKernelGGL((k_cg_xpend<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
+                       (const int32_t*)c->wire_cloud, (const CgState*)L.cg, rows, cs.s, (const C*)p, xc);
+    CHAFF_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_add_scaled<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
                        (const int32_t*)c->wire_cloud, (const double*)L.rn, (const int32_t*)L.colmap, rows, cs.s, s,
                        xc, L.x);
@@ -1540,7 +1844,7 @@ chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y
     CHAFF_HIP(hipEventCreate(&b));
     double bms = 1e300;
     int bv = default_variant(s);
-    for (int v = 0; v <= 4; ++v) {
+    for (int v = 0; v <= 7; ++v) {
         for (int rep = 0; rep < 7; ++rep) {
             if (rep == 2) CHAFF_HIP(hipEventRecord(a, st));
             chaff_status r = spmm_public(c, prec, Z, X, Y, s, v, st);
@@ -1576,9 +1880,9 @@ int32_t tune_report(char* buf, int32_t len) {
         const TuneEntry& e = g_tune[i];
         char line[512];
         std::snprintf(line, sizeof line,
-                      "%s{\"n\":%lld,\"nnzb\":%lld,\"s\":%lld,\"prec\":%d,\"best\":%d,\"ms\":[%.4f,%.4f,%.4f,%.4f,%.4f]}",
+                      "%s{\"n\":%lld,\"nnzb\":%lld,\"s\":%lld,\"prec\":%d,\"best\":%d,\"ms\":[%.4f,%.4f,%.4f,%.4f,%.4f,%.4f,%.4f,%.4f]}",
                       i ? "," : "", (long long)e.n, (long long)e.nnzb, (long long)e.s, e.prec, e.best, e.ms[0],
-                      e.ms[1], e.ms[2], e.ms[3], e.ms[4]);
+                      e.ms[1], e.ms[2], e.ms[3], e.ms[4], e.ms[5], e.ms[6], e.ms[7]);
         out += line;
     }
     out += "]";
