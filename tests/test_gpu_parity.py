@@ -342,3 +342,24 @@ def test_cocg_column_compaction(B, n_clouds):
     e = current_err(_to_np(X), xo)
     say(f"  current err {e.max():.3e}")
     assert e.max() <= 1e-4
+
+
+@pytest.mark.parametrize("R", [40, 64, 70])
+def test_cocg_wide_rhs_matrix_core_product(B, R):
+    """At more than 32 right-hand sides the complex64 COCG product runs on the
+    matrix cores (64-column tiles, ragged last tile for 40 and 70)."""
+    cloud = W.random_cloud(31, 900, box_lam=8.0, d_c_lam=1.5)
+    inc = W.random_incidences(np.random.default_rng(32), R)
+    say(f"[solve] COCG R={R} N={cloud.n}")
+    cl = B.build_cloud(cloud)
+    Z, P = B.fill_Z(cl, B.C64)
+    X, info = B.solve(cl, Z, P, inc.k_hat, inc.e_hat,
+                      B.solve_opts(tol=1e-6, method=B.COCG, restart=500, inner_tol=1e-3))
+    say(f"  cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e}")
+    assert np.all(info["rel_res"] <= 1e-6)
+    Zs, _ = mom.snfc_matrix(cloud)
+    u = mom.excitation(cloud, inc.k_hat, inc.e_hat)
+    xo = osolve.sparse_solve(Zs, u)
+    e = current_err(_to_np(X), xo)
+    say(f"  current err {e.max():.3e}")
+    assert e.max() <= 1e-4
