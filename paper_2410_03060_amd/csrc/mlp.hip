@@ -42,6 +42,8 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // nearest even on the FP32
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// the same rounding (nearest even) by the hardware conversion, for activations
+__device__ __forceinline__ uint16_t f2bf_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ uint16_t d2bf(double x) { return f2bf((float)x); }
 
 __device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {
@@ -67,7 +69,9 @@ __device__ __forceinline__ void mma_rows(const uint16_t* const (&ap)[MT], const 
     }
 }
 
-__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// logistic function with the hardware exponential and reciprocal (about 1 ulp each;
+// the result is rounded to BF16 or enters a BF16 product)
+__device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 __device__ __forceinline__ float wave_sum(float v) {  // fixed butterfly order
 #pragma unroll
@@ -201,6 +205,154 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs g) {
         if (TRAIN) {
             sq = wave_sum(sq);
             if (lane == 0) g.loss_part[wave] = sq;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ fused inference
+// All four layers in one persistent kernel: each workgroup copies the BF16
+// weights into LDS once (rows padded by 8 elements so that the 16 rows a
+// ds_read_b128 touches fall in distinct banks), then every wave walks its own
+// 32-row tiles: layer 1 reads the features from HBM, the hidden activations
+// stay in the wave's LDS tile, and only the 14 outputs are written.  Weight
+// traffic is 116 KB per workgroup instead of per 32-row tile.
+constexpr int FLD1 = NF + 8, FLDH = NH + 8;   // padded LDS row strides (BF16)
+constexpr int FUSED_LDS = (NH * FLD1 + 2 * NH * FLDH + NOP * FLDH + 4 * 32 * FLDH) * 2;
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_fwd_fused(const uint16_t* __restrict__ feat, int64_t M,
+                                                   const float* __restrict__ th, Packed pk, float* __restrict__ Y) {
+    extern __shared__ uint16_t lds[];
+    uint16_t* w1 = lds;                      // [128][FLD1]
+    uint16_t* w2 = w1 + NH * FLD1;           // [128][FLDH]
+    uint16_t* w3 = w2 + NH * FLDH;           // [128][FLDH]
+    uint16_t* w4 = w3 + NH * FLDH;           // [16][FLDH]
+    uint16_t* act = w4 + NOP * FLDH;         // [4 waves][32][FLDH]
+    // weights -> LDS (16-byte chunks)
+    for (int t = threadIdx.x; t < NH * (NF / 8); t += 256) {
+        const int r = t / (NF / 8), c = (t % (NF / 8)) * 8;
+        *reinterpret_cast<uint4*>(w1 + r * FLD1 + c) = *reinterpret_cast<const uint4*>(pk.wt1 + r * NF + c);
+    }
+    for (int t = threadIdx.x; t < NH * (NH / 8); t += 256) {
+        const int r = t / (NH / 8), c = (t % (NH / 8)) * 8;
+        *reinterpret_cast<uint4*>(w2 + r * FLDH + c) = *reinterpret_cast<const uint4*>(pk.wt2 + r * NH + c);
+        *reinterpret_cast<uint4*>(w3 + r * FLDH + c) = *reinterpret_cast<const uint4*>(pk.wt3 + r * NH + c);
+    }
+    for (int t = threadIdx.x; t < NOP * (NH / 8); t += 256) {
+        const int r = t / (NH / 8), c = (t % (NH / 8)) * 8;
+        *reinterpret_cast<uint4*>(w4 + r * FLDH + c) = *reinterpret_cast<const uint4*>(pk.wt4 + r * NH + c);
+    }
+    __syncthreads();
+    // The weights are the A operand (rows = output features) and the activations
+    // the B operand (columns = sample rows): a lane then holds 4 consecutive
+    // output features of one sample, written to the LDS tile as one 8-byte store.
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint16_t* my = act + w * 32 * FLDH;
+    const int l16 = lane & 15, g4 = (lane >> 4) * 4, kb = (lane >> 4) * 8;
+    const int64_t n_tiles = (M + 31) / 32;
+    constexpr int KS1 = NF / 32, MT = NH / 16;
+    auto load_tile = [&](int64_t tile, bf16x8 (&fa)[KS1][2]) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t m = tile * 32 + 16 * j + l16;
+#pragma unroll
+            for (int ks = 0; ks < KS1; ++ks) fa[ks][j] = m < M ? ld8(feat + m * NF + ks * 32 + kb) : zero8();
+        }
+    };
+    // bias + SiLU of acc -> BF16 activation tile
+    auto to_tile = [&](const f32x4 (&acc)[MT][2], const float* bias) {
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            const int f0 = 16 * i + g4;
+            const float4 b = *reinterpret_cast<const float4*>(bias + f0);
+            const float bb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                uint16_t h[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float z = acc[i][j][r] + bb[r];
+                    h[r] = f2bf_hw(z * sigmoidf(z));
+                }
+                *reinterpret_cast<uint2*>(my + (16 * j + l16) * FLDH + f0) =
+                    make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+            }
+        }
+        wave_lds_sync();
+    };
+    const int64_t t_step = (int64_t)gridDim.x * 4;
+    int64_t tile = (int64_t)blockIdx.x * 4 + w;
+    bf16x8 fa[KS1][2];
+    if (tile < n_tiles) load_tile(tile, fa);
+    for (; tile < n_tiles; tile += t_step) {
+        const int64_t m0 = tile * 32;
+        bf16x8 fnext[KS1][2];
+        if (tile + t_step < n_tiles) load_tile(tile + t_step, fnext);
+        f32x4 acc[MT][2];
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks) {   // layer 1
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const bf16x8 a = ld8(w1 + (16 * i + l16) * FLD1 + ks * 32 + kb);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, fa[ks][j], acc[i][j], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int layer = 0; layer < 2; ++layer) {   // layers 2 and 3
+            to_tile(acc, th + (layer == 0 ? OB1 : OB2));
+            const uint16_t* wl = layer == 0 ? w2 : w3;
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+            for (int k = 0; k < NH; k += 32) {
+                bf16x8 b[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) b[j] = ld8(my + (16 * j + l16) * FLDH + k + kb);
+#pragma unroll
+                for (int i = 0; i < MT; ++i) {
+                    const bf16x8 a = ld8(wl + (16 * i + l16) * FLDH + k + kb);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+        to_tile(acc, th + OB3);
+        f32x4 out[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int k = 0; k < NH; k += 32) {   // output layer (14 of 16 rows of W4^T used)
+            const bf16x8 a = ld8(w4 + l16 * FLDH + k + kb);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                out[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ld8(my + (16 * j + l16) * FLDH + k + kb), out[j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t m = m0 + 16 * j + l16;
+            if (m < M) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int f = g4 + r;
+                    if (f < NO) Y[m * NO + f] = out[j][r] + th[OB4 + f];
+                }
+            }
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks) {
+            fa[ks][0] = fnext[ks][0];
+            fa[ks][1] = fnext[ks][1];
         }
     }
 }
@@ -363,49 +515,59 @@ __device__ __forceinline__ double sinc_d(double x) {
     return sin(x) / x;
 }
 
-constexpr int FT_THREADS = 128;
-constexpr int FT_LD = NF + 2;  // LDS row stride in BF16 (odd number of dwords)
+constexpr int FW_CAND = 256;   // near-set rows up to this length are ranked in parallel
 
-// One thread per sample row = p*R + r (caller order p).  Rows are built in
-// LDS and written out as contiguous dwords.
-__global__ __launch_bounds__(FT_THREADS) void k_features(const Wire* __restrict__ wires, const int32_t* __restrict__ perm,
-                                                         const int32_t* __restrict__ iperm,
-                                                         const int64_t* __restrict__ row_ptr,
-                                                         const int32_t* __restrict__ col_idx, int64_t R,
-                                                         int64_t row0, int64_t n_rows, const double* __restrict__ k_hat,
-                                                         const double* __restrict__ e_hat, double k, double lam,
-                                                         double d_c, uint16_t* __restrict__ feat) {
+// One wave per wire p (caller order) and the rows p*R + r of it that fall in
+// the requested range.  The 16 nearest neighbours are chosen once per wire:
+// every lane ranks its candidates by counting the candidates with a smaller
+// (squared distance, caller index) key (rows longer than FW_CAND fall back to
+// repeated minimum search), and the neighbours' geometry is staged in LDS.
+// The features that do not depend on the incidence are formed once per wire.
+__global__ __launch_bounds__(64) void k_features(const Wire* __restrict__ wires, const int32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ iperm,
+                                                 const int64_t* __restrict__ row_ptr,
+                                                 const int32_t* __restrict__ col_idx, int64_t R, int64_t row0,
+                                                 int64_t n_rows, const double* __restrict__ k_hat,
+                                                 const double* __restrict__ e_hat, double k, double lam, double d_c,
+                                                 uint16_t* __restrict__ feat) {
 #pragma clang fp contract(off)
-    __shared__ uint32_t lds[FT_THREADS * FT_LD / 2];
-    uint16_t* my = reinterpret_cast<uint16_t*>(lds) + threadIdx.x * FT_LD;
-    const int64_t t = (int64_t)blockIdx.x * FT_THREADS + threadIdx.x;
-    if (t < n_rows) {
-        const int64_t row = row0 + t;
-        const int64_t p = row / R;
-        const int64_t r = row - p * R;
-        const int32_t ip = iperm[p];
-        const Wire w = wires[ip];
-        const double kx = k_hat[3 * r], ky = k_hat[3 * r + 1], kz = k_hat[3 * r + 2];
-        const double ex = e_hat[3 * r], ey = e_hat[3 * r + 1], ez = e_hat[3 * r + 2];
-        const double sp = (w.tx * ex + w.ty * ey + w.tz * ez) >= 0.0 ? 1.0 : -1.0;
-        const double tx = sp * w.tx, ty = sp * w.ty, tz = sp * w.tz;
-        const double te = tx * ex + ty * ey + tz * ez;
-        const double beta = k * (kx * tx + ky * ty + kz * tz);
-        const double D = w.len / 8.0;
-        const double env = sinc_d(beta * D / 2.0);
-        const double a = te * (env * env);
-        const int64_t e0 = row_ptr[ip], e1 = row_ptr[ip + 1];
-        const int64_t cnt = e1 - e0 - 1;
-        my[0] = d2bf(10.0 * (w.len / lam - 0.5));
-        my[1] = d2bf((double)cnt / 16.0);
-        for (int q = 0; q < 7; ++q) {
-            const double sq = -0.5 * w.len + (q + 1) * D;
-            double sn, cs;
-            sincos(beta * sq, &sn, &cs);
-            my[2 + 2 * q] = d2bf(a * cs);
-            my[3 + 2 * q] = d2bf(-a * sn);
+    __shared__ double cd2[FW_CAND];
+    __shared__ int32_t cid[FW_CAND], cint[FW_CAND];
+    __shared__ int32_t slot[KNB];
+    __shared__ double sg[KNB][8];   // d.x, d.y, d.z, d2, t'.x, t'.y, t'.z, L'
+    __shared__ uint16_t fixed[KNB][4];   // |d|/d_c, length feature, Re, Im exp(-j k |d|)
+    const int lane = threadIdx.x;
+    const int64_t p = row0 / R + blockIdx.x;
+    const int64_t rb = p * R > row0 ? p * R : row0;
+    const int64_t re = (p + 1) * R < row0 + n_rows ? (p + 1) * R : row0 + n_rows;
+    if (rb >= re) return;   // uniform over the (single-wave) block
+    const int32_t ip = iperm[p];
+    const Wire w = wires[ip];
+    const int64_t e0 = row_ptr[ip], e1 = row_ptr[ip + 1];
+    const int64_t ne = e1 - e0;   // includes the diagonal
+    const int64_t cnt = ne - 1;
+    if (lane < KNB) slot[lane] = -1;
+    if (ne <= FW_CAND) {
+        for (int64_t t = lane; t < ne; t += 64) {
+            const int32_t c = col_idx[e0 + t];
+            cint[t] = c;
+            cid[t] = perm[c];
+            cd2[t] = c == ip ? 0.0 : dist2(w, wires[c]);
         }
-        // neighbours in ascending (squared distance, caller index)
+        __syncthreads();
+        for (int64_t t = lane; t < ne; t += 64) {
+            if (cint[t] == ip) continue;
+            const double d2 = cd2[t];
+            const int32_t id = cid[t];
+            int rank = 0;
+            for (int64_t u = 0; u < ne; ++u) {
+                if (cint[u] == ip) continue;
+                const double du = cd2[u];
+                rank += (du < d2 || (du == d2 && cid[u] < id)) ? 1 : 0;
+            }
+            if (rank < KNB) slot[rank] = cint[t];
+        }
+    } else {   // long row: repeated minimum search (the same on every lane)
         double pd2 = -1.0;
         int32_t pid = -1;
         for (int j = 0; j < KNB; ++j) {
@@ -420,42 +582,99 @@ __global__ __launch_bounds__(FT_THREADS) void k_features(const Wire* __restrict_
                 const bool before = d2 < bd2 || (d2 == bd2 && id < bid);
                 if (after && before) { bd2 = d2; bid = id; bint = c; }
             }
-            uint16_t* f = my + FOWN + FNB * j;
-            if (bint < 0) {
-                for (int i = 0; i < FNB; ++i) f[i] = 0;
-                continue;
-            }
+            if (bint < 0) break;
+            if (lane == 0) slot[j] = bint;
             pd2 = bd2;
             pid = bid;
-            const Wire v = wires[bint];
-            const double dx = v.cx - w.cx, dy = v.cy - w.cy, dz = v.cz - w.cz;
-            const double sv = (v.tx * ex + v.ty * ey + v.tz * ez) >= 0.0 ? 1.0 : -1.0;
-            const double ux = sv * v.tx, uy = sv * v.ty, uz = sv * v.tz;
-            double sn, cs;
-            sincos(k * (kx * dx + ky * dy + kz * dz), &sn, &cs);
+        }
+    }
+    __syncthreads();
+    // per-slot geometry and the incidence-independent features
+    if (lane < KNB && slot[lane] >= 0) {
+        const Wire v = wires[slot[lane]];
+        const double d2 = dist2(w, v);
+        sg[lane][0] = v.cx - w.cx;
+        sg[lane][1] = v.cy - w.cy;
+        sg[lane][2] = v.cz - w.cz;
+        sg[lane][3] = d2;
+        sg[lane][4] = v.tx;
+        sg[lane][5] = v.ty;
+        sg[lane][6] = v.tz;
+        sg[lane][7] = v.len;
+        double sn, cs;
+        sincos(k * sqrt(d2), &sn, &cs);
+        fixed[lane][0] = d2bf(sqrt(d2) / d_c);
+        fixed[lane][1] = d2bf(10.0 * (v.len / lam - 0.5));
+        fixed[lane][2] = d2bf(cs);
+        fixed[lane][3] = d2bf(-sn);
+    }
+    __syncthreads();
+    // two rows per pass: lanes 0-31 the first, 32-63 the second; within a half,
+    // lane m < 16 writes neighbour slot m, 16 <= m < 23 own rooftop m - 16,
+    // m = 23 the two scalar own features.  Every active lane evaluates exactly
+    // one sine/cosine per row.
+    const double D = w.len / 8.0;
+    const int half = lane >> 5, m = lane & 31;
+    for (int64_t row2 = rb; row2 < re; row2 += 2) {
+        const int64_t row = row2 + half;
+        const bool live = row < re;
+        const int64_t r = (live ? row : row2) - p * R;
+        const double kx = k_hat[3 * r], ky = k_hat[3 * r + 1], kz = k_hat[3 * r + 2];
+        const double ex = e_hat[3 * r], ey = e_hat[3 * r + 1], ez = e_hat[3 * r + 2];
+        const double sp = (w.tx * ex + w.ty * ey + w.tz * ez) >= 0.0 ? 1.0 : -1.0;
+        const double tx = sp * w.tx, ty = sp * w.ty, tz = sp * w.tz;
+        const bool is_slot = m < KNB && slot[m < KNB ? m : 0] >= 0;
+        const bool is_own = m >= 16 && m < 23;
+        const int jj = m < KNB ? m : 0;
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+        if (is_slot) {
+            dx = sg[jj][0];
+            dy = sg[jj][1];
+            dz = sg[jj][2];
+        }
+        double beta = 0.0, arg = 0.0;
+        if (is_own) {
+            beta = k * (kx * tx + ky * ty + kz * tz);
+            arg = beta * (-0.5 * w.len + (m - 16 + 1) * D);
+        } else if (is_slot) {
+            arg = k * (kx * dx + ky * dy + kz * dz);
+        }
+        double sn, cs;
+        sincos(arg, &sn, &cs);
+        if (!live) continue;
+        uint16_t* out = feat + (row - row0) * NF;
+        if (is_slot) {
+            const double vtx = sg[jj][4], vty = sg[jj][5], vtz = sg[jj][6];
+            const double sv = (vtx * ex + vty * ey + vtz * ez) >= 0.0 ? 1.0 : -1.0;
+            const double ux = sv * vtx, uy = sv * vty, uz = sv * vtz;
             const double ue = ux * ex + uy * ey + uz * ez;
-            f[0] = d2bf(sqrt(bd2) / d_c);
+            uint16_t* f = out + FOWN + FNB * jj;
+            f[0] = fixed[jj][0];
             f[1] = d2bf((tx * dx + ty * dy + tz * dz) / d_c);
             f[2] = d2bf((ux * dx + uy * dy + uz * dz) / d_c);
             f[3] = d2bf(tx * ux + ty * uy + tz * uz);
             f[4] = d2bf(ue * cs);
             f[5] = d2bf(-ue * sn);
-            f[6] = d2bf(10.0 * (v.len / lam - 0.5));
+            f[6] = fixed[jj][1];
             f[7] = d2bf(kx * ux + ky * uy + kz * uz);
-            const double dist = sqrt(bd2);
-            sincos(k * dist, &sn, &cs);
-            f[8] = d2bf(cs);
-            f[9] = d2bf(-sn);
+            f[8] = fixed[jj][2];
+            f[9] = fixed[jj][3];
             f[10] = d2bf(1.0);
+        } else if (m < KNB) {   // empty slot
+            uint16_t* f = out + FOWN + FNB * m;
+#pragma unroll
+            for (int g = 0; g < FNB; ++g) f[g] = 0;
+        } else if (is_own) {
+            const double te = tx * ex + ty * ey + tz * ez;
+            const double env = sinc_d(beta * D / 2.0);
+            const double a = te * (env * env);
+            const int q = m - 16;
+            out[2 + 2 * q] = d2bf(a * cs);
+            out[3 + 2 * q] = d2bf(-a * sn);
+        } else if (m == 23) {
+            out[0] = d2bf(10.0 * (w.len / lam - 0.5));
+            out[1] = d2bf((double)cnt / 16.0);
         }
-    }
-    __syncthreads();
-    const int64_t b0 = (int64_t)blockIdx.x * FT_THREADS;
-    const int64_t nb = n_rows - b0 < FT_THREADS ? n_rows - b0 : FT_THREADS;
-    uint32_t* out = reinterpret_cast<uint32_t*>(feat + b0 * NF);
-    for (int64_t d = threadIdx.x; d < nb * (NF / 2); d += FT_THREADS) {
-        const int64_t rr = d / (NF / 2), ww = d % (NF / 2);
-        out[d] = lds[rr * (FT_LD / 2) + ww];
     }
 }
 
@@ -591,15 +810,12 @@ TrainBufs carve_train(Carve& cv, int64_t Mpad) {
 
 struct FwdBufs {
     Packed pk;
-    uint16_t *h0, *h1;
     float* Y;
 };
 
 FwdBufs carve_fwd(Carve& cv, int64_t Mpad, bool with_y) {
     FwdBufs b{};
     carve_packed(cv, b.pk);
-    b.h0 = cv.take<uint16_t>(Mpad * NH);
-    b.h1 = cv.take<uint16_t>(Mpad * NH);
     b.Y = with_y ? cv.take<float>(Mpad * NO) : nullptr;
     return b;
 }
@@ -612,25 +828,18 @@ chaff_status launch_pack(const float* theta, const Packed& pk, hipStream_t st) {
 
 double layer_flops(int64_t m, int k, int n) { return 2.0 * (double)m * k * n; }
 
-// Forward of rows [0, M) of feat (BF16 [*][192]) into Y [M][14]; h0/h1 ping-pong.
-chaff_status forward_rows(const float* theta, const FwdBufs& b, const uint16_t* feat, int64_t M, float* Y,
-                          hipStream_t st) {
-    const int64_t Mpad = pad_rows(M, ROWS_WG);
-    FwdArgs a{};
-    a.M = M;
-    a.Mpad = Mpad;
-    const unsigned grid = (unsigned)(Mpad / ROWS_WG);
-    {
-        ProfScope ps("mlp_forward", st, layer_flops(M, NF, NH) + 2 * layer_flops(M, NH, NH) + layer_flops(M, NH, NO), true);
-        a.A = feat; a.lda = NF; a.Wt = b.pk.wt1; a.K = NF; a.bias = theta + OB1; a.a_out = b.h0;
-        hipLaunchKernelGGL((k_fwd<false, false>), dim3(grid), dim3(256), 0, st, a);
-        a.A = b.h0; a.lda = NH; a.Wt = b.pk.wt2; a.K = NH; a.bias = theta + OB2; a.a_out = b.h1;
-        hipLaunchKernelGGL((k_fwd<false, false>), dim3(grid), dim3(256), 0, st, a);
-        a.A = b.h1; a.Wt = b.pk.wt3; a.bias = theta + OB3; a.a_out = b.h0;
-        hipLaunchKernelGGL((k_fwd<false, false>), dim3(grid), dim3(256), 0, st, a);
-        a.A = b.h0; a.Wt = b.pk.wt4; a.bias = theta + OB4; a.a_out = nullptr; a.Y = Y;
-        hipLaunchKernelGGL((k_fwd<true, false>), dim3(grid), dim3(256), 0, st, a);
-    }
+// Fused inference over rows [0, M): one persistent workgroup per CU.
+chaff_status forward_fused(const float* theta, const Packed& pk, const uint16_t* feat, int64_t M, float* Y,
+                           hipStream_t st) {
+    static const bool attr = [] {
+        return hipFuncSetAttribute((const void*)k_fwd_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   FUSED_LDS) == hipSuccess;
+    }();
+    if (!attr) return fail(CHAFF_EHIP, "cannot reserve LDS for the fused forward kernel");
+    const int64_t tiles = (M + 31) / 32;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(256, (tiles + 3) / 4));
+    ProfScope ps("mlp_forward", st, layer_flops(M, NF, NH) + 2 * layer_flops(M, NH, NH) + layer_flops(M, NH, NO), true);
+    hipLaunchKernelGGL(k_fwd_fused, dim3(grid), dim3(256), FUSED_LDS, st, feat, M, theta, pk, Y);
     CHAFF_LAUNCH_CHECK();
     return CHAFF_OK;
 }
@@ -653,7 +862,7 @@ chaff_status mlp_forward(const float* theta, const uint16_t* feat, int64_t M, fl
     if (!cv.ok()) return fail(CHAFF_EWORKSPACE, "mlp workspace too small");
     chaff_status s = launch_pack(theta, b.pk, st);
     if (s != CHAFF_OK) return s;
-    return forward_rows(theta, b, feat, M, Y, st);
+    return forward_fused(theta, b.pk, feat, M, Y, st);
 }
 
 chaff_status mlp_grad(const float* theta, const uint16_t* feat, const float* T, const int64_t* idx, int64_t M,
@@ -744,7 +953,8 @@ chaff_status mlp_features(Cloud* c, const double* k_hat, const double* e_hat, in
     if (n_rows == 0) return CHAFF_OK;
     const double k = 2.0 * 3.14159265358979323846 / c->wavelength;
     ProfScope ps("mlp_features", st, (double)n_rows * NF * 2.0);
-    hipLaunchKernelGGL(k_features, dim3(nblk(n_rows, FT_THREADS)), dim3(FT_THREADS), 0, st, (const Wire*)c->wires,
+    const int64_t n_wires = (row0 + n_rows - 1) / R - row0 / R + 1;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)n_wires), dim3(64), 0, st, (const Wire*)c->wires,
                        (const int32_t*)c->perm, (const int32_t*)c->iperm, (const int64_t*)c->row_ptr,
                        (const int32_t*)c->col_idx, R, row0, n_rows, k_hat, e_hat, k, c->wavelength, c->d_c, feat);
     CHAFF_LAUNCH_CHECK();
@@ -790,7 +1000,7 @@ chaff_status mlp_guess(Cloud* c, chaff_prec prec, const void* Pinv, const float*
         const int64_t nr = std::min(chunk, total - r0);
         s = mlp_features(c, k_hat, e_hat, R, r0, nr, feat, st);
         if (s != CHAFF_OK) return s;
-        s = forward_rows(theta, b, feat, nr, b.Y, st);
+        s = forward_fused(theta, b.pk, feat, nr, b.Y, st);
         if (s != CHAFF_OK) return s;
         ProfScope ps("mlp_assemble", st, (double)nr * (NO * 4 + 7 * 16) + (double)nr / R * 49 * (prec == CHAFF_C64 ? 8 : 16));
         if (prec == CHAFF_C64)
