@@ -153,7 +153,14 @@ def cpu_baseline(wl, n_sample: int = 2000, r_sample: int = 8):
     scale = n_full / sample.n
     t_full = (t1 - t0) * scale + (t2 - t1) / r_s * R * scale
     systems = cloud.n_clouds * R
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": systems / t_full, "unit": "solved angles/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": cpu_model,
             "sample": f"{sample.n} of {n_full} wires (first cloud, nearest its centroid) and {r_s} of {R} "
                       f"incidences: setup {t1 - t0:.2f} s + {r_s} incidences {t2 - t1:.2f} s, each scaled "
                       f"by the wire ratio {scale:.1f}; full workload estimated at {t_full:.1f} s"}

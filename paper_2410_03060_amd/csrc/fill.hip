@@ -65,8 +65,7 @@ __device__ __forceinline__ Anti anti(double v, double b) {
 // K_mn(d) = int_0^1 int_0^1 xi^m xi'^n F(d + xi - xi') dxi' dxi by repeated
 // integration by parts (xi: test segment, xi': source segment).  Returns the
 // rooftop-half combinations K[a][b] with phi_+ = xi, phi_- = 1 - xi.
-__device__ void static_self(int d, double b, double K[2][2]) {
-    Anti p1 = anti(d + 1.0, b), p0 = anti((double)d, b), m1 = anti(d - 1.0, b);
+__device__ void static_self(const Anti& p1, const Anti& p0, const Anti& m1, double K[2][2]) {
     double k00 = (p1.f2 - p0.f2) - (p0.f2 - m1.f2);
     double k01 = -(p0.f2 - m1.f2) + (p1.f3 - p0.f3) - (p0.f3 - m1.f3);
     double k10 = (p1.f2 - p0.f2) - (p1.f3 - 2.0 * p0.f3 + m1.f3);
@@ -79,17 +78,31 @@ __device__ void static_self(int d, double b, double K[2][2]) {
 
 // ------------------------------------------------------------------ self blocks
 
+// One wave per wire, four wires per workgroup; each wave works in its own LDS
+// slot and synchronises only with itself.
+constexpr int SELF_WAVES = 4;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename R>
-__global__ __launch_bounds__(64) void k_self(const Wire* __restrict__ wires, int64_t n,
-                                             const int64_t* __restrict__ diag_pos,
-                                             cplx<R>* __restrict__ Z, cplx<R>* __restrict__ Pinv,
-                                             FillParams prm, int32_t* __restrict__ status) {
+__global__ __launch_bounds__(64 * SELF_WAVES) void k_self(const Wire* __restrict__ wires, int64_t n,
+                                                          const int64_t* __restrict__ diag_pos,
+                                                          cplx<R>* __restrict__ Z, cplx<R>* __restrict__ Pinv,
+                                                          FillParams prm, int32_t* __restrict__ status) {
     using C = cplx<R>;
-    __shared__ C T[8][2][2];       // T_ab(d), d = 0..7
-    __shared__ C Ab[7][14];        // augmented [Z | I] for the inverse
-    const int lane = threadIdx.x;
-    const int64_t w = blockIdx.x;
-    if (w >= n) return;
+    __shared__ C Ts[SELF_WAVES][8][2][2];    // T_ab(d), d = 0..7
+    __shared__ C Abs[SELF_WAVES][7][14];     // augmented [Z | I] for the inverse
+    __shared__ Anti As[SELF_WAVES][4];       // static antiderivatives at v = -1, 0, 1, 2
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * SELF_WAVES + wv;
+    if (w >= n) return;   // uniform over the wave; waves never wait for each other
+    auto& T = Ts[wv];
+    auto& Ab = Abs[wv];
     const Wire wr = wires[w];
     const int d = lane >> 3, kk = lane & 7;
     const double Dd = wr.len / NSEG;
@@ -97,6 +110,8 @@ __global__ __launch_bounds__(64) void k_self(const Wire* __restrict__ wires, int
     const R a2 = (R)(wr.rad * wr.rad);
     const R inv_lam = (R)prm.inv_lambda;
     const int q = prm.q;
+    // the four FP64 antiderivative evaluations of the closed-form static part, one lane each
+    if (lane < 4) As[wv][lane] = anti((double)(lane - 1), wr.rad / Dd);
 
     C m00 = {0, 0}, m01 = {0, 0}, m10 = {0, 0}, m11 = {0, 0};
     if (kk < q) {
@@ -139,6 +154,7 @@ __global__ __launch_bounds__(64) void k_self(const Wire* __restrict__ wires, int
         m10.re += __shfl_xor(m10.re, o); m10.im += __shfl_xor(m10.im, o);
         m11.re += __shfl_xor(m11.re, o); m11.im += __shfl_xor(m11.im, o);
     }
+    wave_sync();   // As visible
     if (kk == 0) {
         const R sc = (R)(Dd * Dd / (4.0 * PI));
         C A[2][2];
@@ -146,9 +162,9 @@ __global__ __launch_bounds__(64) void k_self(const Wire* __restrict__ wires, int
         A[0][1] = cscale(csub(m10, m11), sc);
         A[1][0] = cscale(csub(m01, m11), sc);
         A[1][1] = cscale(cadd(csub(csub(m00, m10), m01), m11), sc);
-        if (d <= 1) {
+        if (d <= 1) {   // v = d + 1, d, d - 1 sit at As[d + 2], As[d + 1], As[d]
             double K[2][2];
-            static_self(d, wr.rad / Dd, K);
+            static_self(As[wv][d + 2], As[wv][d + 1], As[wv][d], K);
             for (int a = 0; a < 2; ++a)
                 for (int b = 0; b < 2; ++b) A[a][b].re += (R)(Dd / (4.0 * PI) * K[a][b]);
         }
@@ -160,7 +176,7 @@ __global__ __launch_bounds__(64) void k_self(const Wire* __restrict__ wires, int
                 T[d][a][b] = csub(A[a][b], cscale(B, sg * sz));
             }
     }
-    __syncthreads();
+    wave_sync();
     C* Zb = Z + diag_pos[w] * NB2;
     if (lane < NB2) {
         const int qi = lane / NB, qj = lane % NB;
@@ -177,7 +193,7 @@ __global__ __launch_bounds__(64) void k_self(const Wire* __restrict__ wires, int
         Ab[qi][qj] = acc;
         Ab[qi][NB + qj] = (qi == qj) ? C{1, 0} : C{0, 0};
     }
-    __syncthreads();
+    wave_sync();
     if (Pinv == nullptr) return;
     // Gauss-Jordan with partial pivoting; lane c < 14 owns column c
     bool singular = false;
@@ -192,13 +208,13 @@ __global__ __launch_bounds__(64) void k_self(const Wire* __restrict__ wires, int
         C pv = Ab[best][piv];
         C f[NB];
         for (int r = 0; r < NB; ++r) f[r] = Ab[r][piv];
-        __syncthreads();
+        wave_sync();
         if (lane < 2 * NB) {
             C tmp = Ab[piv][lane];
             Ab[piv][lane] = Ab[best][lane];
             Ab[best][lane] = tmp;
         }
-        __syncthreads();
+        wave_sync();
         if (best != piv) { C t = f[piv]; f[piv] = f[best]; f[best] = t; }
         R inv_m = (R)1 / bm;
         C ip = {pv.re * inv_m, -pv.im * inv_m};
@@ -208,7 +224,7 @@ __global__ __launch_bounds__(64) void k_self(const Wire* __restrict__ wires, int
             for (int r = 0; r < NB; ++r)
                 if (r != piv) Ab[r][lane] = csub(Ab[r][lane], cmul(f[r], rowp));
         }
-        __syncthreads();
+        wave_sync();
     }
     if (singular) {
         if (lane == 0) atomicOr(status, 1);
@@ -362,7 +378,8 @@ static chaff_status fill_impl(Cloud* c, void* Zv, void* Pinv, hipStream_t st) {
     }
     {
         ProfScope pss("fill_self", st, 24.0 * 8.0 * c->q_self * c->q_self * (double)c->n, true);
-        hipLaunchKernelGGL((k_self<R>), dim3((unsigned)c->n), dim3(64), 0, st, (const Wire*)c->wires, c->n,
+        hipLaunchKernelGGL((k_self<R>), dim3((unsigned)((c->n + SELF_WAVES - 1) / SELF_WAVES)), dim3(64 * SELF_WAVES), 0,
+                           st, (const Wire*)c->wires, c->n,
                            (const int64_t*)c->diag_pos, Z, static_cast<C*>(Pinv), ps, c->d_status);
     }
     CHAFF_LAUNCH_CHECK();

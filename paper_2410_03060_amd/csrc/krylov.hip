@@ -45,13 +45,25 @@ __global__ __launch_bounds__(256) void k_spmm_rowq(const int64_t* __restrict__ r
     const int64_t e0 = DIAG ? i : row_ptr[i];
     const int64_t e1 = DIAG ? i + 1 : row_ptr[i + 1];
     cplx<R> acc = {0, 0};
+    // the column index and Z row of the next block are requested one block ahead
+    int64_t col_n = DIAG ? i : (e0 < e1 ? col_idx[e0] : 0);
+    CZ zn[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) zn[k] = e0 < e1 ? Z[e0 * NB2 + q * NB + k] : CZ{0, 0};
     for (int64_t e = e0; e < e1; ++e) {
-        const int64_t col = DIAG ? i : col_idx[e];
-        const CZ* zr = Z + e * NB2 + q * NB;
+        const int64_t col = col_n;
+        CZ zc[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) zc[k] = zn[k];
+        if (e + 1 < e1) {
+            if (!DIAG) col_n = col_idx[e + 1];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) zn[k] = Z[(e + 1) * NB2 + q * NB + k];
+        }
         const CX* xb = X + col * NB * s + r;
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-            cplx<R> z = ccast<cplx<R>>(zr[k]);
+            cplx<R> z = ccast<cplx<R>>(zc[k]);
             cplx<R> x = ccast<cplx<R>>(xb[k * s]);
             cfma(acc, z, x);
         }
@@ -83,13 +95,22 @@ __global__ __launch_bounds__(256) void k_spmm_rowq_multi(const int64_t* __restri
     cplx<R> acc[SC];
 #pragma unroll
     for (int c = 0; c < SC; ++c) acc[c] = {0, 0};
-    const int64_t e1 = row_ptr[i + 1];
-    for (int64_t e = row_ptr[i]; e < e1; ++e) {
-        const int64_t col = col_idx[e];
-        const CZ* zr = Z + e * NB2 + q * NB;
+    const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+    // the column index and Z row of the next block are requested one block ahead
+    int64_t col_n = e0 < e1 ? col_idx[e0] : 0;
+    CZ zn[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) zn[k] = e0 < e1 ? Z[e0 * NB2 + q * NB + k] : CZ{0, 0};
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t col = col_n;
         cplx<R> z[NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) z[k] = ccast<cplx<R>>(zr[k]);
+        for (int k = 0; k < NB; ++k) z[k] = ccast<cplx<R>>(zn[k]);
+        if (e + 1 < e1) {
+            col_n = col_idx[e + 1];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) zn[k] = Z[(e + 1) * NB2 + q * NB + k];
+        }
         const CX* xb = X + col * NB * s + r0;
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -1207,7 +1228,7 @@ static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec,
     SolveShape sh;
     sh.method = method;
     sh.mg = method != CHAFF_GMRES ? 1 : m;
-    sh.nvec = method != CHAFF_GMRES ? 5 : m + 1;
+    sh.nvec = method != CHAFF_GMRES ? 4 : m + 1;
     sh.n = c->n;
     sh.rows = c->n * NB;
     sh.s = s;
@@ -1374,7 +1395,7 @@ static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& 
 template <typename C>
 static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc, const SolveLayout& L,
                                  std::vector<int32_t>& colmap, const std::vector<int32_t>& keep, int64_t s_full,
-                                 C* xc, C* r, C* z, C* p, C* q, hipStream_t st) {
+                                 C* xc, C* r, C* p, C* q, hipStream_t st) {
     const int64_t rows = cs.rows, s_old = cs.s, s_new = (int64_t)keep.size();
     ProfScope ps("cocg_compact", st, (double)rows * s_old * sizeof(C) * 5 + 2.0 * rows * s_new * sizeof(C) * 3);
     hipLaunchKernelGGL((k_cg_xpend<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
@@ -1385,7 +1406,6 @@ static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc
                        s_full, xc, L.x);
     CHAFF_LAUNCH_CHECK();
     CHAFF_HIP(hipMemcpyAsync(L.keep, keep.data(), s_new * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    (void)z;
     for (C* v : {r, p}) {
         hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)v, rows,
                            s_old, (const int32_t*)L.keep, s_new, q);
@@ -1434,12 +1454,11 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
                                const std::vector<double>& ckpt, const std::vector<int32_t>& act, bool first,
                                int& iters, hipStream_t st) {
     const int64_t rows = sh.rows, s = sh.s, vs = rows * s, nsys = sh.nsys;
-    C* V = static_cast<C*>(L.V);   // [x_c | r | (spare) | p | q], each with room for [rows][s]
+    C* V = static_cast<C*>(L.V);   // [x_c | r | p | q], each with room for [rows][s]
     C* xc = V;
     C* r = V + vs;
-    C* z = V + 2 * vs;
-    C* p = V + 3 * vs;
-    C* q = V + 4 * vs;
+    C* p = V + 2 * vs;
+    C* q = V + 3 * vs;
     const bool use_rr = o->method == CHAFF_COCG_RR;
     const bool compact = !use_rr && s > 1;
     SolveShape cs = sh;            // current shape (columns shrink under compaction)
@@ -1511,7 +1530,7 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
                 if (live) keep.push_back((int32_t)j);
             }
             if (!keep.empty() && (int64_t)keep.size() <= wst / 2) {
-                chaff_status cst = cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, z, p, q, st);
+                chaff_status cst = cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, p, q, st);
                 if (cst != CHAFF_OK) return cst;
                 pending_applied = true;
                 if (g_verbose)

@@ -223,6 +223,25 @@ def test_p8_translation_and_rotation_invariance():
     assert abs(bistatic(flip, inc.k_hat[:1], inc.e_hat[:1], obs_r, obs_e) - s0) <= 1e-10 * s0
 
 
+# --------------------------------------------------------------------------- P13
+
+def test_p13_bistatic_cut_peaks_in_the_forward_direction():
+    """A cloud many wavelengths wide scatters most strongly along the incident
+    propagation direction, where every wire's contribution arrives in phase
+    (the forward lobe of the bistatic cut reported in Sec. III-A)."""
+    cl = W.c1().cloud                                   # 64 wires in a 10-wavelength cube
+    kh = np.array([[1.0, 0.0, 0.0]])
+    e = np.array([[0.0, 0.0, 1.0]])
+    x = solve.dense_solve(mom.dense_Z(cl), mom.excitation(cl, kh, e))
+    phi = np.radians(np.arange(0.0, 360.0, 1.0))
+    r = np.stack([np.cos(phi), np.sin(phi), np.zeros_like(phi)], axis=1)
+    pol = np.tile([0.0, 0.0, -1.0], (phi.size, 1))     # theta-hat on the horizontal cut
+    sig = mom.rcs_from_currents(cl, x, r, pol)[0]
+    i = int(np.argmax(sig))
+    assert min(i, 360 - i) <= 2
+    assert sig[i] > 10.0 * sig[180]                     # far above the backscatter
+
+
 # --------------------------------------------------------------------------- P9
 
 @pytest.mark.parametrize("d", [-1, 0, 1])
