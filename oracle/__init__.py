@@ -15,7 +15,9 @@ Everything is plain NumPy/SciPy in complex128:
                  and block-sparse matrix (eq. 9), excitation (eq. 4) and the
                  far-field / RCS functional;
 * ``solve``   -- dense LU ("entire coupling"), sparse direct and FP64 GMRES;
-* ``mlp``     -- reference forward/backward of the learned initial guess.
+* ``mlp``     -- reference forward/backward of the learned initial guess;
+* ``precond`` -- cell order of the wires and the cluster block-Jacobi
+                 preconditioner (dense inverse per group of nearby wires).
 
 Pins (tests/test_oracle_pins.py) tie each function to something outside the
 oracle itself: the resonant half-wave dipole RCS, Galerkin symmetry,
@@ -23,4 +25,4 @@ reciprocity, the optical theorem, segment-refinement convergence, the
 orientation-averaged dipole RCS quoted in Sec. III-B, closed-form integrals
 checked by adaptive quadrature, and brute force on tiny inputs.
 """
-from . import mlp, mom, solve  # noqa: F401
+from . import mlp, mom, precond, solve  # noqa: F401
