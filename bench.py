@@ -39,6 +39,7 @@ KERNEL_SYMBOLS = {
     "fill_mutual": ("chaff::k_mutual", "paper_2410_03060_amd/csrc/fill.hip"),
     "fill_self": ("chaff::k_self", "paper_2410_03060_amd/csrc/fill.hip"),
     "rcs_mono": ("chaff::k_mono", "paper_2410_03060_amd/csrc/farfield.hip"),
+    "cluster_build": ("chaff::k_cluster_build", "paper_2410_03060_amd/csrc/precond.hip"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
@@ -85,7 +86,8 @@ CONFIGS = {
                desc="1,000,000 wires (7M unknowns), uniform sphere R=50 lambda, d_c=1 lambda, "
                     "64 azimuth incidences, complex64 + FP64 refinement, learned initial guess"),
 }
-GUESSES = {"zero": 0, "bj": 2, "mlp": 1}
+GUESSES = {"zero": 0, "bj": 2, "mlp": 1}   # bj: x0 = P u with the solve's preconditioner P
+PRECONDS = {"block": 0, "cluster": 1}
 # training recipe of the learned guess per evaluation workload: (generator, clouds, epochs)
 MLP_TRAINING = {"c4_eval": ("c4_train_cloud", 200, 12), "c5": ("c5_train_cloud", 64, 12)}
 METHODS = {"gmres": 0, "cocg": 1, "cocg_rr": 2}
@@ -296,6 +298,9 @@ def main(argv=None) -> int:
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
     ap.add_argument("--guess", default=None, choices=sorted(GUESSES),
                     help="initial guess: zero, bj (block-Jacobi) or mlp (learned; trained before timing)")
+    ap.add_argument("--precond", default=None, choices=sorted(PRECONDS),
+                    help="preconditioner: block (inverse self blocks) or cluster (inverse diagonal "
+                         "blocks of groups of 8 nearby wires)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the untimed zero / block-Jacobi / learned guess comparison")
     ap.add_argument("--no-sweep", action="store_true", help="skip the product sweep over RHS counts")
@@ -340,6 +345,8 @@ def main(argv=None) -> int:
     torch.cuda.synchronize()
 
     guess = a.guess or cfg.get("guess", "zero")
+    pc = a.precond or cfg.get("precond", "block")
+    opts.precond = PRECONDS[pc]
     mlp_report = None
     theta = None
     if guess == "mlp":
@@ -349,9 +356,10 @@ def main(argv=None) -> int:
         gk = guess_kind or guess
         cl = B.build_cloud(geom)
         Z, P = B.fill_Z(cl, prec)
+        M = B.cluster_precond(cl, Z, prec) if pc == "cluster" else P
         x0 = B.mlp_guess(cl, P, theta, kh, eh, prec=prec) if gk == "mlp" else None
         opts.use_x0 = GUESSES[gk]
-        X, info = B.solve(cl, Z, P, kh, eh, opts, x0=x0)
+        X, info = B.solve(cl, Z, M, kh, eh, opts, x0=x0)
         sig = B.rcs(cl, X, -kh, eh, monostatic=True)
         return cl, X, info, sig, Z
 
@@ -431,7 +439,7 @@ def main(argv=None) -> int:
         "config": {"workload": a.config, "description": cfg["desc"], "wires": int(wl.cloud.n),
                    "clouds": int(wl.cloud.n_clouds), "rhs": int(R), "unknowns": int(wl.cloud.n * 7),
                    "nnzb": int(cl.nnzb), "pairs": int(cl.n_pairs), "method": method, "restart": restart,
-                   "tol": a.tol, "initial_guess": guess},
+                   "tol": a.tol, "initial_guess": guess, "preconditioner": pc},
         "solver": {"cycles": infos[-1]["cycles"], "iterations": infos[-1]["iterations"],
                    "max_rel_residual": infos[-1]["max_rel_residual"],
                    "systems_per_step": int(wl.cloud.n_clouds * R), "solved_total": solved},

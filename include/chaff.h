@@ -148,16 +148,26 @@ typedef struct {
     int32_t restart;          /* GMRES(m) cycle length, 1..200 (30) */
     int32_t max_cycles;       /* restart/refinement cycles (50) */
     int32_t use_x0;           /* 0: x0 = 0; 1: X holds an initial guess on entry;
-                                 2: block-Jacobi guess x0 = Pinv u */
+                                 2: preconditioner guess x0 = P u (P the preconditioner
+                                    passed as Pinv: block or cluster) */
     int32_t prec;             /* chaff_prec of Z, Pinv and the Krylov vectors */
     int32_t spmm_variant;     /* -1: tuned (chaff_autotune) or default choice; else variant 0..7 */
     int32_t method;           /* chaff_method */
+    int32_t precond;          /* chaff_precond: what the Pinv argument of chaff_solve holds */
+    int32_t reserved;         /* must be 0 */
 } chaff_solve_opts;
+
+/* Preconditioner passed to chaff_solve as Pinv.
+ *   CHAFF_PRECOND_BLOCK   [N][7][7] inverse self blocks from chaff_fill_Z
+ *                         (the block-diagonal preconditioner of Sec. II-B);
+ *   CHAFF_PRECOND_CLUSTER the buffer of chaff_cluster_precond (inverse
+ *                         diagonal blocks of groups of 8 nearby wires). */
+typedef enum { CHAFF_PRECOND_BLOCK = 0, CHAFF_PRECOND_CLUSTER = 1 } chaff_precond;
 
 /* Krylov method of each refinement cycle.  GMRES(m) with classical
  * Gram-Schmidt applied twice; COCG = conjugate-orthogonal CG, valid because
  * Z and its block-diagonal inverse are complex symmetric (bilinear a^T b),
- * with five vectors and no restart inside a cycle.  CHAFF_COCG restarts the
+ * with four vectors and no restart inside a cycle.  CHAFF_COCG restarts the
  * recurrence at every refinement checkpoint; CHAFF_COCG_RR keeps the search
  * direction and only replaces the recursive residual by the FP64 true one. */
 typedef enum { CHAFF_GMRES = 0, CHAFF_COCG = 1, CHAFF_COCG_RR = 2 } chaff_method;
@@ -170,7 +180,8 @@ typedef struct {
 } chaff_solve_stats;
 
 size_t chaff_solve_workspace_bytes(chaff_cloud c, const chaff_solve_opts* o, int64_t n_rhs);
-/*   Z, Pinv  from chaff_fill_Z with the same prec (COCG needs both symmetric: they are).
+/*   Z        from chaff_fill_Z; Pinv the preconditioner named by o->precond
+ *            (same prec; COCG needs both symmetric: they are).
  *   restart  GMRES cycle length, or the step cap of one COCG cycle.
  *   k_hat, e_hat [R][3] double: propagation direction and polarisation (unit).
  *   X        [N*7][R] complex double, caller order; input guess if use_x0 == 1.
@@ -181,6 +192,34 @@ chaff_status chaff_solve(chaff_cloud c, const chaff_solve_opts* o, const void* Z
                          const void* Pinv, const double* k_hat, const double* e_hat,
                          int64_t n_rhs, void* X, void* ws, size_t ws_bytes,
                          chaff_solve_stats* st, double* rel_res, chaff_stream stream);
+
+/* ------------------------------------------------------------------ cluster preconditioner
+ * The block-diagonal preconditioner of Sec. II-B taken over groups of nearby
+ * wires.  Clusters are runs of CHAFF_CLUSTER_WIRES consecutive wires of one
+ * cloud in the internal order (wires sorted by cloud, Morton code of their
+ * neighbour-search cell, caller index); the last cluster of a cloud may be
+ * shorter.  A cluster's block is the inverse, computed in FP64 with partial
+ * pivoting, of the cluster's (7 w x 7 w) diagonal submatrix of Z, padded to
+ * CHAFF_CLUSTER_ROWS x CHAFF_CLUSTER_ROWS with the identity.  Each block is
+ * complex symmetric, as Z is, so COCG may use it.
+ *
+ * Buffer M (device, 256-byte aligned, chaff_cluster_precond_bytes):
+ *   [n_clusters] { int32 first wire (internal index), int32 wires }, padded
+ *   to a multiple of 256 bytes, then [n_clusters][56][56] complex (prec),
+ *   row-major, rows and columns in the cluster's internal wire order.
+ * It is tied to the handle it was built for and to Z of the same prec. */
+#define CHAFF_CLUSTER_WIRES 8
+#define CHAFF_CLUSTER_ROWS 56
+int64_t chaff_cluster_count(chaff_cloud c);   /* number of clusters; -1 for a NULL handle */
+size_t chaff_cluster_precond_bytes(chaff_cloud c, chaff_prec prec);   /* 0 on a bad argument */
+/* Builds M from Z (chaff_fill_Z, same prec).  Host-synchronising; returns
+ * CHAFF_ESINGULAR if a cluster block has a zero pivot (M is then unusable). */
+chaff_status chaff_cluster_precond(chaff_cloud c, chaff_prec prec, const void* Z, void* M,
+                                   chaff_stream stream);
+/* Y = M X on the internal order: X, Y [N*7][s] complex (prec), row-major,
+ * distinct buffers. */
+chaff_status chaff_cluster_apply(chaff_cloud c, chaff_prec prec, const void* M, const void* X,
+                                 void* Y, int64_t s, chaff_stream stream);
 
 /* Excitation alone: U [N*7][R] complex double (caller order), eq. (4) without
  * its -(j/(w mu0)) factor, closed-form triangle transform. */

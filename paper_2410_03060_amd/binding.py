@@ -50,7 +50,8 @@ class CloudInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("restart", C.c_int32),
                 ("max_cycles", C.c_int32), ("use_x0", C.c_int32), ("prec", C.c_int32),
-                ("spmm_variant", C.c_int32), ("method", C.c_int32)]
+                ("spmm_variant", C.c_int32), ("method", C.c_int32), ("precond", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class KernelTime(C.Structure):
@@ -106,6 +107,11 @@ EXPORTS = {
     "chaff_mlp_guess_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int64]),
     "chaff_mlp_guess": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "chaff_cluster_count": (C.c_int64, [C.c_void_p]),
+    "chaff_cluster_precond_bytes": (C.c_size_t, [C.c_void_p, C.c_int]),
+    "chaff_cluster_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chaff_cluster_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.c_void_p]),
     "chaff_last_error": (C.c_char_p, []),
     "chaff_version": (C.c_char_p, []),
 }
@@ -295,11 +301,51 @@ def fill_Z(cl: Cloud, prec: int = C64, with_pinv: bool = True):
 
 
 GMRES, COCG, COCG_RR = 0, 1, 2
+PRECOND_BLOCK, PRECOND_CLUSTER = 0, 1
+CLUSTER_WIRES, CLUSTER_ROWS = 8, 56
 
 
 def solve_opts(tol=1e-6, inner_tol=1e-4, restart=30, max_cycles=50, use_x0=0, prec=C64,
-               spmm_variant=-1, method=GMRES) -> SolveOpts:
-    return SolveOpts(tol, inner_tol, restart, max_cycles, int(use_x0), prec, spmm_variant, method)
+               spmm_variant=-1, method=GMRES, precond=PRECOND_BLOCK) -> SolveOpts:
+    return SolveOpts(tol, inner_tol, restart, max_cycles, int(use_x0), prec, spmm_variant, method,
+                     int(precond), 0)
+
+
+def cluster_count(cl: Cloud) -> int:
+    return int(lib().chaff_cluster_count(cl.handle))
+
+
+def cluster_precond(cl: Cloud, Z, prec: int = C64):
+    """Cluster block-Jacobi preconditioner buffer (chaff_cluster_precond): uint8 [bytes]."""
+    nbytes = lib().chaff_cluster_precond_bytes(cl.handle, prec)
+    if nbytes == 0:
+        raise ChaffError(EINVAL, last_error() or "bad cluster preconditioner arguments")
+    M = torch.empty(nbytes, dtype=torch.uint8, device=cl.device)
+    _check(lib().chaff_cluster_precond(cl.handle, prec, _ptr(Z), _ptr(M), _stream()))
+    return M
+
+
+def cluster_table(cl: Cloud, M):
+    """[n_clusters, 2] int32 view (first internal wire, wires) of a preconditioner buffer."""
+    n = cluster_count(cl)
+    return M[:n * 8].view(torch.int32).view(n, 2)
+
+
+def cluster_blocks(cl: Cloud, M, prec: int = C64):
+    """[n_clusters, 56, 56] complex view of the inverse blocks of a preconditioner buffer."""
+    n = cluster_count(cl)
+    off = (n * 8 + 255) // 256 * 256
+    dt = torch.complex64 if prec == C64 else torch.complex128
+    esz = 8 if prec == C64 else 16
+    return M[off:off + n * CLUSTER_ROWS * CLUSTER_ROWS * esz].view(dt).view(n, CLUSTER_ROWS, CLUSTER_ROWS)
+
+
+def cluster_apply(cl: Cloud, M, X, prec: int = C64, Y=None):
+    """Y = M X on the internal order (chaff_cluster_apply); X is [N*7, s]."""
+    if Y is None:
+        Y = torch.empty_like(X)
+    _check(lib().chaff_cluster_apply(cl.handle, prec, _ptr(M), _ptr(X), _ptr(Y), X.shape[1], _stream()))
+    return Y
 
 
 def solve(cl: Cloud, Z, Pinv, k_hat, e_hat, opts: SolveOpts | None = None, x0=None,

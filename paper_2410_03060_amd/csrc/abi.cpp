@@ -96,6 +96,11 @@ chaff_status mlp_targets(Cloud* c, chaff_prec prec, const void* Pinv, const doub
 size_t mlp_guess_workspace_bytes(const Cloud* c, int64_t R);
 chaff_status mlp_guess(Cloud* c, chaff_prec prec, const void* Pinv, const float* theta, const double* k_hat,
                        const double* e_hat, int64_t R, void* X, void* ws, size_t ws_bytes, hipStream_t st);
+int64_t cluster_count(const Cloud* c);
+size_t cluster_buffer_bytes(const Cloud* c, chaff_prec prec);
+chaff_status cluster_precond(Cloud* c, chaff_prec prec, const void* Z, void* M, hipStream_t st);
+chaff_status cluster_apply_public(Cloud* c, chaff_prec prec, const void* M, const void* X, void* Y, int64_t s,
+                                  hipStream_t st);
 
 }  // namespace chaff
 
@@ -324,6 +329,9 @@ static chaff_status check_opts(const chaff_solve_opts* o) {
     if (o->method != CHAFF_GMRES && o->method != CHAFF_COCG && o->method != CHAFF_COCG_RR)
         return fail(CHAFF_EINVAL, "method must be CHAFF_GMRES, CHAFF_COCG or CHAFF_COCG_RR");
     if (o->method != CHAFF_GMRES && o->restart > 1000000) return fail(CHAFF_EINVAL, "restart too large");
+    if (o->reserved != 0) return fail(CHAFF_EINVAL, "reserved must be 0");
+    if (o->precond != CHAFF_PRECOND_BLOCK && o->precond != CHAFF_PRECOND_CLUSTER)
+        return fail(CHAFF_EINVAL, "precond must be CHAFF_PRECOND_BLOCK or CHAFF_PRECOND_CLUSTER");
     return CHAFF_OK;
 }
 
@@ -340,11 +348,40 @@ chaff_status chaff_solve(chaff_cloud h, const chaff_solve_opts* o, const void* Z
     chaff_status s = check_opts(o);
     if (s != CHAFF_OK) return s;
     if (!Z || !Pinv) return fail(CHAFF_EINVAL, "Z and Pinv are required");
+    if (o->precond == CHAFF_PRECOND_CLUSTER && ((uintptr_t)Pinv % 256) != 0)
+        return fail(CHAFF_EINVAL, "the cluster preconditioner buffer must be 256-byte aligned");
     if (!k_hat || !e_hat || !X || !ws) return fail(CHAFF_EINVAL, "NULL k_hat/e_hat/X/ws");
     if (n_rhs < 1 || n_rhs > 65535) return fail(CHAFF_EINVAL, "n_rhs must be in [1, 65535]");
     size_t need = solve_workspace_bytes(&h->c, o, n_rhs);
     if (ws_bytes < need) return fail(CHAFF_EWORKSPACE, "solve workspace too small: need " + std::to_string(need));
     return solve(&h->c, o, Z, Pinv, k_hat, e_hat, n_rhs, X, ws, ws_bytes, st, rel_res, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+int64_t chaff_cluster_count(chaff_cloud h) { return h ? cluster_count(&h->c) : -1; }
+
+size_t chaff_cluster_precond_bytes(chaff_cloud h, chaff_prec prec) {
+    if (!h || (prec != CHAFF_C64 && prec != CHAFF_C128)) return 0;
+    return cluster_buffer_bytes(&h->c, prec);
+}
+
+chaff_status chaff_cluster_precond(chaff_cloud h, chaff_prec prec, const void* Z, void* M, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !Z || !M) return fail(CHAFF_EINVAL, "NULL argument");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
+    if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
+    return cluster_precond(&h->c, prec, Z, M, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_cluster_apply(chaff_cloud h, chaff_prec prec, const void* M, const void* X, void* Y, int64_t s,
+                                 chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !M || !X || !Y) return fail(CHAFF_EINVAL, "NULL argument");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
+    if (s < 1 || s > 65535) return fail(CHAFF_EINVAL, "s must be in [1, 65535]");
+    if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
+    return cluster_apply_public(&h->c, prec, M, X, Y, s, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
 

@@ -9,6 +9,7 @@
 // product reads Z once for every right-hand side, while dot products are
 // reduced per cloud over fixed row chunks in a fixed order (deterministic).
 #include "common.hpp"
+#include "precond.hpp"
 #include "prof.hpp"
 
 #include <algorithm>
@@ -535,7 +536,7 @@ __global__ void k_excitation(const Wire* __restrict__ wires, const int32_t* __re
 struct Chunk {
     int64_t w0, w1;      // wire range (internal order), within one cloud
     int32_t cloud;
-    int32_t pad;
+    int32_t cl0;         // solver chunks: cluster that starts at w0 (chunks are cluster-aligned)
 };
 
 constexpr int RB = 256;  // threads per reduction block
@@ -1116,6 +1117,114 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
     if (threadIdx.x < ST && r < s) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + r] = v2;
 }
 
+// Cluster preconditioner form of k_cg_update: r -= alpha q, then z = M r per
+// cluster (M the cluster's 56 x 56 inverse block), written over q, with the
+// partial r^T z and ||r||^2.  One workgroup walks its chunk's clusters; the
+// updated residual rows of a cluster are staged in LDS, and with 64-column
+// tiles each wave forms 14 rows of z from wave-uniform reads of the block.
+template <typename CZ, typename C, int ST>
+__global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
+                                                     const CZ* __restrict__ Mb, C* qz, C* __restrict__ rv, int64_t s,
+                                                     c128* __restrict__ part, int nslot, int slot0) {
+    using R = typename real_of<C>::type;
+    constexpr int NSUB = RB / ST;
+    constexpr int RPT = (CLR + NSUB - 1) / NSUB;
+    constexpr bool FULL = NSUB * RPT == CLR;
+    // the block is staged in LDS for complex64 (25 KB); complex128 reads it from memory
+    constexpr bool STAGED = sizeof(CZ) == sizeof(c64);
+    // the residual tile, reused for the final column reduction (RB complex doubles)
+    constexpr int RS_N = std::max<int>(CLR * ST, RB * (int)(sizeof(c128) / sizeof(cplx<R>)));
+    __shared__ __align__(16) cplx<R> rs[RS_N];
+    __shared__ __align__(16) CZ ms[STAGED ? CLR2 : 2];
+    const Chunk ch = chunks[blockIdx.x];
+    const int col = threadIdx.x % ST;
+    const int rsub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
+    const int64_t r = (int64_t)blockIdx.y * ST + col;
+    const bool live = r < s;
+    const int64_t rc = live ? r : s - 1;   // loads of idle lanes stay inside the vectors
+    cplx<R> na = {0, 0};
+    if (live) {
+        const CgState& S = cg[(int64_t)ch.cloud * s + r];
+        na = cplx<R>{-(R)S.alpha_re, -(R)S.alpha_im};
+    }
+    c128 rz = {0, 0}, rr = {0, 0};
+    int64_t kc = ch.cl0;
+    for (int64_t w = ch.w0; w < ch.w1; w += CLW, ++kc) {
+        const int nr = (int)std::min<int64_t>(CLW, ch.w1 - w) * NB;
+        const int64_t row0 = w * NB;
+        const CZ* mb = Mb + kc * CLR2;
+        if (STAGED) stage_block<CZ, RB>(ms, mb);
+        // r -= alpha q: every load is issued before any arithmetic
+        cplx<R> res[RPT], qv[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int rho = std::min(rsub * RPT + j, nr - 1);
+            const int64_t o = (row0 + rho) * s + rc;
+            res[j] = rv[o];
+            qv[j] = qz[o];
+        }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int rho = rsub * RPT + j;
+            const bool ok = live && rho < nr;
+            cplx<R> v = res[j];
+            cfma(v, na, qv[j]);
+            if (!ok) v = cplx<R>{0, 0};
+            res[j] = v;
+            if (ok) {
+                rv[(row0 + rho) * s + r] = v;
+                rr.re += (double)v.re * v.re + (double)v.im * v.im;
+            }
+            if (FULL || rho < CLR) rs[rho * ST + col] = v;
+        }
+        __syncthreads();
+        cplx<R> acc[RPT];
+        cluster_rows<R, CZ, ST, RPT, FULL, STAGED>(ms, mb, rs, col, rsub, acc);
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int rho = rsub * RPT + j;
+            if (live && rho < nr) {
+                qz[(row0 + rho) * s + r] = acc[j];
+                cfma(rz, ccast<c128>(res[j]), ccast<c128>(acc[j]));
+            }
+        }
+        __syncthreads();
+    }
+    c128* red = reinterpret_cast<c128*>(rs);
+    c128 v = block_col_reduce(rz, ST, red);
+    if (threadIdx.x < ST && live) part[((int64_t)blockIdx.x * nslot + slot0) * s + r] = v;
+    c128 v2 = block_col_reduce(rr, ST, red);
+    if (threadIdx.x < ST && live) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + r] = v2;
+}
+
+// Cluster preconditioner form of k_cg_pdir: z was stored by k_cg_update_cl.
+//   x += alpha p_old (deferred; skipped with pend = 0), p = z + beta p_old.
+template <typename C, int ST>
+__global__ __launch_bounds__(RB) void k_cg_pdir_z(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
+                                                  const C* __restrict__ z, C* __restrict__ p, C* __restrict__ x,
+                                                  int64_t s, int pend) {
+    using R = typename real_of<C>::type;
+    const Chunk ch = chunks[blockIdx.x];
+    const int rsub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
+    const int64_t r = (int64_t)blockIdx.y * ST + threadIdx.x % ST;
+    if (r >= s) return;
+    const CgState& S = cg[(int64_t)ch.cloud * s + r];
+    const cplx<R> a = {pend ? (R)S.alpha_re : (R)0, pend ? (R)S.alpha_im : (R)0};
+    const cplx<R> b = {(R)S.beta_re, (R)S.beta_im};
+    for (int64_t row = ch.w0 * NB + rsub; row < ch.w1 * NB; row += RB / ST) {
+        const int64_t o = row * s + r;
+        const cplx<R> pv = p[o];
+        cplx<R> zv = z[o];
+        if (pend) {
+            cplx<R> xv = x[o];
+            cfma(xv, a, pv);
+            x[o] = xv;
+        }
+        cfma(zv, b, pv);
+        p[o] = zv;
+    }
+}
+
 // After the update: new rho = r^T z, recursive norm; convergence and checkpoint
 // flags; beta for p = z + beta p.  mode 0: first step of a run (beta = 0);
 // mode 1: ordinary step; mode 2: step right after a residual replacement
@@ -1211,7 +1320,11 @@ struct SolveLayout {
 
 // Wires per reduction chunk (about 2048 chunks in total): streaming kernels
 // reduce per chunk; COCG's product uses its own small tiles (see k_cocg_spmm).
-static int64_t chunk_wires(int64_t n, int /*method*/) { return std::max<int64_t>(32, (n + 2047) / 2048); }
+// Wires per solver chunk: a multiple of the cluster width, so that chunks
+// starting at a cloud's first wire never split a cluster.
+static int64_t chunk_wires(int64_t n, int /*method*/) {
+    return (int64_t)align_up((size_t)std::max<int64_t>(32, (n + 2047) / 2048), CLW);
+}
 constexpr int TILE_GROUP = 256;   // tiles per first-stage group of the sigma reduction
 
 struct SolveShape {
@@ -1369,6 +1482,19 @@ static void launch_cg_pdir(const SolveShape& sh, SolveLayout& L, const CZ* Pinv,
                        Pinv, r, p, x, sh.s, pend);
 }
 template <typename CZ, typename C, int ST>
+static void launch_cg_update_cl(const SolveShape& sh, SolveLayout& L, const CZ* Mb, C* qz, C* r, hipStream_t st) {
+    const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
+    hipLaunchKernelGGL((k_cg_update_cl<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks,
+                       (const CgState*)L.cg, Mb, qz, r, sh.s, L.part, sh.nslot, 0);
+}
+template <typename C, int ST>
+static void launch_cg_pdir_z(const SolveShape& sh, SolveLayout& L, const C* z, C* p, C* x, int pend,
+                             hipStream_t st) {
+    const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
+    hipLaunchKernelGGL((k_cg_pdir_z<C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const CgState*)L.cg,
+                       z, p, x, sh.s, pend);
+}
+template <typename CZ, typename C, int ST>
 static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& L, const CZ* Z, const C* p, C* q,
                              hipStream_t st) {
     const int ct = (int)((sh.s + ST - 1) / ST);
@@ -1395,7 +1521,7 @@ static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& 
 template <typename C>
 static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc, const SolveLayout& L,
                                  std::vector<int32_t>& colmap, const std::vector<int32_t>& keep, int64_t s_full,
-                                 C* xc, C* r, C* p, C* q, hipStream_t st) {
+                                 C* xc, C* r, C* p, C* q, bool q_live, hipStream_t st) {
     const int64_t rows = cs.rows, s_old = cs.s, s_new = (int64_t)keep.size();
     ProfScope ps("cocg_compact", st, (double)rows * s_old * sizeof(C) * 5 + 2.0 * rows * s_new * sizeof(C) * 3);
     hipLaunchKernelGGL((k_cg_xpend<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
@@ -1406,11 +1532,19 @@ static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc
                        s_full, xc, L.x);
     CHAFF_LAUNCH_CHECK();
     CHAFF_HIP(hipMemcpyAsync(L.keep, keep.data(), s_new * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    for (C* v : {r, p}) {
+    // xc was flushed and zeroed above: it is the staging buffer of the gathers
+    // and is cleared again afterwards.
+    for (C* v : {r, p, q}) {
+        if (v == q && !q_live) continue;   // q is rebuilt by the next product
         hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)v, rows,
-                           s_old, (const int32_t*)L.keep, s_new, q);
+                           s_old, (const int32_t*)L.keep, s_new, xc);
         CHAFF_LAUNCH_CHECK();
-        CHAFF_HIP(hipMemcpyAsync(v, q, (size_t)rows * s_new * sizeof(C), hipMemcpyDeviceToDevice, st));
+        CHAFF_HIP(hipMemcpyAsync(v, xc, (size_t)rows * s_new * sizeof(C), hipMemcpyDeviceToDevice, st));
+    }
+    {
+        const int64_t words = rows * s_old * (int64_t)sizeof(C) / 4;
+        hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(words)), dim3(256), 0, st, (uint32_t*)xc, words);
+        CHAFF_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL((k_gather_sys<CgState>), dim3(blocks_for((int64_t)cs.n_clouds * s_new, 64)), dim3(64), 0, st,
                        (const CgState*)L.cg, cs.n_clouds, s_old, (const int32_t*)L.keep, s_new, L.cg2);
@@ -1461,6 +1595,11 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     C* q = V + 3 * vs;
     const bool use_rr = o->method == CHAFF_COCG_RR;
     const bool compact = !use_rr && s > 1;
+    // cluster preconditioner: z = M r is formed by the update and kept in q
+    const bool clus = o->precond == CHAFF_PRECOND_CLUSTER;
+    const CZ* Mb = clus ? reinterpret_cast<const CZ*>(reinterpret_cast<const char*>(Pinv) +
+                                                      cluster_table_bytes(cluster_count(c)))
+                        : nullptr;
     SolveShape cs = sh;            // current shape (columns shrink under compaction)
     SolveLayout Lc = L;            // current tile set
     std::vector<int32_t> colmap(s);
@@ -1489,7 +1628,19 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     std::vector<int32_t> flags;
     for (int k = 0; k <= o->restart; ++k) {
         const int wst = spmm_tile_width(cs.s);
-        {   // r -= alpha q, r^T (P r), ||r||^2 (alpha = 0 on entry)
+        if (clus) {   // r -= alpha q, z = M r (over q), r^T z, ||r||^2
+            ProfScope pu("k_cg_update", st,
+                         (4.0 * rows * cs.s) * sizeof(C) + (double)cluster_count(c) * CLR2 * sizeof(CZ));
+            switch (wst) {
+                case 1: launch_cg_update_cl<CZ, C, 1>(cs, Lc, Mb, q, r, st); break;
+                case 2: launch_cg_update_cl<CZ, C, 2>(cs, Lc, Mb, q, r, st); break;
+                case 4: launch_cg_update_cl<CZ, C, 4>(cs, Lc, Mb, q, r, st); break;
+                case 8: launch_cg_update_cl<CZ, C, 8>(cs, Lc, Mb, q, r, st); break;
+                case 16: launch_cg_update_cl<CZ, C, 16>(cs, Lc, Mb, q, r, st); break;
+                case 32: launch_cg_update_cl<CZ, C, 32>(cs, Lc, Mb, q, r, st); break;
+                default: launch_cg_update_cl<CZ, C, 64>(cs, Lc, Mb, q, r, st); break;
+            }
+        } else {   // r -= alpha q, r^T (P r), ||r||^2 (alpha = 0 on entry)
             ProfScope pu("k_cg_update", st, (3.0 * rows * cs.s) * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
             const C* qc = q;
             switch (wst) {
@@ -1530,7 +1681,7 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
                 if (live) keep.push_back((int32_t)j);
             }
             if (!keep.empty() && (int64_t)keep.size() <= wst / 2) {
-                chaff_status cst = cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, p, q, st);
+                chaff_status cst = cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, p, q, clus, st);
                 if (cst != CHAFF_OK) return cst;
                 pending_applied = true;
                 if (g_verbose)
@@ -1539,7 +1690,21 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         }
         mode = 1;
         ++iters;
-        {   // x += alpha p_old (deferred), p = P r + beta p_old
+        if (clus) {   // x += alpha p_old (deferred), p = z + beta p_old
+            const int pend = pending_applied ? 0 : 1;
+            pending_applied = false;
+            ProfScope pp("k_cg_p", st, (3.0 + 2.0 * pend) * rows * cs.s * sizeof(C));
+            const C* zc = q;
+            switch (spmm_tile_width(cs.s)) {
+                case 1: launch_cg_pdir_z<C, 1>(cs, Lc, zc, p, xc, pend, st); break;
+                case 2: launch_cg_pdir_z<C, 2>(cs, Lc, zc, p, xc, pend, st); break;
+                case 4: launch_cg_pdir_z<C, 4>(cs, Lc, zc, p, xc, pend, st); break;
+                case 8: launch_cg_pdir_z<C, 8>(cs, Lc, zc, p, xc, pend, st); break;
+                case 16: launch_cg_pdir_z<C, 16>(cs, Lc, zc, p, xc, pend, st); break;
+                case 32: launch_cg_pdir_z<C, 32>(cs, Lc, zc, p, xc, pend, st); break;
+                default: launch_cg_pdir_z<C, 64>(cs, Lc, zc, p, xc, pend, st); break;
+            }
+        } else {   // x += alpha p_old (deferred), p = P r + beta p_old
             const int pend = pending_applied ? 0 : 1;
             pending_applied = false;
             ProfScope pp("k_cg_p", st, (3.0 + 2.0 * pend) * rows * cs.s * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
@@ -1597,6 +1762,10 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     SolveLayout L = carve_solve(ws, ws_bytes, sh);
     if (L.bytes > ws_bytes)
         return fail(CHAFF_EWORKSPACE, "solve workspace too small: need " + std::to_string(L.bytes));
+    if (o->precond == CHAFF_PRECOND_CLUSTER) {
+        chaff_status ck = cluster_check_table(c, Pinv, st);
+        if (ck != CHAFF_OK) return ck;
+    }
     const int64_t rows = sh.rows, vs = rows * s, nsys = sh.nsys;
     C* V = static_cast<C*>(L.V);
     C* W = static_cast<C*>(L.W);
@@ -1609,10 +1778,13 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         const int64_t cw = chunk_wires(c->n, o->method);
         std::vector<Chunk> ch;
         std::vector<int32_t> off(sh.n_clouds + 1, 0);
+        int64_t cl_base = 0;   // clusters of the clouds before k
         for (int k = 0; k < sh.n_clouds; ++k) {
             off[k] = (int32_t)ch.size();
             for (int64_t w0 = c->cloud_off[k]; w0 < c->cloud_off[k + 1]; w0 += cw)
-                ch.push_back(Chunk{w0, std::min<int64_t>(w0 + cw, c->cloud_off[k + 1]), k, 0});
+                ch.push_back(Chunk{w0, std::min<int64_t>(w0 + cw, c->cloud_off[k + 1]), k,
+                                   (int32_t)(cl_base + (w0 - c->cloud_off[k]) / CLW)});
+            cl_base += (c->cloud_off[k + 1] - c->cloud_off[k] + CLW - 1) / CLW;
         }
         off[sh.n_clouds] = (int32_t)ch.size();
         if (!ch.empty())
@@ -1643,6 +1815,11 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     if (o->use_x0 == 1) {
         hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)Xout,
                            (const int32_t*)c->perm, c->n, s, L.x, 0);
+    } else if (o->use_x0 == 2 && o->precond == CHAFF_PRECOND_CLUSTER) {
+        // cluster guess x0 = M u (FP64 vectors, stored blocks)
+        sst0 = cluster_apply_launch(c, (chaff_prec)o->prec, Pinv, L.b, true, L.x, true, false, s, st,
+                                    "guess_cluster");
+        if (sst0 != CHAFF_OK) return sst0;
     } else if (o->use_x0 == 2) {
         // block-Jacobi guess x0 = Pinv u (FP64 vectors, stored Pinv)
         sst0 = spmm_launch<CZ, c128, c128, 0, true>(nullptr, nullptr, Pinv, (const c128*)L.b, (const c128*)nullptr,
@@ -1745,8 +1922,12 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
             ++iters;
             C* vj = V + (int64_t)j * vs;
             // W = Z P v_j
-            sst = spmm_launch<CZ, C, C, 0, true>(nullptr, nullptr, Pinv, vj, (const C*)nullptr, T, c->n, c->n, s, -1, st,
-                                                 "precond");
+            if (o->precond == CHAFF_PRECOND_CLUSTER)
+                sst = cluster_apply_launch(c, (chaff_prec)o->prec, Pinv, vj, sizeof(C) == 16, T, sizeof(C) == 16,
+                                           false, s, st, "precond");
+            else
+                sst = spmm_launch<CZ, C, C, 0, true>(nullptr, nullptr, Pinv, vj, (const C*)nullptr, T, c->n, c->n, s,
+                                                     -1, st, "precond");
             if (sst != CHAFF_OK) return sst;
             sst = spmm_launch<CZ, C, C, 0, false>(c->row_ptr, c->col_idx, Z, T, (const C*)nullptr, W, c->n, c->nnzb,
                                                   s, o->spmm_variant, st);
@@ -1815,8 +1996,12 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         hipLaunchKernelGGL((k_combine<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const C*)V, vs, nv_max,
                            (const c128*)L.Y, (const int32_t*)c->wire_cloud, sh.n_clouds, rows, s, T);
         CHAFF_LAUNCH_CHECK();
-        sst = spmm_launch<CZ, C, c128, 2, true>(nullptr, nullptr, Pinv, T, (const c128*)nullptr, L.x, c->n, c->n, s,
-                                                -1, st, "precond_update_fp64");
+        if (o->precond == CHAFF_PRECOND_CLUSTER)
+            sst = cluster_apply_launch(c, (chaff_prec)o->prec, Pinv, T, sizeof(C) == 16, L.x, true, true, s, st,
+                                       "precond_update_fp64");
+        else
+            sst = spmm_launch<CZ, C, c128, 2, true>(nullptr, nullptr, Pinv, T, (const c128*)nullptr, L.x, c->n, c->n,
+                                                    s, -1, st, "precond_update_fp64");
         if (sst != CHAFF_OK) return sst;
     }
     // --- output (caller order)

@@ -159,3 +159,28 @@ def test_solve_rejects_bad_initial_guess_mode(B):
     o = B.solve_opts(use_x0=3)
     assert L.chaff_solve_workspace_bytes(C.c_void_p(0x1000), C.byref(o), 1) == 0
     assert "use_x0" in B.last_error()
+
+
+def test_solve_rejects_bad_preconditioner_and_reserved_field(B):
+    L = B.lib()
+    o = B.solve_opts(precond=2)
+    assert L.chaff_solve_workspace_bytes(C.c_void_p(0x1000), C.byref(o), 1) == 0
+    assert "precond" in B.last_error()
+    o = B.solve_opts()
+    o.reserved = 1
+    assert L.chaff_solve_workspace_bytes(C.c_void_p(0x1000), C.byref(o), 1) == 0
+    assert "reserved" in B.last_error()
+
+
+def test_cluster_entry_points_validate_before_any_launch(B):
+    L = B.lib()
+    H = C.c_void_p(0x1000)          # never dereferenced: every call below fails validation
+    P = C.c_void_p(0x1000)
+    assert L.chaff_cluster_count(None) == -1
+    assert L.chaff_cluster_precond_bytes(None, B.C64) == 0
+    assert L.chaff_cluster_precond(None, B.C64, P, P, None) == B.EINVAL
+    assert L.chaff_cluster_precond(H, 7, P, P, None) == B.EINVAL
+    assert L.chaff_cluster_precond(H, B.C64, P, C.c_void_p(0x1010), None) == B.EINVAL
+    assert "aligned" in B.last_error()
+    assert L.chaff_cluster_apply(H, B.C64, P, P, P, 0, None) == B.EINVAL
+    assert L.chaff_cluster_apply(H, B.C64, None, P, P, 1, None) == B.EINVAL
