@@ -79,12 +79,14 @@ CONFIGS = {
     "c3": dict(prec="c64", method="cocg", restart=2000, inner_tol=1e-5,
                desc="20,000-wire Gaussian cloud + 16 side clouds (500-5,000 wires), d_c=2 lambda, "
                     "360 azimuth incidences, one launch per stage for all 17 clouds"),
-    "c4_eval": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="mlp",
+    "c4_eval": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="mlp", precond="cluster",
                     desc="100,000 wires, uniform sphere R=40 lambda, d_c=1.5 lambda, 8 incidences, "
-                         "learned initial guess (3x128 MLP, BF16, trained on 200 solved clouds)"),
-    "c5": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="mlp",
+                         "cluster block-Jacobi preconditioner, learned initial guess (3x128 MLP, BF16, "
+                         "trained on 200 solved clouds)"),
+    "c5": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="mlp", precond="cluster",
                desc="1,000,000 wires (7M unknowns), uniform sphere R=50 lambda, d_c=1 lambda, "
-                    "64 azimuth incidences, complex64 + FP64 refinement, learned initial guess"),
+                    "64 azimuth incidences, complex64 + FP64 refinement, cluster block-Jacobi "
+                    "preconditioner, learned initial guess"),
 }
 GUESSES = {"zero": 0, "bj": 2, "mlp": 1}   # bj: x0 = P u with the solve's preconditioner P
 PRECONDS = {"block": 0, "cluster": 1}
