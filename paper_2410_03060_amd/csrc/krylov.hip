@@ -1127,7 +1127,11 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
                                                      const CZ* __restrict__ Mb, C* qz, C* __restrict__ rv, int64_t s,
                                                      c128* __restrict__ part, int nslot, int slot0) {
     using R = typename real_of<C>::type;
-    constexpr int NSUB = RB / ST;
+    // 64-column tiles: two adjacent columns per lane, so every block value
+    // read from LDS serves two columns (half the LDS reads per FMA)
+    constexpr int CW = ST == 64 ? 2 : 1;
+    constexpr int TPC = ST / CW;           // lanes per row group
+    constexpr int NSUB = RB / TPC;         // row groups
     constexpr int RPT = (CLR + NSUB - 1) / NSUB;
     constexpr bool FULL = NSUB * RPT == CLR;
     // the block is staged in LDS for complex64 (25 KB); complex128 reads it from memory
@@ -1137,17 +1141,24 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
     __shared__ __align__(16) cplx<R> rs[RS_N];
     __shared__ __align__(16) CZ ms[STAGED ? CLR2 : 2];
     const Chunk ch = chunks[blockIdx.x];
-    const int col = threadIdx.x % ST;
-    const int rsub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
-    const int64_t r = (int64_t)blockIdx.y * ST + col;
-    const bool live = r < s;
-    const int64_t rc = live ? r : s - 1;   // loads of idle lanes stay inside the vectors
-    cplx<R> na = {0, 0};
-    if (live) {
-        const CgState& S = cg[(int64_t)ch.cloud * s + r];
-        na = cplx<R>{-(R)S.alpha_re, -(R)S.alpha_im};
+    const int col = (int)(threadIdx.x % TPC) * CW;
+    const int rsub = (TPC == 64) ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / TPC);
+    const int64_t r0 = (int64_t)blockIdx.y * ST + col;
+    bool live[CW];
+    int64_t rc[CW];
+    cplx<R> na[CW];
+    c128 rz[CW], rr[CW];
+#pragma unroll
+    for (int cc = 0; cc < CW; ++cc) {
+        live[cc] = r0 + cc < s;
+        rc[cc] = live[cc] ? r0 + cc : s - 1;   // loads of idle lanes stay inside the vectors
+        na[cc] = cplx<R>{0, 0};
+        if (live[cc]) {
+            const CgState& S = cg[(int64_t)ch.cloud * s + r0 + cc];
+            na[cc] = cplx<R>{-(R)S.alpha_re, -(R)S.alpha_im};
+        }
+        rz[cc] = rr[cc] = c128{0, 0};
     }
-    c128 rz = {0, 0}, rr = {0, 0};
     int64_t kc = ch.cl0;
     for (int64_t w = ch.w0; w < ch.w1; w += CLW, ++kc) {
         const int nr = (int)std::min<int64_t>(CLW, ch.w1 - w) * NB;
@@ -1155,46 +1166,58 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
         const CZ* mb = Mb + kc * CLR2;
         if (STAGED) stage_block<CZ, RB>(ms, mb);
         // r -= alpha q: every load is issued before any arithmetic
-        cplx<R> res[RPT], qv[RPT];
+        cplx<R> res[RPT * CW], qv[RPT * CW];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
             const int rho = std::min(rsub * RPT + j, nr - 1);
-            const int64_t o = (row0 + rho) * s + rc;
-            res[j] = rv[o];
-            qv[j] = qz[o];
+#pragma unroll
+            for (int cc = 0; cc < CW; ++cc) {
+                const int64_t o = (row0 + rho) * s + rc[cc];
+                res[j * CW + cc] = rv[o];
+                qv[j * CW + cc] = qz[o];
+            }
         }
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
             const int rho = rsub * RPT + j;
-            const bool ok = live && rho < nr;
-            cplx<R> v = res[j];
-            cfma(v, na, qv[j]);
-            if (!ok) v = cplx<R>{0, 0};
-            res[j] = v;
-            if (ok) {
-                rv[(row0 + rho) * s + r] = v;
-                rr.re += (double)v.re * v.re + (double)v.im * v.im;
+#pragma unroll
+            for (int cc = 0; cc < CW; ++cc) {
+                const bool ok = live[cc] && rho < nr;
+                cplx<R> v = res[j * CW + cc];
+                cfma(v, na[cc], qv[j * CW + cc]);
+                if (!ok) v = cplx<R>{0, 0};
+                if (ok) {
+                    rv[(row0 + rho) * s + r0 + cc] = v;
+                    rr[cc].re += (double)v.re * v.re + (double)v.im * v.im;
+                }
+                if (FULL || rho < CLR) rs[rho * ST + col + cc] = v;
             }
-            if (FULL || rho < CLR) rs[rho * ST + col] = v;
         }
         __syncthreads();
-        cplx<R> acc[RPT];
-        cluster_rows<R, CZ, ST, RPT, FULL, STAGED>(ms, mb, rs, col, rsub, acc);
+        cplx<R> acc[RPT * CW];
+        cluster_rows<R, CZ, ST, RPT, FULL, STAGED, CW>(ms, mb, rs, col, rsub, acc);
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
             const int rho = rsub * RPT + j;
-            if (live && rho < nr) {
-                qz[(row0 + rho) * s + r] = acc[j];
-                cfma(rz, ccast<c128>(res[j]), ccast<c128>(acc[j]));
+#pragma unroll
+            for (int cc = 0; cc < CW; ++cc) {
+                if (live[cc] && rho < nr) {   // the residual is re-read from its LDS tile
+                    qz[(row0 + rho) * s + r0 + cc] = acc[j * CW + cc];
+                    cfma(rz[cc], ccast<c128>(rs[rho * ST + col + cc]), ccast<c128>(acc[j * CW + cc]));
+                }
             }
         }
         __syncthreads();
     }
+    // column sums: lanes with equal (lane % TPC) hold the same columns
     c128* red = reinterpret_cast<c128*>(rs);
-    c128 v = block_col_reduce(rz, ST, red);
-    if (threadIdx.x < ST && live) part[((int64_t)blockIdx.x * nslot + slot0) * s + r] = v;
-    c128 v2 = block_col_reduce(rr, ST, red);
-    if (threadIdx.x < ST && live) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + r] = v2;
+#pragma unroll
+    for (int cc = 0; cc < CW; ++cc) {
+        c128 v = block_col_reduce(rz[cc], TPC, red);
+        if ((int)threadIdx.x < TPC && live[cc]) part[((int64_t)blockIdx.x * nslot + slot0) * s + r0 + cc] = v;
+        c128 v2 = block_col_reduce(rr[cc], TPC, red);
+        if ((int)threadIdx.x < TPC && live[cc]) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + r0 + cc] = v2;
+    }
 }
 
 // Cluster preconditioner form of k_cg_pdir: z was stored by k_cg_update_cl.

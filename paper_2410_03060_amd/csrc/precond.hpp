@@ -37,23 +37,33 @@ chaff_status cluster_apply_launch(const Cloud* c, chaff_prec prec, const void* M
 // staged there) or straight from memory (mb).  With FULL (NSUB * RPT == 56)
 // every row exists and no guard is emitted; with 64-column tiles the rows are
 // wave-uniform, so every read of the block is a broadcast.
-template <typename R, typename CZ, int ST, int RPT, bool FULL, bool STAGED>
+// CW adjacent columns per lane (col, col + 1, ...): each value read from the
+// block then serves CW columns.
+template <typename R, typename CZ, int ST, int RPT, bool FULL, bool STAGED, int CW = 1>
 __device__ __forceinline__ void cluster_rows(const CZ* __restrict__ ms, const CZ* __restrict__ mb,
                                              const cplx<R>* __restrict__ xs, int col, int rsub,
-                                             cplx<R> (&acc)[RPT]) {
+                                             cplx<R> (&acc)[RPT * CW]) {
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) acc[j] = cplx<R>{0, 0};
+    for (int j = 0; j < RPT * CW; ++j) acc[j] = cplx<R>{0, 0};
 #pragma unroll 2
     for (int k = 0; k < CLR; k += 2) {
-        const cplx<R> x0 = xs[k * ST + col];
-        const cplx<R> x1 = xs[(k + 1) * ST + col];
+        cplx<R> x0[CW], x1[CW];
+#pragma unroll
+        for (int cc = 0; cc < CW; ++cc) {
+            x0[cc] = xs[k * ST + col + cc];
+            x1[cc] = xs[(k + 1) * ST + col + cc];
+        }
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
             const int rho = rsub * RPT + j;
             if (FULL || rho < CLR) {
                 const CZ* row = (STAGED ? ms : mb) + rho * CLR + k;
-                cfma(acc[j], ccast<cplx<R>>(row[0]), x0);
-                cfma(acc[j], ccast<cplx<R>>(row[1]), x1);
+                const cplx<R> m0 = ccast<cplx<R>>(row[0]), m1 = ccast<cplx<R>>(row[1]);
+#pragma unroll
+                for (int cc = 0; cc < CW; ++cc) {
+                    cfma(acc[j * CW + cc], m0, x0[cc]);
+                    cfma(acc[j * CW + cc], m1, x1[cc]);
+                }
             }
         }
     }
