@@ -413,7 +413,11 @@ def main(argv=None) -> int:
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": None}
     roof["traffic"] = measured_traffic(a.config, name)
-    roof.update({"kernel": name, "symbol": KERNEL_SYMBOLS.get(name, (name,))[0], "launches": k["launches"],
+    symbols = dict(KERNEL_SYMBOLS)
+    if pc == "cluster":   # the cluster path runs its own update and direction kernels
+        symbols.update({"k_cg_update": ("chaff::k_cg_update_cl", KERNEL_SYMBOLS["k_cg_update"][1]),
+                        "k_cg_p": ("chaff::k_cg_pdir_z", KERNEL_SYMBOLS["k_cg_p"][1])})
+    roof.update({"kernel": name, "symbol": symbols.get(name, (name,))[0], "launches": k["launches"],
                  "avg_ms": k["total_ms"] / k["launches"], "work_per_launch": k["work"] / k["launches"],
                  "timing": "HIP events recorded on the launch stream around every launch in the timed steps"})
     kernels = {n: {"ms_total": round(v["total_ms"], 3), "launches": v["launches"],

@@ -1652,7 +1652,7 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     for (int k = 0; k <= o->restart; ++k) {
         const int wst = spmm_tile_width(cs.s);
         if (clus) {   // r -= alpha q, z = M r (over q), r^T z, ||r||^2
-            ProfScope pu("k_cg_update", st,
+            ProfScope pu(wst == 64 ? "k_cg_update" : "k_cg_update_narrow", st,
                          (4.0 * rows * cs.s) * sizeof(C) + (double)cluster_count(c) * CLR2 * sizeof(CZ));
             switch (wst) {
                 case 1: launch_cg_update_cl<CZ, C, 1>(cs, Lc, Mb, q, r, st); break;
@@ -1664,7 +1664,8 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
                 default: launch_cg_update_cl<CZ, C, 64>(cs, Lc, Mb, q, r, st); break;
             }
         } else {   // r -= alpha q, r^T (P r), ||r||^2 (alpha = 0 on entry)
-            ProfScope pu("k_cg_update", st, (3.0 * rows * cs.s) * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
+            ProfScope pu(wst == 64 ? "k_cg_update" : "k_cg_update_narrow", st,
+                         (3.0 * rows * cs.s) * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
             const C* qc = q;
             switch (wst) {
                 case 1: launch_cg_update<CZ, C, 1>(cs, Lc, Pinv, qc, r, st); break;
@@ -1716,7 +1717,8 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         if (clus) {   // x += alpha p_old (deferred), p = z + beta p_old
             const int pend = pending_applied ? 0 : 1;
             pending_applied = false;
-            ProfScope pp("k_cg_p", st, (3.0 + 2.0 * pend) * rows * cs.s * sizeof(C));
+            ProfScope pp(spmm_tile_width(cs.s) == 64 ? "k_cg_p" : "k_cg_p_narrow", st,
+                         (3.0 + 2.0 * pend) * rows * cs.s * sizeof(C));
             const C* zc = q;
             switch (spmm_tile_width(cs.s)) {
                 case 1: launch_cg_pdir_z<C, 1>(cs, Lc, zc, p, xc, pend, st); break;
@@ -1730,7 +1732,8 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         } else {   // x += alpha p_old (deferred), p = P r + beta p_old
             const int pend = pending_applied ? 0 : 1;
             pending_applied = false;
-            ProfScope pp("k_cg_p", st, (3.0 + 2.0 * pend) * rows * cs.s * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
+            ProfScope pp(spmm_tile_width(cs.s) == 64 ? "k_cg_p" : "k_cg_p_narrow", st,
+                         (3.0 + 2.0 * pend) * rows * cs.s * sizeof(C) + (double)sh.n * NB2 * sizeof(CZ));
             const int ws2 = spmm_tile_width(cs.s);
             const C* rc_ = r;
             switch (ws2) {
@@ -1745,7 +1748,9 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         }
         CHAFF_LAUNCH_CHECK();
         {   // q = Z p with per-tile p^T q
-            ProfScope ps("spmm", st, ((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 8.0 * (c->n + 1) +
+            // full-width launches are timed apart from the narrower ones after a compaction
+            ProfScope ps(cs.cocg_st == 64 ? "spmm" : "spmm_narrow", st,
+                         ((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 8.0 * (c->n + 1) +
                                          3.0 * rows * cs.s * sizeof(C));
             switch (cs.cocg_st) {
                 case 8: launch_cocg_spmm<CZ, C, 8>(c, cs, Lc, Z, p, q, st); break;
