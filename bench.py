@@ -170,8 +170,24 @@ def cpu_baseline(wl, n_sample: int = 2000, r_sample: int = 8):
                       f"by the wire ratio {scale:.1f}; full workload estimated at {t_full:.1f} s"}
 
 
-def fill_summary(prof):
-    """Fill rate in the timed steps: algorithmic flop (24 per Green sample) over kernel time."""
+FLOPS_FILE = os.path.join(ROOT, "profiles", "valu_flops.json")
+
+
+def executed_flop(config, kernel):
+    """Executed FP32 flop per launch from the committed VALU counter record, if its source is unchanged."""
+    try:
+        with open(FLOPS_FILE) as f:
+            ent = json.load(f).get(config, {}).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not ent or ent.get("source_sha256_16") != source_hash(ent["source"]):
+        return None
+    return ent["executed_flop_per_launch"]
+
+
+def fill_summary(prof, config=None):
+    """Fill rate in the timed steps: algorithmic flop (24 per Green sample) over kernel time, and the
+    executed FP32 flop counted by the VALU instruction counters (profiles/valu_flops.json) over the same time."""
     out = {}
     tot_w = tot_ms = 0.0
     for name in ("fill_mutual", "fill_self"):
@@ -179,7 +195,12 @@ def fill_summary(prof):
         if not k or k["total_ms"] <= 0:
             continue
         tf = k["work"] / (k["total_ms"] * 1e-3) / 1e12
-        out[name] = {"TFLOP/s": tf, "frac": tf / FP32_PEAK_TFLOPS, "ms_per_launch": k["total_ms"] / k["launches"]}
+        ms = k["total_ms"] / k["launches"]
+        out[name] = {"TFLOP/s": tf, "frac": tf / FP32_PEAK_TFLOPS, "ms_per_launch": ms}
+        ex = executed_flop(config, name) if config else None
+        if ex is not None:
+            out[name]["executed_TFLOP/s"] = ex / (ms * 1e-3) / 1e12
+            out[name]["executed_frac"] = out[name]["executed_TFLOP/s"] / FP32_PEAK_TFLOPS
         tot_w += k["work"]
         tot_ms += k["total_ms"]
     if tot_ms > 0:
@@ -452,15 +473,33 @@ def main(argv=None) -> int:
         "roofline": roof,
         "autotune": tuning,
         "kernels": kernels,
-        "fill": fill_summary(prof),
+        "fill": fill_summary(prof, a.config),
         "spmm_sweep": None,
         "memory": memory,
         "mlp": mlp_report,
         "guess_comparison": None,
         "comparator": None,
         "cpu_baseline": None,
+        "pcie_inclusive": None,
     }
     del X, sig, cl
+    # PCIe-inclusive figure (untimed for `value`): the same step with the geometry
+    # uploaded from host memory at its start and sigma copied back at its end
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    geom_h = B.upload(wl.cloud)
+    cl_h = B.build_cloud(geom_h)
+    Z_h, P_h = B.fill_Z(cl_h, prec)
+    M_h = B.cluster_precond(cl_h, Z_h, prec) if pc == "cluster" else P_h
+    x0_h = B.mlp_guess(cl_h, P_h, theta, kh, eh, prec=prec) if guess == "mlp" else None
+    opts.use_x0 = GUESSES[guess]
+    X_h, info_h = B.solve(cl_h, Z_h, M_h, kh, eh, opts, x0=x0_h)
+    sig_h = B.rcs(cl_h, X_h, -kh, eh, monostatic=True).cpu()
+    t_h = time.perf_counter() - t0
+    out["pcie_inclusive"] = {"value": int((info_h["rel_res"] <= a.tol).sum()) / t_h, "ms_per_step": t_h * 1e3,
+                             "what": "one step with the wire geometry uploaded from host memory and sigma "
+                                     "copied to host memory inside the timed interval"}
+    del geom_h, cl_h, Z_h, P_h, M_h, x0_h, X_h, sig_h
     if not a.no_sweep:
         out["spmm_sweep"] = spmm_sweep(B, geom, prec)
     if not a.no_compare and a.config in MLP_TRAINING:
