@@ -329,6 +329,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-sweep", action="store_true", help="skip the product sweep over RHS counts")
     ap.add_argument("--no-comparator", action="store_true",
                     help="skip the plain FP64 one-RHS-at-a-time solver comparison")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time the steps without the per-launch HIP events (no roofline or kernel table); "
+                         "for launch-bound workloads, where the events themselves cost a visible share")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     a = ap.parse_args(argv)
@@ -402,7 +405,7 @@ def main(argv=None) -> int:
               f"res={info['max_rel_residual']:.2e} solve={info['seconds']:.3f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     torch.cuda.reset_peak_memory_stats()
-    B.profile_enable(True)
+    B.profile_enable(not a.no_profile)
     t0 = time.perf_counter()
     solved = 0
     infos = []
@@ -422,33 +425,35 @@ def main(argv=None) -> int:
     assert np.all(np.isfinite(sig_np))
 
     # dominant kernel of the timed region and its roofline
-    ranked = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])
-    name, k = ranked[0]
-    sec = k["total_ms"] / 1e3
-    if k["unit"] == "flop":
-        ach = k["work"] / sec / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP32_PEAK_TFLOPS, "traffic": None}
-    else:
-        ach = k["work"] / sec / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None}
-    roof["traffic"] = measured_traffic(a.config, name)
-    symbols = dict(KERNEL_SYMBOLS)
-    if pc == "cluster":   # the cluster path runs its own update and direction kernels
-        symbols.update({"k_cg_update": ("chaff::k_cg_update_cl", KERNEL_SYMBOLS["k_cg_update"][1]),
-                        "k_cg_p": ("chaff::k_cg_pdir_z", KERNEL_SYMBOLS["k_cg_p"][1])})
-    roof.update({"kernel": name, "symbol": symbols.get(name, (name,))[0], "launches": k["launches"],
-                 "avg_ms": k["total_ms"] / k["launches"], "work_per_launch": k["work"] / k["launches"],
-                 "timing": "HIP events recorded on the launch stream around every launch in the timed steps"})
-    kernels = {n: {"ms_total": round(v["total_ms"], 3), "launches": v["launches"],
-                   ("GB/s" if v["unit"] == "B" else "TFLOP/s"):
-                       (round(v["work"] / (v["total_ms"] / 1e3) / (1e9 if v["unit"] == "B" else 1e12), 2)
-                        if v["work"] > 0 and v["total_ms"] > 0 else None)}
-               for n, v in ranked[:12]}
-    if a.kernels:
-        for n, v in ranked:
-            print(f"  {n:28s} {v['launches']:7d} {v['total_ms']:10.3f} ms", file=sys.stderr)
+    roof, kernels = None, None
+    if prof:
+        ranked = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])
+        name, k = ranked[0]
+        sec = k["total_ms"] / 1e3
+        if k["unit"] == "flop":
+            ach = k["work"] / sec / 1e12
+            roof = {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": ach / FP32_PEAK_TFLOPS, "traffic": None}
+        else:
+            ach = k["work"] / sec / 1e9
+            roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": None}
+        roof["traffic"] = measured_traffic(a.config, name)
+        symbols = dict(KERNEL_SYMBOLS)
+        if pc == "cluster":   # the cluster path runs its own update and direction kernels
+            symbols.update({"k_cg_update": ("chaff::k_cg_update_cl", KERNEL_SYMBOLS["k_cg_update"][1]),
+                            "k_cg_p": ("chaff::k_cg_pdir_z", KERNEL_SYMBOLS["k_cg_p"][1])})
+        roof.update({"kernel": name, "symbol": symbols.get(name, (name,))[0], "launches": k["launches"],
+                     "avg_ms": k["total_ms"] / k["launches"], "work_per_launch": k["work"] / k["launches"],
+                     "timing": "HIP events recorded on the launch stream around every launch in the timed steps"})
+        kernels = {n: {"ms_total": round(v["total_ms"], 3), "launches": v["launches"],
+                       ("GB/s" if v["unit"] == "B" else "TFLOP/s"):
+                           (round(v["work"] / (v["total_ms"] / 1e3) / (1e9 if v["unit"] == "B" else 1e12), 2)
+                            if v["work"] > 0 and v["total_ms"] > 0 else None)}
+                   for n, v in ranked[:12]}
+        if a.kernels:
+            for n, v in ranked:
+                print(f"  {n:28s} {v['launches']:7d} {v['total_ms']:10.3f} ms", file=sys.stderr)
 
     out = {
         "metric": "solved angles/sec at <=0.1 dB RCS error; fill GFLOP/s and SpMM GB/s vs peak",
