@@ -272,11 +272,13 @@ def compare_guesses(step, kinds):
     return out
 
 
-def fp64_comparator(B, geom, wl, kh, eh, tol, config, r_sample=4):
+def fp64_comparator(B, geom, wl, kh, eh, tol, config, r_sample=4, X_ours=None, sig_ours=None):
     """The plain FP64 GPU solver: complex128 fill and COCG, zero initial guess,
     one incidence per solve.  Setup (neighbour search + fill) is timed once,
     r_sample incidences are solved one by one; the workload's cost is then
-    setup + R x the mean per-incidence solve (+ RCS)."""
+    setup + R x the mean per-incidence solve (+ RCS).  With the fast path's
+    currents and sigma of the last timed step, the sampled incidences also give
+    its accuracy against this FP64 solution (relative current error, sigma in dB)."""
     import torch
     R = kh.shape[0]
     r_s = min(R, r_sample)
@@ -288,12 +290,27 @@ def fp64_comparator(B, geom, wl, kh, eh, tol, config, r_sample=4):
     t1 = time.perf_counter()
     o = B.solve_opts(tol=tol, inner_tol=1e-5, restart=5000, max_cycles=60, prec=B.C128, method=B.COCG)
     iters = []
+    refs = []
     for r in range(r_s):
         X, info = B.solve(cl, Z, P, kh[r:r + 1], eh[r:r + 1], o)
-        B.rcs(cl, X, -kh[r:r + 1], eh[r:r + 1], monostatic=True)
+        sg = B.rcs(cl, X, -kh[r:r + 1], eh[r:r + 1], monostatic=True)
         iters.append(info["iterations"])
+        if X_ours is not None:
+            refs.append((X, sg))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    accuracy = None
+    if X_ours is not None:
+        cerr, dberr = [], []
+        for r, (Xr, sg) in enumerate(refs):
+            xr = Xr[:, 0]
+            cerr.append(float(torch.linalg.vector_norm(X_ours[:, r] - xr) / torch.linalg.vector_norm(xr)))
+            so = sig_ours[:, r].double().cpu()
+            sr = sg[:, 0].double().cpu()
+            live = sr > 0   # an empty cloud scatters nothing on either side
+            dberr.append(float((10.0 * torch.log10(so[live] / sr[live])).abs().max()) if bool(live.any()) else 0.0)
+        accuracy = {"incidences": r_s, "max_rel_current_error": max(cerr), "max_rcs_error_db": max(dberr),
+                    "what": "fast path (last timed step) against this FP64 solver, per sampled incidence"}
     per = (t2 - t1) / r_s
     total = (t1 - t0) + R * per
     systems = wl.cloud.n_clouds * R
@@ -303,7 +320,7 @@ def fp64_comparator(B, geom, wl, kh, eh, tol, config, r_sample=4):
     return {"kind": "plain FP64 GPU solver: complex128 fill and COCG, zero initial guess, one incidence per solve",
             "value": systems / total, "unit": "solved angles/s", "setup_seconds": t1 - t0,
             "seconds_per_incidence": per, "incidences_sampled": r_s, "iterations": iters,
-            "speedup_of_value": None}
+            "accuracy_of_value": accuracy, "speedup_of_value": None}
 
 
 def main(argv=None) -> int:
@@ -413,6 +430,7 @@ def main(argv=None) -> int:
         cl, X, info, sig, _ = step()
         infos.append(info)
         solved += int((info["rel_res"] <= a.tol).sum())
+    X_last, sig_last = X, sig
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     B.profile_enable(False)
@@ -510,7 +528,7 @@ def main(argv=None) -> int:
     if not a.no_compare and a.config in MLP_TRAINING:
         out["guess_comparison"] = compare_guesses(step, ["zero", "bj"] + (["mlp"] if theta is not None else []))
     if not a.no_comparator:
-        out["comparator"] = fp64_comparator(B, geom, wl, kh, eh, a.tol, a.config)
+        out["comparator"] = fp64_comparator(B, geom, wl, kh, eh, a.tol, a.config, X_ours=X_last, sig_ours=sig_last)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     if out["comparator"]:

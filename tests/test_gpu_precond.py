@@ -220,3 +220,23 @@ def test_cocg_compaction_with_cluster_preconditioner(B):
     e = current_err(_np(X), _oracle_x(cloud, inc))
     say(f"  current err {e.max():.3e}")
     assert e.max() <= 1e-4
+
+
+def test_other_buffers_are_rejected_as_cluster_preconditioner(B):
+    """The host checks the first and last cluster entries before any launch:
+    the block-Jacobi inverses passed where a cluster buffer is expected fail
+    with CHAFF_EINVAL (the check reads 16 bytes of the valid buffer)."""
+    import torch
+    cloud = _clouds()["ragged_301"]
+    say(f"[precond] wrong buffer rejected: N={cloud.n}")
+    cl = B.build_cloud(cloud)
+    Z, P = B.fill_Z(cl, B.C64)
+    X = torch.zeros((7 * cloud.n, 2), dtype=torch.complex64, device="cuda")
+    with pytest.raises(B.ChaffError) as e:
+        B.cluster_apply(cl, P, X, B.C64)
+    assert e.value.status == B.EINVAL
+    inc = W.azimuth_incidences(2)
+    with pytest.raises(B.ChaffError) as e:
+        B.solve(cl, Z, P, inc.k_hat, inc.e_hat,
+                B.solve_opts(tol=1e-6, method=B.COCG, restart=100, precond=B.PRECOND_CLUSTER))
+    assert e.value.status == B.EINVAL
