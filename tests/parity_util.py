@@ -103,7 +103,8 @@ def fp32_block_check(rows, cols, Zg, Zo, rel=1e-5, floor=1e-7, row_rel=2e-6):
     rn = np.zeros(n)
     np.add.at(rd, rows, d ** 2)
     np.add.at(rn, rows, nb ** 2)
-    row_err = np.sqrt(rd) / np.sqrt(rn)
+    have = rn > 0   # rows present in the comparison (all of them, or a sample)
+    row_err = np.sqrt(rd[have]) / np.sqrt(rn[have])
     out = {"max_rel": float((d / nb).max()), "median_rel": float(np.median(d / nb)),
            "max_abs_over_diag": float((d / nd).max()), "max_row_rel": float(row_err.max()),
            "n_fail": int((~ok).sum())}

@@ -1,0 +1,160 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration the
+benchmark times: complex64 fill, cluster block-Jacobi preconditioner, COCG
+with FP64 refinement to 1e-6, every incidence of the workload in lockstep
+(the initial guess is the preconditioner's; the learned guess only changes
+the starting vector).  The oracle cannot factor these systems, so sampled
+outputs are computed one by one and compared:
+
+  * internal wire order: the oracle's cell order over the whole cloud (exact);
+  * neighbour rows of sampled wires: a brute-force FP64 distance test over the
+    whole cloud (exact);
+  * sampled mutual and self blocks: the FP32 block criterion (R21);
+  * sampled cluster blocks: within kappa * 3e-5 + 1e-6 of the oracle's inverse
+    of its own submatrix (first-order perturbation of an inverse);
+  * currents, through the residual of sampled block rows computed with the
+    oracle's blocks and excitation: ||u_i - sum_j Z_ij x_j|| <= 2 (1e-6 ||u||
+    + 2e-6 ||Z_row i|| ||x over the row's columns||) — the solver's FP64
+    residual target plus the FP32 block-row bound of R21;
+  * monostatic RCS of four incidences: the oracle's far-field functional on
+    the library's currents, <= 1e-4 dB.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mom, precond
+from paper_2410_03060_amd import workloads as W
+from parity_util import fp32_block_check, say
+
+pytestmark = pytest.mark.gpu
+
+NB = 7
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_03060_amd import binding
+    binding.lib()
+    return binding
+
+
+def _near_brute(cloud, i):
+    """Same-cloud wires j != i with ((dx*dx + dy*dy) + dz*dz) <= d_c*d_c (FP64, each step rounded)."""
+    c = cloud.center
+    k = int(np.searchsorted(cloud.cloud_off, i, side="right") - 1)
+    lo, hi = int(cloud.cloud_off[k]), int(cloud.cloud_off[k + 1])
+    d = c[lo:hi] - c[i]
+    d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    j = np.nonzero(d2 <= cloud.d_c * cloud.d_c)[0] + lo
+    return j[j != i]
+
+
+def _sub(cloud, idx):
+    return W.single_cloud(cloud.center[idx], cloud.tangent[idx], cloud.length[idx], cloud.wavelength,
+                          cloud.d_c, cloud.radius[idx])
+
+
+@pytest.mark.parametrize("config", ["c4_eval", "c5"])
+def test_full_size_sampled_parity(B, config):
+    import torch
+    wl = getattr(W, config)()
+    cloud = wl.cloud
+    R = wl.inc.k_hat.shape[0]
+    k = 2.0 * math.pi / cloud.wavelength
+    say(f"[fullsize] {config}: N={cloud.n} R={R}, complex64, cluster preconditioner, COCG")
+    cl = B.build_cloud(cloud)
+    Z, _ = B.fill_Z(cl, B.C64, with_pinv=False)
+    M = B.cluster_precond(cl, Z, B.C64)
+    X, info = B.solve(cl, Z, M, wl.inc.k_hat, wl.inc.e_hat,
+                      B.solve_opts(tol=1e-6, method=B.COCG, restart=5000, max_cycles=60, inner_tol=1e-5,
+                                   use_x0=2, precond=B.PRECOND_CLUSTER))
+    sel = np.arange(0, R, max(1, R // 4))[:4]
+    sig = B.rcs(cl, X, -wl.inc.k_hat, wl.inc.e_hat, monostatic=True)[0].cpu().numpy()[sel]
+    Xs = X[:, torch.as_tensor(sel, device=X.device)].cpu().numpy()
+    say(f"  solve: cycles {info['cycles']} iterations {info['iterations']} residual {info['max_rel_residual']:.2e}")
+    assert info["max_rel_residual"] <= 1e-6
+
+    row_ptr, col_idx, perm, _ = cl.pattern()
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(cloud.n, dtype=perm.dtype)
+    assert np.array_equal(perm, precond.cell_order(cloud))
+
+    rng = np.random.default_rng(7)
+    wires = np.sort(rng.choice(cloud.n, 48, replace=False))
+    # neighbour rows, and the blocks of those rows
+    rows_b, cols_b, pos_b = [], [], []
+    for i in wires:
+        ii = int(iperm[i])
+        e0, e1 = int(row_ptr[ii]), int(row_ptr[ii + 1])
+        cols = perm[col_idx[e0:e1]].astype(np.int64)
+        nb = np.sort(_near_brute(cloud, int(i)))
+        assert np.array_equal(np.sort(cols[cols != i]), nb)
+        rows_b += [int(i)] * (e1 - e0)
+        cols_b += cols.tolist()
+        pos_b += list(range(e0, e1))
+    rows_b, cols_b = np.array(rows_b), np.array(cols_b)
+    Zg = Z[torch.as_tensor(pos_b, device=Z.device)].cpu().numpy()
+    Zo = np.empty(Zg.shape, dtype=np.complex128)
+    off = rows_b != cols_b
+    Zo[off] = mom.mutual_blocks(cloud.center, cloud.tangent, cloud.length, cloud.radius, rows_b[off], cols_b[off], k)
+    Zo[~off] = mom.self_blocks(cloud.length[rows_b[~off]], cloud.radius[rows_b[~off]], k)
+    figs, ok = fp32_block_check(rows_b, cols_b, Zg, Zo)
+    say(f"  {len(wires)} rows, {len(rows_b)} blocks: {figs}")
+    assert ok
+
+    # residual of the sampled rows with the oracle's blocks and excitation (incidences sel)
+    kh, eh = wl.inc.k_hat[sel], wl.inc.e_hat[sel]
+    unorm = np.zeros(len(sel))
+    for s0 in range(0, cloud.n, 100_000):
+        u = mom.excitation(_sub(cloud, np.arange(s0, min(s0 + 100_000, cloud.n))), kh, eh)
+        unorm += np.sum(np.abs(u) ** 2, axis=0)
+    unorm = np.sqrt(unorm)
+    worst = 0.0
+    for i in wires:
+        m = rows_b == i
+        cols, Zr = cols_b[m], Zo[m]
+        u_i = mom.excitation(_sub(cloud, np.array([i])), kh, eh)
+        xr = np.stack([Xs[NB * j:NB * j + NB] for j in cols])          # [blocks, 7, |sel|]
+        r_i = u_i - np.einsum("bqk,bkr->qr", Zr, xr)
+        bound = 1e-6 * unorm + 2e-6 * np.linalg.norm(Zr) * np.linalg.norm(xr.reshape(-1, len(sel)), axis=0)
+        ratio = np.linalg.norm(r_i, axis=0) / bound
+        worst = max(worst, float(ratio.max()))
+    say(f"  sampled-row residual / bound: max {worst:.3f}")
+    assert worst <= 2.0
+
+    # cluster blocks against the oracle's inverse of their own submatrix
+    groups = precond.clusters(cloud, 8)
+    ks = np.sort(rng.choice(len(groups), 12, replace=False))
+    Mg = B.cluster_blocks(cl, M, B.C64)[torch.as_tensor(ks, device=Z.device)].cpu().numpy().astype(np.complex128)
+    worst_c = 0.0
+    for t, kc in enumerate(ks):
+        g = groups[kc]
+        m = len(g)
+        D = np.zeros((NB * m, NB * m), dtype=np.complex128)
+        D_self = mom.self_blocks(cloud.length[g], cloud.radius[g], k)
+        for a in range(m):
+            D[NB * a:NB * a + NB, NB * a:NB * a + NB] = D_self[a]
+        nbrs = [set(_near_brute(cloud, int(g[a])).tolist()) for a in range(m)]
+        near = [(a, b) for a in range(m) for b in range(m) if a != b and int(g[b]) in nbrs[a]]
+        if near:
+            I = np.array([g[a] for a, _ in near])
+            J = np.array([g[b] for _, b in near])
+            blk = mom.mutual_blocks(cloud.center, cloud.tangent, cloud.length, cloud.radius, I, J, k)
+            for (a, b), zb in zip(near, blk):
+                D[NB * a:NB * a + NB, NB * b:NB * b + NB] = zb
+        Mo = np.linalg.inv(D)
+        err = np.linalg.norm(Mg[t, :NB * m, :NB * m] - Mo) / np.linalg.norm(Mo)
+        bound = 3e-5 * np.linalg.cond(D) + 1e-6
+        worst_c = max(worst_c, err / bound)
+    say(f"  {len(ks)} cluster blocks: err / bound max {worst_c:.3f}")
+    assert worst_c <= 1.0
+
+    # monostatic RCS: the oracle's functional on the library's currents
+    so = mom.monostatic_rcs(cloud, Xs, kh, eh)
+    db = np.abs(10 * np.log10(sig / so))
+    say(f"  rcs of {len(sel)} incidences: max {db.max():.2e} dB")
+    assert db.max() <= 1e-4
