@@ -1159,24 +1159,29 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
         }
         rz[cc] = rr[cc] = c128{0, 0};
     }
+    // the next cluster's residual and q rows are loaded while the current one
+    // is multiplied (software pipelining across the chunk's clusters)
+    cplx<R> res[RPT * CW], qv[RPT * CW];
+    auto load_rows = [&](int64_t w_, cplx<R>* res_, cplx<R>* qv_) {
+        const int nr_ = (int)std::min<int64_t>(CLW, ch.w1 - w_) * NB;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int rho = std::min(rsub * RPT + j, nr_ - 1);
+#pragma unroll
+            for (int cc = 0; cc < CW; ++cc) {
+                const int64_t o = (w_ * NB + rho) * s + rc[cc];
+                res_[j * CW + cc] = rv[o];
+                qv_[j * CW + cc] = qz[o];
+            }
+        }
+    };
+    if (ch.w0 < ch.w1) load_rows(ch.w0, res, qv);
     int64_t kc = ch.cl0;
     for (int64_t w = ch.w0; w < ch.w1; w += CLW, ++kc) {
         const int nr = (int)std::min<int64_t>(CLW, ch.w1 - w) * NB;
         const int64_t row0 = w * NB;
         const CZ* mb = Mb + kc * CLR2;
         if (STAGED) stage_block<CZ, RB>(ms, mb);
-        // r -= alpha q: every load is issued before any arithmetic
-        cplx<R> res[RPT * CW], qv[RPT * CW];
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int rho = std::min(rsub * RPT + j, nr - 1);
-#pragma unroll
-            for (int cc = 0; cc < CW; ++cc) {
-                const int64_t o = (row0 + rho) * s + rc[cc];
-                res[j * CW + cc] = rv[o];
-                qv[j * CW + cc] = qz[o];
-            }
-        }
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
             const int rho = rsub * RPT + j;
@@ -1194,6 +1199,7 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
             }
         }
         __syncthreads();
+        if (w + CLW < ch.w1) load_rows(w + CLW, res, qv);   // r and q of this cluster live in rs and qz now
         cplx<R> acc[RPT * CW];
         cluster_rows<R, CZ, ST, RPT, FULL, STAGED, CW>(ms, mb, rs, col, rsub, acc);
 #pragma unroll
