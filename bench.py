@@ -364,7 +364,7 @@ def main(argv=None) -> int:
                                                "launches": 4}}))
         return 0
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); this build has no multi-GPU "
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the library has no multi-GPU "
               "path. Run with --gpus 1.", file=sys.stderr)
         return 2
 
