@@ -410,9 +410,10 @@ static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, 
         return CHAFF_OK;
     }
     if ((variant == 6 || variant == 7) && !DIAG) {
-        // S columns per tile; S <= 4 packs two block rows into one wave; 7 = XCD-aware order
+        // S columns per tile, several block rows per wave below 32 columns; 7 = XCD-aware order
         const int sw = spmm_tile_width(s) < 4 ? 4 : spmm_tile_width(s);
-        const int64_t nr = sw <= 4 ? 2 : 1;
+        // block rows per wave (several independent gather chains per wave at small widths)
+        const int64_t nr = sw == 4 ? 4 : sw == 8 ? 2 : sw == 16 ? 4 : 1;
         const int64_t n_grp = (n + nr - 1) / nr;
         const int64_t nblk = variant == 7 ? (n_grp + NXCD - 1) / NXCD * NXCD : n_grp;
         dim3 grid((unsigned)nblk, (unsigned)((s + sw - 1) / sw));
@@ -426,7 +427,7 @@ static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, 
                                row_ptr, col_idx, Z, X, B, Y, n, s);                                         \
         break;
         switch (sw) {
-            CHAFF_WR(4, 2) CHAFF_WR(8, 1) CHAFF_WR(16, 1) CHAFF_WR(32, 1) CHAFF_WR(64, 1)
+            CHAFF_WR(4, 4) CHAFF_WR(8, 2) CHAFF_WR(16, 4) CHAFF_WR(32, 1) CHAFF_WR(64, 1)
             default: return fail(CHAFF_EINVAL, "bad tile width");
         }
 #undef CHAFF_WR

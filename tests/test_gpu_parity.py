@@ -135,7 +135,7 @@ def test_excitation_c2(B):
 @pytest.mark.parametrize("s,variant", [(1, 0), (1, 1), (3, 1), (8, 1), (8, 2), (64, 1), (70, 1),
                                        (1, 5), (3, 5), (8, 5), (16, 5), (70, 5),
                                        (1, 6), (3, 6), (8, 6), (16, 6), (33, 6), (70, 6),
-                                       (2, 7), (5, 7), (16, 7), (64, 7)])
+                                       (2, 7), (5, 7), (12, 6), (16, 7), (24, 7), (32, 7), (64, 7)])
 def test_spmm_c2(B, s, variant):
     import torch
     wl = W.c2()
