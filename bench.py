@@ -146,14 +146,22 @@ def cpu_baseline(wl, n_sample: int = 2000, r_sample: int = 8):
     sample = sub_sphere(cloud, n_s) if n_s < cloud.n else cloud
     r_s = min(R, r_sample)
     kh, eh = wl.inc.k_hat[:r_s], wl.inc.e_hat[:r_s]
+    ph = {}
     t0 = time.perf_counter()
-    Zs, _ = mom.snfc_matrix(sample)
+    pairs = mom.near_pairs(sample.center, sample.cloud_off, sample.d_c)
+    ta = time.perf_counter()
+    Zs, _ = mom.snfc_matrix(sample, pairs=pairs)
+    tb = time.perf_counter()
     lu = spla.splu(Zs.tocsc())
     t1 = time.perf_counter()
     u = mom.excitation(sample, kh, eh)
+    tc = time.perf_counter()
     x = lu.solve(u)
+    td = time.perf_counter()
     mom.monostatic_rcs(sample, x, kh, eh)
     t2 = time.perf_counter()
+    ph = {"near_set": ta - t0, "fill": tb - ta, "factor": t1 - tb, "excitation": tc - t1, "solve": td - tc,
+          "rcs": t2 - td}
     scale = n_full / sample.n
     t_full = (t1 - t0) * scale + (t2 - t1) / r_s * R * scale
     systems = cloud.n_clouds * R
@@ -163,8 +171,13 @@ def cpu_baseline(wl, n_sample: int = 2000, r_sample: int = 8):
             cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
     except OSError:
         pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
     return {"value": systems / t_full, "unit": "solved angles/s", "cores": int(threads), "kind": "oracle",
-            "cpu_model": cpu_model,
+            "cpu_model": cpu_model, "cores_available": affinity,
+            "sample_phase_seconds": {k: round(v, 4) for k, v in ph.items()},
             "sample": f"{sample.n} of {n_full} wires (first cloud, nearest its centroid) and {r_s} of {R} "
                       f"incidences: setup {t1 - t0:.2f} s + {r_s} incidences {t2 - t1:.2f} s, each scaled "
                       f"by the wire ratio {scale:.1f}; full workload estimated at {t_full:.1f} s"}
