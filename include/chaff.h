@@ -238,7 +238,8 @@ chaff_status chaff_spmm(chaff_cloud c, chaff_prec prec, const void* Z, const voi
  * per lane; 1: RHS tile per wave; 2: half-width tile; 3: tile in XCD-aware
  * workgroup order; 4: XCD-aware half-width tile; 5: one lane per output row
  * accumulating up to 16 RHS columns, every Z row loaded once; 6: one wave per
- * block row, the block staged in LDS; 7: 6 in XCD-aware order) for this cloud, precision
+ * block row (4, 2 and 4 rows per wave at 4, 8 and 16 columns), the blocks
+ * staged in LDS; 7: 6 in XCD-aware order) for this cloud, precision
  * and RHS count on the caller's Z and two [N*7][s] buffers (contents of Y are
  * overwritten, X is read), and records the fastest in a process-wide table
  * keyed by (N, nnzb, s, prec).  Every later call with variant -1 (chaff_spmm,
