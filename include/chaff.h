@@ -217,7 +217,10 @@ size_t chaff_cluster_precond_bytes(chaff_cloud c, chaff_prec prec);   /* 0 on a 
 chaff_status chaff_cluster_precond(chaff_cloud c, chaff_prec prec, const void* Z, void* M,
                                    chaff_stream stream);
 /* Y = M X on the internal order: X, Y [N*7][s] complex (prec), row-major,
- * distinct buffers. */
+ * distinct buffers.  Host-synchronising: M's first and last cluster entries
+ * are read back and checked against the handle before any launch
+ * (CHAFF_EINVAL for a buffer that is not this cloud's cluster preconditioner);
+ * chaff_solve makes the same check when o->precond is CHAFF_PRECOND_CLUSTER. */
 chaff_status chaff_cluster_apply(chaff_cloud c, chaff_prec prec, const void* M, const void* X,
                                  void* Y, int64_t s, chaff_stream stream);
 
