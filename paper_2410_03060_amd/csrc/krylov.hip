@@ -1118,11 +1118,43 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
     if (threadIdx.x < ST && r < s) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + r] = v2;
 }
 
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// z = M r for one cluster on the FP32 matrix cores (v_mfma_f32_16x16x4_f32,
+// full FP32 products and sums): wave w forms the 16-column tile
+// [16 w, 16 w + 16) of z for the four 16-row tiles of the block (rows 56-63
+// are padding); each 4-deep step of the real form of the complex product
+// takes four MFMAs (re re, -im im, re im, im re).  Lane l supplies the
+// operand entries (row l % 16, depth l / 16) of the block and (depth l / 16,
+// column l % 16) of r, and receives rows 4 (l / 16) + j, j < 4, of column
+// l % 16 of each row tile.
+__device__ __forceinline__ void cluster_tile_mfma(const c64* __restrict__ ms, const c64* __restrict__ rs,
+                                                  int wv, int l, f32x4_t (&zr)[4], f32x4_t (&zi)[4]) {
+    const int lr = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) zr[t] = zi[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int k0 = 0; k0 < CLR; k0 += 4) {
+        const int k = k0 + lk;
+        const c64 b = rs[k * 64 + 16 * wv + lr];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int row = 16 * t + lr;
+            const c64 a = row < CLR ? ms[row * CLR + k] : c64{0.f, 0.f};
+            zr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, b.re, zr[t], 0, 0, 0);
+            zr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.im, b.im, zr[t], 0, 0, 0);
+            zi[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, b.im, zi[t], 0, 0, 0);
+            zi[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, b.re, zi[t], 0, 0, 0);
+        }
+    }
+}
+
 // Cluster preconditioner form of k_cg_update: r -= alpha q, then z = M r per
 // cluster (M the cluster's 56 x 56 inverse block), written over q, with the
 // partial r^T z and ||r||^2.  One workgroup walks its chunk's clusters; the
-// updated residual rows of a cluster are staged in LDS, and with 64-column
-// tiles each wave forms 14 rows of z from wave-uniform reads of the block.
+// updated residual rows of a cluster are staged in LDS.  Complex64 64-column
+// tiles form z on the matrix cores, one 16-column tile per wave; otherwise
+// each lane forms rows of z for its columns from LDS reads of the block.
 template <typename CZ, typename C, int ST>
 __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
                                                      const CZ* __restrict__ Mb, C* qz, C* __restrict__ rv, int64_t s,
@@ -1137,6 +1169,9 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
     constexpr bool FULL = NSUB * RPT == CLR;
     // the block is staged in LDS for complex64 (25 KB); complex128 reads it from memory
     constexpr bool STAGED = sizeof(CZ) == sizeof(c64);
+    // complex64 64-column tiles form z = M r on the matrix cores
+    constexpr bool MFMA = STAGED && sizeof(C) == sizeof(c64) && ST == 64;
+    static_assert(!MFMA || RB == 4 * 64, "the MFMA form takes four waves of 16 columns each");
     // the residual tile, reused for the final column reduction (RB complex doubles)
     constexpr int RS_N = std::max<int>(CLR * ST, RB * (int)(sizeof(c128) / sizeof(cplx<R>)));
     __shared__ __align__(16) cplx<R> rs[RS_N];
@@ -1160,6 +1195,10 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
         }
         rz[cc] = rr[cc] = c128{0, 0};
     }
+    // MFMA form: r^T z per column 16 w + (l % 16), summed over the wave's rows
+    const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t zcol = (int)blockIdx.y * ST + 16 * wv + (lane & 15);
+    c128 rzm = {0, 0};
     // the next cluster's residual and q rows are loaded while the current one
     // is multiplied (software pipelining across the chunk's clusters)
     cplx<R> res[RPT * CW], qv[RPT * CW];
@@ -1201,16 +1240,34 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
         }
         __syncthreads();
         if (w + CLW < ch.w1) load_rows(w + CLW, res, qv);   // r and q of this cluster live in rs and qz now
-        cplx<R> acc[RPT * CW];
-        cluster_rows<R, CZ, ST, RPT, FULL, STAGED, CW>(ms, mb, rs, col, rsub, acc);
+        if constexpr (MFMA) {
+            f32x4_t zr[4], zi[4];
+            cluster_tile_mfma(reinterpret_cast<const c64*>(ms), reinterpret_cast<const c64*>(rs), wv, lane, zr, zi);
+            if (zcol < s) {
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int rho = rsub * RPT + j;
+                for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int cc = 0; cc < CW; ++cc) {
-                if (live[cc] && rho < nr) {   // the residual is re-read from its LDS tile
-                    qz[(row0 + rho) * s + r0 + cc] = acc[j * CW + cc];
-                    cfma(rz[cc], ccast<c128>(rs[rho * ST + col + cc]), ccast<c128>(acc[j * CW + cc]));
+                    for (int j = 0; j < 4; ++j) {
+                        const int rho = 16 * t + 4 * (lane >> 4) + j;
+                        if (rho < nr) {   // the residual is re-read from its LDS tile
+                            const cplx<R> zv = {zr[t][j], zi[t][j]};
+                            qz[(row0 + rho) * s + zcol] = zv;
+                            cfma(rzm, ccast<c128>(rs[rho * ST + 16 * wv + (lane & 15)]), ccast<c128>(zv));
+                        }
+                    }
+            }
+        } else {
+            cplx<R> acc[RPT * CW];
+            cluster_rows<R, CZ, ST, RPT, FULL, STAGED, CW>(ms, mb, rs, col, rsub, acc);
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int rho = rsub * RPT + j;
+#pragma unroll
+                for (int cc = 0; cc < CW; ++cc) {
+                    if (live[cc] && rho < nr) {   // the residual is re-read from its LDS tile
+                        qz[(row0 + rho) * s + r0 + cc] = acc[j * CW + cc];
+                        cfma(rz[cc], ccast<c128>(rs[rho * ST + col + cc]), ccast<c128>(acc[j * CW + cc]));
+                    }
                 }
             }
         }
@@ -1220,10 +1277,20 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
     c128* red = reinterpret_cast<c128*>(rs);
 #pragma unroll
     for (int cc = 0; cc < CW; ++cc) {
-        c128 v = block_col_reduce(rz[cc], TPC, red);
-        if ((int)threadIdx.x < TPC && live[cc]) part[((int64_t)blockIdx.x * nslot + slot0) * s + r0 + cc] = v;
+        if constexpr (!MFMA) {
+            c128 v = block_col_reduce(rz[cc], TPC, red);
+            if ((int)threadIdx.x < TPC && live[cc]) part[((int64_t)blockIdx.x * nslot + slot0) * s + r0 + cc] = v;
+        }
         c128 v2 = block_col_reduce(rr[cc], TPC, red);
         if ((int)threadIdx.x < TPC && live[cc]) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + r0 + cc] = v2;
+    }
+    if constexpr (MFMA) {   // r^T z: the four row groups of a column sit in lanes l, l + 16, l + 32, l + 48
+#pragma unroll
+        for (int off = 16; off < 64; off <<= 1) {
+            rzm.re += __shfl_xor(rzm.re, off, 64);
+            rzm.im += __shfl_xor(rzm.im, off, 64);
+        }
+        if (lane < 16 && zcol < s) part[((int64_t)blockIdx.x * nslot + slot0) * s + zcol] = rzm;
     }
 }
 
