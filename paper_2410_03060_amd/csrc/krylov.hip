@@ -930,15 +930,16 @@ __global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_
 // c) applies block columns k = g, g + G, ... (G = 64/S) to RHS column c, and
 // the G partial sums are combined with cross-lane adds.  sigma = p^T q is
 // reduced per tile in FP64 (tpart[tile][r]); two fixed-order passes then sum
-// tiles per group and groups per cloud.
+// tiles per group and groups per cloud.  The gathers of p are latency bound:
+// complex64 tiles ask the compiler for at least six waves per SIMD (the
+// 64-column tile then fits 68 registers instead of 90, seven waves instead of
+// five); complex128 tiles would spill under that bound.
 constexpr int COCG_TILE_ROWS = RB / 64;
 template <typename CZ, typename C, int S>
-__global__ __launch_bounds__(RB) void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles,
-                                                  int xcd_order,
-                                                  const int64_t* __restrict__ row_ptr,
-                                                  const int32_t* __restrict__ col_idx, const CZ* __restrict__ Z,
-                                                  const C* __restrict__ P, C* __restrict__ Q, int64_t s,
-                                                  c128* __restrict__ tpart) {
+__global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(sizeof(C) == sizeof(c64) ? 6 : 1)))
+void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles, int xcd_order,
+                 const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx, const CZ* __restrict__ Z,
+                 const C* __restrict__ P, C* __restrict__ Q, int64_t s, c128* __restrict__ tpart) {
     using R = typename real_of<C>::type;
     constexpr int G = 64 / S;
     constexpr int KK = (NB + G - 1) / G;
@@ -1155,10 +1156,17 @@ __device__ __forceinline__ void cluster_tile_mfma(const c64* __restrict__ ms, co
 // updated residual rows of a cluster are staged in LDS.  Complex64 64-column
 // tiles form z on the matrix cores, one 16-column tile per wave; otherwise
 // each lane forms rows of z for its columns from LDS reads of the block.
+// The MFMA form keeps no rows of the next cluster in flight: it asks the
+// compiler for three waves per SIMD (168 registers instead of 236), which
+// hides the loads better than the register prefetch of the vector form.
 template <typename CZ, typename C, int ST>
-__global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
-                                                     const CZ* __restrict__ Mb, C* qz, C* __restrict__ rv, int64_t s,
-                                                     c128* __restrict__ part, int nslot, int slot0) {
+constexpr bool cluster_update_mfma() {
+    return sizeof(CZ) == sizeof(c64) && sizeof(C) == sizeof(c64) && ST == 64;
+}
+template <typename CZ, typename C, int ST>
+__global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(cluster_update_mfma<CZ, C, ST>() ? 3 : 1)))
+void k_cg_update_cl(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg, const CZ* __restrict__ Mb,
+                    C* qz, C* __restrict__ rv, int64_t s, c128* __restrict__ part, int nslot, int slot0) {
     using R = typename real_of<C>::type;
     // 64-column tiles: two adjacent columns per lane, so every block value
     // read from LDS serves two columns (half the LDS reads per FMA)
@@ -1170,7 +1178,7 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
     // the block is staged in LDS for complex64 (25 KB); complex128 reads it from memory
     constexpr bool STAGED = sizeof(CZ) == sizeof(c64);
     // complex64 64-column tiles form z = M r on the matrix cores
-    constexpr bool MFMA = STAGED && sizeof(C) == sizeof(c64) && ST == 64;
+    constexpr bool MFMA = cluster_update_mfma<CZ, C, ST>();
     static_assert(!MFMA || RB == 4 * 64, "the MFMA form takes four waves of 16 columns each");
     // the residual tile, reused for the final column reduction (RB complex doubles)
     constexpr int RS_N = std::max<int>(CLR * ST, RB * (int)(sizeof(c128) / sizeof(cplx<R>)));
@@ -1199,8 +1207,9 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
     const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const int64_t zcol = (int)blockIdx.y * ST + 16 * wv + (lane & 15);
     c128 rzm = {0, 0};
-    // the next cluster's residual and q rows are loaded while the current one
-    // is multiplied (software pipelining across the chunk's clusters)
+    // vector form: the next cluster's residual and q rows are loaded while the
+    // current one is multiplied (software pipelining across the chunk's
+    // clusters); the MFMA form loads each cluster's rows when it starts it
     cplx<R> res[RPT * CW], qv[RPT * CW];
     auto load_rows = [&](int64_t w_, cplx<R>* res_, cplx<R>* qv_) {
         const int nr_ = (int)std::min<int64_t>(CLW, ch.w1 - w_) * NB;
@@ -1215,12 +1224,14 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
             }
         }
     };
-    if (ch.w0 < ch.w1) load_rows(ch.w0, res, qv);
+    constexpr bool PIPE = !MFMA;
+    if (PIPE && ch.w0 < ch.w1) load_rows(ch.w0, res, qv);
     int64_t kc = ch.cl0;
     for (int64_t w = ch.w0; w < ch.w1; w += CLW, ++kc) {
         const int nr = (int)std::min<int64_t>(CLW, ch.w1 - w) * NB;
         const int64_t row0 = w * NB;
         const CZ* mb = Mb + kc * CLR2;
+        if (!PIPE) load_rows(w, res, qv);
         if (STAGED) stage_block<CZ, RB>(ms, mb);
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
@@ -1239,7 +1250,7 @@ __global__ __launch_bounds__(RB) void k_cg_update_cl(const Chunk* __restrict__ c
             }
         }
         __syncthreads();
-        if (w + CLW < ch.w1) load_rows(w + CLW, res, qv);   // r and q of this cluster live in rs and qz now
+        if (PIPE && w + CLW < ch.w1) load_rows(w + CLW, res, qv);   // r and q of this cluster live in rs and qz now
         if constexpr (MFMA) {
             f32x4_t zr[4], zi[4];
             cluster_tile_mfma(reinterpret_cast<const c64*>(ms), reinterpret_cast<const c64*>(rs), wv, lane, zr, zi);
