@@ -20,6 +20,11 @@ below follow that recipe at the sizes the hot path is measured on:
 * ``c5``  1,000,000 wires uniform in a sphere of radius 50 wavelengths,
   d_c = 1 wavelength, 64 azimuth incidences.
 
+The statistical ensembles (``ensemble``) draw many independent trials of
+identical or two-length wires uniform in a sphere whose radius follows from
+the mean spacing d_mean (volume per wire d_mean^3), with a physical wire
+radius of 10 micrometres.
+
 Random draws are made with ``numpy.random.default_rng(seed)`` in a fixed
 order: positions, then orientations, then lengths, then angles.
 """
@@ -280,6 +285,53 @@ def random_cloud(seed: int, n: int, box_lam: float = 4.0, d_c_lam: float = math.
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4_eval": c4_eval, "c5": c5}
+
+
+# --------------------------------------------------------------------------- ensembles
+
+# Speed of light used to turn frequencies into wavelengths in the ensemble
+# recipes (the paper quotes frequencies in GHz and lengths in metres).
+C0 = 3.0e8
+# Physical wire radius of the ensembles: D = 20 micrometres (Sec. II).
+WIRE_RADIUS = 10e-6
+
+
+def sphere_radius_for_spacing(n: int, d_mean: float) -> float:
+    """Radius of the sphere whose volume per wire is d_mean^3: (4/3) pi a^3 = n d_mean^3."""
+    return d_mean * (3.0 * n / (4.0 * math.pi)) ** (1.0 / 3.0)
+
+
+def spacing_of_sphere(n: int, a: float) -> float:
+    """Mean spacing d_mean = (V / n)^(1/3) of n wires in a sphere of radius a."""
+    return (4.0 * math.pi * a ** 3 / (3.0 * n)) ** (1.0 / 3.0)
+
+
+def ensemble_trial(seed: int, n: int, sphere_radius: float, length, wavelength: float,
+                   d_c: float, wire_radius: float = WIRE_RADIUS) -> Cloud:
+    """One trial of a statistical ensemble (Sec. III-B, III-C, IV): n wires
+    uniform in a sphere, isotropic orientations.  ``length`` is one length for
+    every wire or a sequence of lengths that the wires take in turn (wire i
+    gets length[i % len(length)])."""
+    rng = np.random.default_rng(seed)
+    c = _uniform_ball(rng, n, sphere_radius)
+    t = _isotropic(rng, n)
+    lens = np.atleast_1d(np.asarray(length, dtype=np.float64))
+    L = lens[np.arange(n) % lens.size]
+    return single_cloud(c, t, L, wavelength, d_c, np.full(n, wire_radius))
+
+
+def ensemble(seed0: int, trials: int, n: int, sphere_radius: float, length, wavelength: float,
+             d_c: float, wire_radius: float = WIRE_RADIUS) -> Cloud:
+    """``trials`` independent trials as the clouds of one multi-cloud input;
+    trial t is ``ensemble_trial(seed0 + t, ...)`` whatever the trial count."""
+    return concat_clouds([ensemble_trial(seed0 + t, n, sphere_radius, length, wavelength, d_c, wire_radius)
+                          for t in range(trials)])
+
+
+def v_incidence() -> Incidence:
+    """The ensembles' single incidence: V-polarised (theta-hat = -z) wave
+    arriving from +x along the xy-plane."""
+    return azimuth_incidences(1)
 
 
 # --------------------------------------------------------------------------- learned guess
