@@ -92,7 +92,7 @@ GUESSES = {"zero": 0, "bj": 2, "mlp": 1}   # bj: x0 = P u with the solve's preco
 PRECONDS = {"block": 0, "cluster": 1}
 # training recipe of the learned guess per evaluation workload: (generator, clouds, epochs)
 MLP_TRAINING = {"c4_eval": ("c4_train_cloud", 200, 12), "c5": ("c5_train_cloud", 64, 12)}
-METHODS = {"gmres": 0, "cocg": 1, "cocg_rr": 2}
+METHODS = {"gmres": 0, "cocg": 1, "cocg_rr": 2, "gcr": 3}
 
 
 def make_workload(name):

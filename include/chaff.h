@@ -145,7 +145,7 @@ chaff_status chaff_fill_Z(chaff_cloud c, chaff_prec prec, void* Z, void* Pinv,
 typedef struct {
     double  tol;              /* relative FP64 residual target per system (1e-6) */
     double  inner_tol;        /* relative reduction asked of one FP32 cycle (1e-4) */
-    int32_t restart;          /* GMRES(m) cycle length, 1..200 (30) */
+    int32_t restart;          /* GMRES(m) / GCR(m) cycle length, 1..200 (30); COCG: step cap per cycle */
     int32_t max_cycles;       /* restart/refinement cycles (50) */
     int32_t use_x0;           /* 0: x0 = 0; 1: X holds an initial guess on entry;
                                  2: preconditioner guess x0 = P u (P the preconditioner
@@ -169,8 +169,13 @@ typedef enum { CHAFF_PRECOND_BLOCK = 0, CHAFF_PRECOND_CLUSTER = 1 } chaff_precon
  * Z and its block-diagonal inverse are complex symmetric (bilinear a^T b),
  * with four vectors and no restart inside a cycle.  CHAFF_COCG restarts the
  * recurrence at every refinement checkpoint; CHAFF_COCG_RR keeps the search
- * direction and only replaces the recursive residual by the FP64 true one. */
-typedef enum { CHAFF_GMRES = 0, CHAFF_COCG = 1, CHAFF_COCG_RR = 2 } chaff_method;
+ * direction and only replaces the recursive residual by the FP64 true one.
+ * CHAFF_GCR is the generalized conjugate residual method of Sec. II-B,
+ * restarted every `restart` (= m <= 200) steps and right-preconditioned:
+ * it keeps the m preconditioned directions and their images under Z
+ * (2m + 2 vectors), made orthonormal by classical Gram-Schmidt applied
+ * twice, and minimises the residual over them at every step. */
+typedef enum { CHAFF_GMRES = 0, CHAFF_COCG = 1, CHAFF_COCG_RR = 2, CHAFF_GCR = 3 } chaff_method;
 
 typedef struct {
     int32_t cycles;           /* refinement sweeps (= GMRES restart cycles) run */

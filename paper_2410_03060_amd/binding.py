@@ -300,7 +300,7 @@ def fill_Z(cl: Cloud, prec: int = C64, with_pinv: bool = True):
     return Z, P
 
 
-GMRES, COCG, COCG_RR = 0, 1, 2
+GMRES, COCG, COCG_RR, GCR = 0, 1, 2, 3
 PRECOND_BLOCK, PRECOND_CLUSTER = 0, 1
 CLUSTER_WIRES, CLUSTER_ROWS = 8, 56
 

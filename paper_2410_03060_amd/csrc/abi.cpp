@@ -320,15 +320,16 @@ static chaff_status check_opts(const chaff_solve_opts* o) {
     if (!o) return fail(CHAFF_EINVAL, "opts is NULL");
     if (!(o->tol > 0) || !(o->tol < 1)) return fail(CHAFF_EINVAL, "tol must be in (0, 1)");
     if (!(o->inner_tol > 0) || !(o->inner_tol < 1)) return fail(CHAFF_EINVAL, "inner_tol must be in (0, 1)");
-    if (o->restart < 1 || (o->method == CHAFF_GMRES && o->restart > 200))
-        return fail(CHAFF_EINVAL, "restart must be in [1, 200] (GMRES) or >= 1 (COCG)");
+    const bool restarted = o->method == CHAFF_GMRES || o->method == CHAFF_GCR;
+    if (o->restart < 1 || (restarted && o->restart > 200))
+        return fail(CHAFF_EINVAL, "restart must be in [1, 200] (GMRES, GCR) or >= 1 (COCG)");
     if (o->max_cycles < 1) return fail(CHAFF_EINVAL, "max_cycles must be >= 1");
     if (o->use_x0 < 0 || o->use_x0 > 2) return fail(CHAFF_EINVAL, "use_x0 must be 0, 1 or 2");
     if (o->prec != CHAFF_C64 && o->prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
     if (o->spmm_variant < -1 || o->spmm_variant > 7) return fail(CHAFF_EINVAL, "spmm_variant must be in [-1, 7]");
-    if (o->method != CHAFF_GMRES && o->method != CHAFF_COCG && o->method != CHAFF_COCG_RR)
-        return fail(CHAFF_EINVAL, "method must be CHAFF_GMRES, CHAFF_COCG or CHAFF_COCG_RR");
-    if (o->method != CHAFF_GMRES && o->restart > 1000000) return fail(CHAFF_EINVAL, "restart too large");
+    if (o->method != CHAFF_GMRES && o->method != CHAFF_COCG && o->method != CHAFF_COCG_RR && o->method != CHAFF_GCR)
+        return fail(CHAFF_EINVAL, "method must be CHAFF_GMRES, CHAFF_COCG, CHAFF_COCG_RR or CHAFF_GCR");
+    if (!restarted && o->restart > 1000000) return fail(CHAFF_EINVAL, "restart too large");
     if (o->reserved != 0) return fail(CHAFF_EINVAL, "reserved must be 0");
     if (o->precond != CHAFF_PRECOND_BLOCK && o->precond != CHAFF_PRECOND_CLUSTER)
         return fail(CHAFF_EINVAL, "precond must be CHAFF_PRECOND_BLOCK or CHAFF_PRECOND_CLUSTER");

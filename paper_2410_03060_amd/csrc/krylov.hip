@@ -1448,8 +1448,11 @@ struct SolveShape {
 static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec, int method) {
     SolveShape sh;
     sh.method = method;
-    sh.mg = method != CHAFF_GMRES ? 1 : m;
-    sh.nvec = method != CHAFF_GMRES ? 4 : m + 1;
+    const bool cocg = method == CHAFF_COCG || method == CHAFF_COCG_RR;
+    sh.mg = cocg ? 1 : m;
+    // GMRES: m + 1 basis vectors; GCR: m directions, their m images, the
+    // working residual and the correction; COCG: four vectors
+    sh.nvec = method == CHAFF_GMRES ? m + 1 : method == CHAFF_GCR ? 2 * m + 2 : 4;
     sh.n = c->n;
     sh.rows = c->n * NB;
     sh.s = s;
@@ -1474,7 +1477,7 @@ static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec,
         sh.cocg_xcd = (v == 1 || v == 2 || v == 6) ? 0 : 1;
     }
     sh.tile_w = COCG_TILE_ROWS;
-    if (method != CHAFF_GMRES) {
+    if (cocg) {
         for (int k = 0; k < c->n_clouds; ++k) {
             const int64_t nw = c->cloud_off[k + 1] - c->cloud_off[k];
             const int64_t nt = (nw + sh.tile_w - 1) / sh.tile_w;
@@ -1865,6 +1868,175 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     return CHAFF_OK;
 }
 
+// ------------------------------------------------------------------ GCR (Sec. II-B)
+
+// 1 / ||Q_j|| per system; a finished system gets 0, and a vanishing Q_j (no
+// new direction) finishes the system for the rest of the cycle
+__global__ void k_gcr_beta(int64_t nsys, const c128* __restrict__ nrm2, SysState* __restrict__ sys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsys) return;
+    SysState S = sys[i];
+    const double b2 = nrm2[i].re;
+    if (!S.done && !(b2 > 1e-300 && isfinite(b2))) S.done = 1;
+    S.inv_beta = S.done ? 0.0 : 1.0 / sqrt(b2);
+    sys[i] = S;
+}
+
+// Q_j *= inv_beta, U_j *= inv_beta (per system)
+template <typename C>
+__global__ void k_gcr_scale(C* __restrict__ Q, C* __restrict__ U, const int32_t* __restrict__ wire_cloud,
+                            const SysState* __restrict__ sys, int64_t n_rows, int64_t s) {
+    using R = typename real_of<C>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s) return;
+    const int64_t row = t / s, r = t - (t / s) * s;
+    const R f = (R)sys[(int64_t)wire_cloud[row / NB] * s + r].inv_beta;
+    Q[t] = cscale(Q[t], f);
+    U[t] = cscale(U[t], f);
+}
+
+// alpha = Q_j^H rho (0 for finished systems), and -alpha
+__global__ void k_gcr_alpha(int64_t nsys, const c128* __restrict__ dot, const SysState* __restrict__ sys,
+                            c128* __restrict__ alpha, c128* __restrict__ neg_alpha) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsys) return;
+    const c128 a = sys[i].done ? c128{0, 0} : dot[i];
+    alpha[i] = a;
+    neg_alpha[i] = c128{-a.re, -a.im};
+}
+
+// ||rho|| (relative to the cycle start) against the system's target; counts
+// the systems still running
+__global__ void k_gcr_check(int64_t nsys, const c128* __restrict__ nrm2, SysState* __restrict__ sys,
+                            int32_t* __restrict__ n_active) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsys) return;
+    SysState S = sys[i];
+    if (S.done) return;
+    S.est = sqrt(fmax(nrm2[i].re, 0.0));
+    if (S.est <= S.target || !isfinite(S.est)) S.done = 1;
+    else atomicAdd(n_active, 1);
+    sys[i] = S;
+}
+
+// x += ||r|| xc (FP64 solution, per system)
+template <typename C>
+__global__ void k_gcr_finish(const C* __restrict__ xc, const int32_t* __restrict__ wire_cloud,
+                             const double* __restrict__ rn, int64_t n_rows, int64_t s, c128* __restrict__ x) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s) return;
+    const int64_t row = t / s, r = t - (t / s) * s;
+    const double f = rn[(int64_t)wire_cloud[row / NB] * s + r];
+    const c128 v = ccast<c128>(xc[t]);
+    x[t] = c128{x[t].re + f * v.re, x[t].im + f * v.im};
+}
+
+// One restarted GCR(m) cycle, right-preconditioned, every system in lockstep
+// with its own coefficients.  rho = r / ||r|| is the working residual and xc
+// the correction (precision C).  Step j: U_j = P rho and Q_j = Z U_j; two
+// classical Gram-Schmidt passes make Q_j orthogonal (Hermitian products) to
+// Q_0 .. Q_{j-1}, the same combinations are applied to U_j so that Q_j = Z U_j
+// keeps holding, and both are scaled to ||Q_j|| = 1; then alpha = Q_j^H rho,
+// rho -= alpha Q_j (minimal residual over the directions so far) and
+// xc += alpha U_j.  A system stops once ||rho|| reaches its target; at the end
+// x += ||r|| xc.  L.sys, L.rn and L.inv_rn are set by the caller.
+template <typename C, typename CZ>
+static chaff_status gcr_cycle(Cloud* c, const chaff_solve_opts* o, const SolveShape& sh, SolveLayout& L,
+                              const CZ* Z, const CZ* Pinv, int& iters, hipStream_t st) {
+    const int64_t rows = sh.rows, s = sh.s, vs = rows * s, nsys = sh.nsys;
+    const int m = sh.m;
+    C* V = static_cast<C*>(L.V);
+    C* U = V;                                  // U_j = V[j]
+    C* Q = V + (int64_t)m * vs;                // Q_j = V[m + j]
+    C* rho = V + (int64_t)2 * m * vs;
+    C* xc = rho + vs;
+    const int wst = spmm_tile_width(s);
+    const dim3 grid(sh.n_chunks, (unsigned)((s + wst - 1) / wst));
+    const int32_t* wc = (const int32_t*)c->wire_cloud;
+    const int norm_slot = sh.nslot - 1;
+    hipLaunchKernelGGL((k_start_vector<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.r, wc,
+                       (const double*)L.inv_rn, sh.n_clouds, rows, s, rho);
+    CHAFF_LAUNCH_CHECK();
+    const int64_t xc_words = vs * (int64_t)(sizeof(C) / 4);
+    hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(xc_words, 256)), dim3(256), 0, st, (uint32_t*)xc, xc_words);
+    CHAFF_LAUNCH_CHECK();
+    chaff_status sst;
+    for (int j = 0; j < m; ++j) {
+        ++iters;
+        C* uj = U + (int64_t)j * vs;
+        C* qj = Q + (int64_t)j * vs;
+        if (o->precond == CHAFF_PRECOND_CLUSTER)
+            sst = cluster_apply_launch(c, (chaff_prec)o->prec, Pinv, rho, sizeof(C) == 16, uj, sizeof(C) == 16,
+                                       false, s, st, "precond");
+        else
+            sst = spmm_launch<CZ, C, C, 0, true>(nullptr, nullptr, Pinv, rho, (const C*)nullptr, uj, c->n, c->n, s,
+                                                 -1, st, "precond");
+        if (sst != CHAFF_OK) return sst;
+        sst = spmm_launch<CZ, C, C, 0, false>(c->row_ptr, c->col_idx, Z, uj, (const C*)nullptr, qj, c->n, c->nnzb,
+                                              s, o->spmm_variant, st);
+        if (sst != CHAFF_OK) return sst;
+        for (int pass = 0; pass < 2 && j > 0; ++pass) {   // classical Gram-Schmidt, twice
+            for (int i0 = 0; i0 < j; i0 += GV) {
+                ProfScope p1("k_dots", st, (double)(std::min(GV, j - i0) + 1) * vs * sizeof(C));
+                hipLaunchKernelGGL((k_dots<C>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)Q, vs, i0,
+                                   std::min(GV, j - i0), (const C*)qj, s, wst, L.part, sh.nslot);
+                CHAFF_LAUNCH_CHECK();
+            }
+            chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, j, s,
+                      L.h1, st);
+            CHAFF_LAUNCH_CHECK();
+            ProfScope p2("k_update", st, (double)(2 * j + 4) * vs * sizeof(C));
+            hipLaunchKernelGGL((k_update<C, false>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)Q, vs,
+                               j, (const c128*)L.h1, sh.n_clouds, qj, s, wst, L.part, sh.nslot, 0);
+            CHAFF_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_update<C, false>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)U, vs,
+                               j, (const c128*)L.h1, sh.n_clouds, uj, s, wst, L.part, sh.nslot, 0);
+            CHAFF_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL((k_norm2<C>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)qj, s, wst, L.part,
+                           sh.nslot, norm_slot);
+        CHAFF_LAUNCH_CHECK();
+        chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, norm_slot, 1, s,
+                  L.nrm, st);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gcr_beta, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const c128*)L.nrm, L.sys);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_gcr_scale<C>), dim3(blocks_for(vs)), dim3(256), 0, st, qj, uj, wc,
+                           (const SysState*)L.sys, rows, s);
+        CHAFF_LAUNCH_CHECK();
+        // alpha = Q_j^H rho; rho -= alpha Q_j (with ||rho||^2); xc += alpha U_j
+        hipLaunchKernelGGL((k_dots<C>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)qj, vs, 0, 1,
+                           (const C*)rho, s, wst, L.part, sh.nslot);
+        CHAFF_LAUNCH_CHECK();
+        chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, 0, 1, s, L.h2, st);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gcr_alpha, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const c128*)L.h2,
+                           (const SysState*)L.sys, L.Y, L.G);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_update<C, true>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)qj, vs, 1,
+                           (const c128*)L.Y, sh.n_clouds, rho, s, wst, L.part, sh.nslot, norm_slot);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_update<C, false>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const C*)uj, vs, 1,
+                           (const c128*)L.G, sh.n_clouds, xc, s, wst, L.part, sh.nslot, 0);
+        CHAFF_LAUNCH_CHECK();
+        chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, sh.n_clouds, sh.nslot, norm_slot, 1, s,
+                  L.nrm, st);
+        CHAFF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)L.counter, (int64_t)1);
+        hipLaunchKernelGGL(k_gcr_check, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const c128*)L.nrm, L.sys,
+                           L.counter);
+        CHAFF_LAUNCH_CHECK();
+        int32_t n_act = 0;
+        CHAFF_HIP(hipMemcpyAsync(&n_act, L.counter, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        CHAFF_HIP(hipStreamSynchronize(st));
+        if (n_act == 0) break;
+    }
+    hipLaunchKernelGGL((k_gcr_finish<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const C*)xc, wc,
+                       (const double*)L.rn, rows, s, L.x);
+    CHAFF_LAUNCH_CHECK();
+    return CHAFF_OK;
+}
+
 template <typename C, typename CZ>
 static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z, const CZ* Pinv,
                                const double* k_hat, const double* e_hat, int64_t s, c128* Xout, void* ws,
@@ -1907,7 +2079,7 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         // COCG product tiles (cloud-aligned) and their groups (cloud-aligned)
         std::vector<Chunk> tl;
         std::vector<int32_t> gto, cgo(sh.n_clouds + 1, 0);
-        if (sh.method != CHAFF_GMRES) {
+        if (sh.method == CHAFF_COCG || sh.method == CHAFF_COCG_RR) {
             build_tiles(c, sh.tile_w, tl, gto, cgo);
             if (!tl.empty())
                 CHAFF_HIP(hipMemcpyAsync(L.tiles, tl.data(), tl.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
@@ -1998,7 +2170,7 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         ++cycles;
         CHAFF_HIP(hipMemcpyAsync(L.rn, hrn.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
         CHAFF_HIP(hipMemcpyAsync(L.inv_rn, hinv.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
-        if (sh.method != CHAFF_GMRES) {
+        if (sh.method == CHAFF_COCG || sh.method == CHAFF_COCG_RR) {
             // fixed per-system scale for the whole run (set by the first cycle)
             const bool first = cocg_scale.empty();
             if (first) cocg_scale.assign(nsys, 0.0);
@@ -2020,6 +2192,11 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
             continue;
         }
         CHAFF_HIP(hipMemcpyAsync(L.sys, hsys.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, st));
+        if (sh.method == CHAFF_GCR) {
+            sst = gcr_cycle<C, CZ>(c, o, sh, L, Z, Pinv, iters, st);
+            if (sst != CHAFF_OK) return sst;
+            continue;
+        }
         // g = e_1 for every system
         {
             std::vector<c128> g0((size_t)nsys * (m + 1), c128{0, 0});

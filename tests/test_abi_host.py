@@ -172,6 +172,16 @@ def test_solve_rejects_bad_preconditioner_and_reserved_field(B):
     assert "reserved" in B.last_error()
 
 
+def test_solve_rejects_unknown_method_and_long_gcr_cycles(B):
+    L = B.lib()
+    o = B.solve_opts(method=4)
+    assert L.chaff_solve_workspace_bytes(C.c_void_p(0x1000), C.byref(o), 1) == 0
+    assert "method" in B.last_error()
+    o = B.solve_opts(method=B.GCR, restart=201)
+    assert L.chaff_solve_workspace_bytes(C.c_void_p(0x1000), C.byref(o), 1) == 0
+    assert "restart" in B.last_error()
+
+
 def test_cluster_entry_points_validate_before_any_launch(B):
     L = B.lib()
     H = C.c_void_p(0x1000)          # never dereferenced: every call below fails validation

@@ -157,14 +157,27 @@ def test_spmm_c2(B, s, variant):
 
 # ----------------------------------------------------------------------------- solve + rcs
 
+_METHODS = {"gmres": "GMRES", "cocg": "COCG", "gcr": "GCR"}
+
+
+def _method_opts(B, method):
+    """Method constant and its cycle settings: restarted methods 30 steps to a
+    1e-4 reduction per refinement cycle, COCG up to 500 steps to 1e-2."""
+    meth = getattr(B, _METHODS[method])
+    restarted = meth in (B.GMRES, B.GCR)
+    return dict(method=meth, restart=30 if restarted else 500, inner_tol=1e-4 if restarted else 1e-2)
+
+
+@pytest.mark.parametrize("method", ["gmres", "gcr"])
 @pytest.mark.parametrize("dense", [False, True])
-def test_c1_complex128_solve_and_bistatic_rcs(B, dense):
+def test_c1_complex128_solve_and_bistatic_rcs(B, dense, method):
     wl = W.c1(d_c=math.inf if dense else 2.0)
-    say(f"[solve] c1 complex128 dense={dense}")
+    say(f"[solve] c1 complex128 dense={dense} {method}")
     cl = B.build_cloud(wl.cloud)
     Z, P = B.fill_Z(cl, B.C128)
     X, info = B.solve(cl, Z, P, wl.inc.k_hat, wl.inc.e_hat,
-                      B.solve_opts(tol=1e-12, restart=60, max_cycles=20, prec=B.C128))
+                      B.solve_opts(tol=1e-12, restart=60, max_cycles=20, prec=B.C128,
+                                   method=getattr(B, _METHODS[method])))
     say(f"  cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e}")
     u = mom.excitation(wl.cloud, wl.inc.k_hat, wl.inc.e_hat)
     if dense:
@@ -190,16 +203,13 @@ def test_c1_complex128_solve_and_bistatic_rcs(B, dense):
     assert abs(sm[0] - smo[0]) <= 1e-9 * smo[0]
 
 
-@pytest.mark.parametrize("method", ["gmres", "cocg"])
+@pytest.mark.parametrize("method", ["gmres", "cocg", "gcr"])
 def test_c2_fp32_refined_solve(B, method):
     wl = W.c2()
     say(f"[solve] c2 complex64 + FP64 refinement to 1e-6, {method}")
     cl = B.build_cloud(wl.cloud)
     Z, P = B.fill_Z(cl, B.C64)
-    meth = B.COCG if method == "cocg" else B.GMRES
-    X, info = B.solve(cl, Z, P, wl.inc.k_hat, wl.inc.e_hat,
-                      B.solve_opts(tol=1e-6, method=meth, restart=30 if meth == B.GMRES else 500,
-                                   inner_tol=1e-4 if meth == B.GMRES else 1e-2))
+    X, info = B.solve(cl, Z, P, wl.inc.k_hat, wl.inc.e_hat, B.solve_opts(tol=1e-6, **_method_opts(B, method)))
     say(f"  cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e}")
     assert info["max_rel_residual"] <= 1e-6
     Zs, _ = mom.snfc_matrix(wl.cloud)
@@ -215,7 +225,7 @@ def test_c2_fp32_refined_solve(B, method):
     assert e_db <= 0.1
 
 
-@pytest.mark.parametrize("method", ["gmres", "cocg"])
+@pytest.mark.parametrize("method", ["gmres", "cocg", "gcr"])
 def test_multicloud_multirhs_one_launch(B, method):
     """Three uneven clouds (one empty) x 6 azimuth RHS in one build/fill/solve/rcs."""
     lam = W.WAVELENGTH
@@ -231,10 +241,7 @@ def test_multicloud_multirhs_one_launch(B, method):
     say(f"[solve] multi-cloud N={cloud.n} clouds={cloud.n_clouds} R=6")
     cl = B.build_cloud(cloud)
     Z, P = B.fill_Z(cl, B.C64)
-    meth = B.COCG if method == "cocg" else B.GMRES
-    X, info = B.solve(cl, Z, P, inc.k_hat, inc.e_hat,
-                      B.solve_opts(tol=1e-6, method=meth, restart=30 if meth == B.GMRES else 500,
-                                   inner_tol=1e-4 if meth == B.GMRES else 1e-2))
+    X, info = B.solve(cl, Z, P, inc.k_hat, inc.e_hat, B.solve_opts(tol=1e-6, **_method_opts(B, method)))
     say(f"  cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e}")
     assert info["max_rel_residual"] <= 1e-6
     Zs, _ = mom.snfc_matrix(cloud)
@@ -249,6 +256,25 @@ def test_multicloud_multirhs_one_launch(B, method):
     for c in (0, 2, 3):
         e_db, _ = db_err(sig[c], so[c])
         assert e_db <= 0.1
+
+
+def test_gcr_and_gmres_minimise_over_the_same_space(B):
+    """Right-preconditioned GCR(m) and GMRES(m) minimise the residual over the
+    same Krylov space, so in FP64 they need the same number of steps and reach
+    the same currents (four RHS, one cycle each)."""
+    wl = W.c2(n=600)
+    inc = W.azimuth_incidences(4)
+    say(f"[solve] GCR against GMRES, N={wl.cloud.n} R=4, complex128")
+    cl = B.build_cloud(wl.cloud)
+    Z, P = B.fill_Z(cl, B.C128)
+    out = {}
+    for name in ("GMRES", "GCR"):
+        X, info = B.solve(cl, Z, P, inc.k_hat, inc.e_hat,
+                          B.solve_opts(tol=1e-10, restart=120, max_cycles=4, prec=B.C128, method=getattr(B, name)))
+        out[name] = (_to_np(X), info)
+        say(f"  {name}: cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e}")
+    assert abs(out["GCR"][1]["iterations"] - out["GMRES"][1]["iterations"]) <= 2
+    assert current_err(out["GCR"][0], out["GMRES"][0]).max() <= 1e-8
 
 
 def test_degenerate_single_wire_and_no_pairs(B):

@@ -143,7 +143,7 @@ def _oracle_x(cloud, inc):
     return osolve.sparse_solve(Zs, u)
 
 
-@pytest.mark.parametrize("method", ["cocg", "gmres"])
+@pytest.mark.parametrize("method", ["cocg", "gmres", "gcr"])
 @pytest.mark.parametrize("guess", [0, 2])
 def test_c2_solve_with_cluster_preconditioner(B, method, guess):
     wl = W.c2()
@@ -151,9 +151,10 @@ def test_c2_solve_with_cluster_preconditioner(B, method, guess):
     cl = B.build_cloud(wl.cloud)
     Z, Pb = B.fill_Z(cl, B.C64)
     M = B.cluster_precond(cl, Z, B.C64)
-    meth = B.COCG if method == "cocg" else B.GMRES
-    kw = dict(tol=1e-6, method=meth, restart=30 if meth == B.GMRES else 500,
-              inner_tol=1e-4 if meth == B.GMRES else 1e-2, use_x0=guess)
+    meth = {"cocg": B.COCG, "gmres": B.GMRES, "gcr": B.GCR}[method]
+    restarted = meth != B.COCG
+    kw = dict(tol=1e-6, method=meth, restart=30 if restarted else 500,
+              inner_tol=1e-4 if restarted else 1e-2, use_x0=guess)
     X, info = B.solve(cl, Z, M, wl.inc.k_hat, wl.inc.e_hat, B.solve_opts(precond=B.PRECOND_CLUSTER, **kw))
     _, info_b = B.solve(cl, Z, Pb, wl.inc.k_hat, wl.inc.e_hat, B.solve_opts(**kw))
     say(f"  cluster: cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e}; "
@@ -180,7 +181,7 @@ def test_complex128_cocg_with_cluster_preconditioner(B):
     assert e.max() <= 1e-10
 
 
-@pytest.mark.parametrize("method", ["cocg", "gmres"])
+@pytest.mark.parametrize("method", ["cocg", "gmres", "gcr"])
 def test_multicloud_with_cluster_preconditioner(B, method):
     cloud = _clouds()["multi"]
     inc = W.azimuth_incidences(6)
@@ -188,10 +189,11 @@ def test_multicloud_with_cluster_preconditioner(B, method):
     cl = B.build_cloud(cloud)
     Z, _ = B.fill_Z(cl, B.C64, with_pinv=False)
     M = B.cluster_precond(cl, Z, B.C64)
-    meth = B.COCG if method == "cocg" else B.GMRES
+    meth = {"cocg": B.COCG, "gmres": B.GMRES, "gcr": B.GCR}[method]
+    restarted = meth != B.COCG
     X, info = B.solve(cl, Z, M, inc.k_hat, inc.e_hat,
-                      B.solve_opts(tol=1e-6, method=meth, restart=30 if meth == B.GMRES else 500,
-                                   inner_tol=1e-4 if meth == B.GMRES else 1e-2, precond=B.PRECOND_CLUSTER))
+                      B.solve_opts(tol=1e-6, method=meth, restart=30 if restarted else 500,
+                                   inner_tol=1e-4 if restarted else 1e-2, precond=B.PRECOND_CLUSTER))
     say(f"  cycles {info['cycles']} iters {info['iterations']} res {info['max_rel_residual']:.2e}")
     assert info["max_rel_residual"] <= 1e-6
     e = current_err(_np(X), _oracle_x(cloud, inc))
