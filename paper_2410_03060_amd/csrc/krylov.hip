@@ -932,8 +932,9 @@ __global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_
 // reduced per tile in FP64 (tpart[tile][r]); two fixed-order passes then sum
 // tiles per group and groups per cloud.  The gathers of p are latency bound:
 // complex64 tiles ask the compiler for at least six waves per SIMD (the
-// 64-column tile then fits 68 registers instead of 90, seven waves instead of
-// five); complex128 tiles would spill under that bound.
+// 64-column MFMA tile fits 60 registers: eight waves); complex128 tiles would
+// spill under that bound.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 constexpr int COCG_TILE_ROWS = RB / 64;
 template <typename CZ, typename C, int S>
 __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(sizeof(C) == sizeof(c64) ? 6 : 1)))
@@ -966,10 +967,17 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
     const int64_t r = ctile_l * S + c;
     const int64_t rc = r < s ? r : 0;
     c128 dot = {0, 0};
+    // complex64 64-column tiles: the 7x7 block times the 7x64 slab on the FP32
+    // matrix cores (v_mfma_f32_4x4x1_16b_f32: 16 blocks of 4 columns, lane l
+    // = RHS column l; rows 0-3 and 4-7 of the block as two 4-row tiles, row 7
+    // zero; four MFMAs per depth step for the real form of the complex product)
+    constexpr bool PMFMA = S == 64 && sizeof(C) == sizeof(c64) && sizeof(CZ) == sizeof(c64);
     if (i < tl.w1) {   // wave-uniform
         cplx<R> acc[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
+        f32x4_t mr[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        f32x4_t mi[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
         CZ zn = (lane < NB2 && e0 < e1) ? Z[e0 * NB2 + lane] : CZ{0, 0};
         for (int64_t e = e0; e < e1; ++e) {
@@ -987,14 +995,33 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if constexpr (PMFMA) {
 #pragma unroll
-            for (int kk = 0; kk < KK; ++kk) {
-                const int k = g + kk * G;
-                if (k < NB) {
+                for (int k = 0; k < NB; ++k) {
 #pragma unroll
-                    for (int q = 0; q < NB; ++q) cfma(acc[q], ccast<cplx<R>>(zs[w][buf][q * NB + k]), x[kk]);
+                    for (int t = 0; t < 2; ++t) {
+                        const int row = 4 * t + (lane & 3);
+                        const c64 a = row < NB ? ccast<c64>(zs[w][buf][row * NB + k]) : c64{0.f, 0.f};
+                        mr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, (float)x[k].re, mr[t], 0, 0, 0);
+                        mr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(-a.im, (float)x[k].im, mr[t], 0, 0, 0);
+                        mi[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, (float)x[k].im, mi[t], 0, 0, 0);
+                        mi[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.im, (float)x[k].re, mi[t], 0, 0, 0);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) {
+                    const int k = g + kk * G;
+                    if (k < NB) {
+#pragma unroll
+                        for (int q = 0; q < NB; ++q) cfma(acc[q], ccast<cplx<R>>(zs[w][buf][q * NB + k]), x[kk]);
+                    }
                 }
             }
+        }
+        if constexpr (PMFMA) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) acc[q] = cplx<R>{(R)mr[q >> 2][q & 3], (R)mi[q >> 2][q & 3]};
         }
 #pragma unroll
         for (int off = S; off < 64; off <<= 1)
@@ -1118,8 +1145,6 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
     c128 v2 = block_col_reduce(rr, ST, red);
     if (threadIdx.x < ST && r < s) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + r] = v2;
 }
-
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // z = M r for one cluster on the FP32 matrix cores (v_mfma_f32_16x16x4_f32,
 // full FP32 products and sums): wave w forms the 16-column tile
