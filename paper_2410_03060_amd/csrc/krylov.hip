@@ -967,11 +967,16 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
     const int64_t r = ctile_l * S + c;
     const int64_t rc = r < s ? r : 0;
     c128 dot = {0, 0};
-    // complex64 64-column tiles: the 7x7 block times the 7x64 slab on the FP32
-    // matrix cores (v_mfma_f32_4x4x1_16b_f32: 16 blocks of 4 columns, lane l
-    // = RHS column l; rows 0-3 and 4-7 of the block as two 4-row tiles, row 7
-    // zero; four MFMAs per depth step for the real form of the complex product)
-    constexpr bool PMFMA = S == 64 && sizeof(C) == sizeof(c64) && sizeof(CZ) == sizeof(c64);
+    // complex64: the 7x7 block times the slab on the FP32 matrix cores
+    // (v_mfma_f32_4x4x1_16b_f32: 16 blocks of 4 lanes, lane l = RHS column
+    // l % S of depth group l / S; the 4 lanes of an MFMA block share their
+    // group, so each block forms its group's partial sums for 4 columns, and
+    // the groups are added by the cross-lane sums below.  Rows 0-3 and 4-7 of
+    // the block are two 4-row tiles, row 7 zero; four MFMAs per depth step for
+    // the real form of the complex product, in the order of cfma, so the
+    // result rounds exactly as the vector form's)
+    constexpr bool PMFMA = sizeof(C) == sizeof(c64) && sizeof(CZ) == sizeof(c64);
+    static_assert(!PMFMA || S % 4 == 0, "an MFMA block of 4 lanes stays inside one depth group");
     if (i < tl.w1) {   // wave-uniform
         cplx<R> acc[NB];
 #pragma unroll
@@ -997,15 +1002,16 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if constexpr (PMFMA) {
 #pragma unroll
-                for (int k = 0; k < NB; ++k) {
+                for (int kk = 0; kk < KK; ++kk) {
+                    const int k = g + kk * G;
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
                         const int row = 4 * t + (lane & 3);
-                        const c64 a = row < NB ? ccast<c64>(zs[w][buf][row * NB + k]) : c64{0.f, 0.f};
-                        mr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, (float)x[k].re, mr[t], 0, 0, 0);
-                        mr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(-a.im, (float)x[k].im, mr[t], 0, 0, 0);
-                        mi[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, (float)x[k].im, mi[t], 0, 0, 0);
-                        mi[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.im, (float)x[k].re, mi[t], 0, 0, 0);
+                        const c64 a = (row < NB && k < NB) ? ccast<c64>(zs[w][buf][row * NB + k]) : c64{0.f, 0.f};
+                        mr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, (float)x[kk].re, mr[t], 0, 0, 0);
+                        mr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(-a.im, (float)x[kk].im, mr[t], 0, 0, 0);
+                        mi[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, (float)x[kk].im, mi[t], 0, 0, 0);
+                        mi[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.im, (float)x[kk].re, mi[t], 0, 0, 0);
                     }
                 }
             } else {
