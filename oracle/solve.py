@@ -43,23 +43,40 @@ def block_jacobi(Zs, nb: int):
 
 
 def gmres_solve(Zs, u: np.ndarray, nb: int, rtol: float = 1e-12, restart: int = 60,
-                maxiter: int = 400) -> np.ndarray:
-    import scipy.sparse.linalg as spla
-    Pinv = block_jacobi(Zs, nb)
-    n = Pinv.shape[0]
+                maxiter: int = 400, apply_m=None, stats: dict | None = None) -> np.ndarray:
+    """GMRES(restart) on each column of u with a preconditioner M ~ Z^-1.
 
-    def apply_p(v):
-        return np.einsum("nij,nj->ni", Pinv, v.reshape(n, nb)).ravel()
+    M is the block-Jacobi inverse of Sec. II-B unless ``apply_m`` (v -> M v)
+    is given, e.g. the cluster inverse of ``oracle.precond``; the
+    preconditioner changes only the iteration count.  ``stats`` (optional)
+    receives the inner-iteration count of every column under "iterations".
+    """
+    import scipy.sparse.linalg as spla
+    if apply_m is None:
+        Pinv = block_jacobi(Zs, nb)
+        n = Pinv.shape[0]
+
+        def apply_p(v):
+            return np.einsum("nij,nj->ni", Pinv, v.reshape(n, nb)).ravel()
+    else:
+        apply_p = apply_m
 
     M = spla.LinearOperator(Zs.shape, matvec=apply_p, dtype=np.complex128)
     u = np.asarray(u)
     cols = [u] if u.ndim == 1 else [u[:, r] for r in range(u.shape[1])]
     out = []
     for b in cols:
+        count = [0]
+
+        def cb(_res, count=count):
+            count[0] += 1
+
         x, info = spla.gmres(Zs, b, M=M, rtol=rtol, atol=0.0, restart=restart,
-                             maxiter=maxiter)
+                             maxiter=maxiter, callback=cb, callback_type="pr_norm")
         if info != 0:
             raise RuntimeError(f"oracle GMRES did not converge (info={info})")
+        if stats is not None:
+            stats.setdefault("iterations", []).append(count[0])
         out.append(x)
     return out[0] if u.ndim == 1 else np.stack(out, axis=1)
 

@@ -120,6 +120,37 @@ def test_blocks_fp32_dense_far_pairs(B):
     assert ok
 
 
+def test_per_wire_radii_blocks_and_solve(B):
+    """Wires of different radii: reduced distance with a^2 = (a_p^2 + a_p'^2)/2
+    between wires and each wire's own radius on itself, both precisions."""
+    cloud = W.random_cloud(41, 160, box_lam=3.0, d_c_lam=1.0)
+    cloud.radius = np.random.default_rng(42).uniform(0.3e-4, 3e-4, cloud.n) * W.WAVELENGTH
+    inc = W.azimuth_incidences(3)
+    say(f"[blocks] per-wire radii: N={cloud.n}, radii {cloud.radius.min():.2e}..{cloud.radius.max():.2e} m")
+    cl = B.build_cloud(cloud)
+    Z64, P64 = B.fill_Z(cl, B.C128)
+    rows, cols, Zg = gpu_blocks_caller(cl, Z64)
+    Zo = mom.cloud_blocks(cloud, rows=rows, cols=cols)
+    err = rel_block_err(Zg, Zo)
+    say(f"  complex128: max rel block err {err.max():.3e} over {len(err)} blocks")
+    assert err.max() <= 1e-11
+    Z32, P32 = B.fill_Z(cl, B.C64)
+    rows, cols, Zg32 = gpu_blocks_caller(cl, Z32)
+    figs, ok = fp32_block_check(rows, cols, Zg32, Zo)
+    say(f"  complex64: {figs}")
+    assert ok
+    Zs, _ = mom.snfc_matrix(cloud)
+    xo = osolve.sparse_solve(Zs, mom.excitation(cloud, inc.k_hat, inc.e_hat))
+    X, info = B.solve(cl, Z64, P64, inc.k_hat, inc.e_hat, B.solve_opts(tol=1e-12, prec=B.C128, restart=60))
+    e = current_err(_to_np(X), xo)
+    say(f"  complex128 solve: iters {info['iterations']} current err {e.max():.3e}")
+    assert e.max() <= 1e-10
+    X, info = B.solve(cl, Z32, P32, inc.k_hat, inc.e_hat, B.solve_opts(tol=1e-6))
+    e = current_err(_to_np(X), xo)
+    say(f"  complex64 + refinement: iters {info['iterations']} current err {e.max():.3e}")
+    assert info["max_rel_residual"] <= 1e-6 and e.max() <= 1e-4
+
+
 # ----------------------------------------------------------------------------- K-e, K-c
 
 def test_excitation_c2(B):
