@@ -133,14 +133,19 @@ chaff_status chaff_fill_Z(chaff_cloud c, chaff_prec prec, void* Z, void* Pinv,
                           chaff_stream stream);
 
 /* ------------------------------------------------------------------ solve
- * Excitation (eq. 4) for R plane waves, then right block-Jacobi
- * preconditioned restarted GMRES on the S-NFC system, one independent system
- * per (cloud, RHS), all advanced in lockstep so each sparse product serves
- * every right-hand side.  With prec = CHAFF_C64 the Krylov work is complex
- * FP32 and every restart cycle is an iterative-refinement sweep against the
- * FP64 true residual u - Z x (Z the stored matrix, FP64 accumulation).  With
- * CHAFF_C128 everything is FP64.  Stops when every system has
- * ||u - Z x||_2 <= tol * ||u||_2 over its cloud's rows.
+ * Excitation (eq. 4) for R plane waves, then a preconditioned Krylov solve of
+ * the S-NFC system, one independent system per (cloud, RHS), all advanced in
+ * lockstep so each sparse product serves every right-hand side.  The Krylov
+ * method of every cycle is o->method: restarted GMRES(m), COCG (two forms) or
+ * GCR(m), the solver of Sec. II-B (see chaff_method).  The preconditioner is
+ * o->precond: the inverse self blocks (block-diagonal preconditioner of
+ * Sec. II-B) or the cluster inverses of chaff_cluster_precond; GMRES and GCR
+ * apply it on the right, COCG as the symmetric M in z = M r.  With prec =
+ * CHAFF_C64 the Krylov work is complex FP32 and every cycle is an
+ * iterative-refinement sweep against the FP64 true residual u - Z x (Z the
+ * stored matrix, FP64 accumulation).  With CHAFF_C128 everything is FP64.
+ * Stops when every system has ||u - Z x||_2 <= tol * ||u||_2 over its
+ * cloud's rows.
  */
 typedef struct {
     double  tol;              /* relative FP64 residual target per system (1e-6) */
@@ -179,7 +184,8 @@ typedef enum { CHAFF_GMRES = 0, CHAFF_COCG = 1, CHAFF_COCG_RR = 2, CHAFF_GCR = 3
 
 typedef struct {
     int32_t cycles;           /* refinement sweeps (= GMRES restart cycles) run */
-    int32_t iterations;       /* Arnoldi steps summed over cycles */
+    int32_t iterations;       /* Krylov steps (one sparse product each: Arnoldi steps of
+                                 GMRES, COCG or GCR steps) summed over cycles */
     double  max_rel_residual; /* final max over systems of the FP64 relative residual */
     double  seconds;          /* host wall time of the call */
 } chaff_solve_stats;
@@ -192,7 +198,9 @@ size_t chaff_solve_workspace_bytes(chaff_cloud c, const chaff_solve_opts* o, int
  *   X        [N*7][R] complex double, caller order; input guess if use_x0 == 1.
  *   ws       device workspace of chaff_solve_workspace_bytes.
  *   rel_res  [host out, optional] [n_clouds*R] final relative residuals (cloud-major).
- *   Host-synchronising: reads residual estimates once per Arnoldi step. */
+ *   Host-synchronising: once per Krylov step the host reads back the count
+ *   of systems still above their checkpoint (one int32), and once per cycle
+ *   the FP64 residual norms. */
 chaff_status chaff_solve(chaff_cloud c, const chaff_solve_opts* o, const void* Z,
                          const void* Pinv, const double* k_hat, const double* e_hat,
                          int64_t n_rhs, void* X, void* ws, size_t ws_bytes,
@@ -375,9 +383,8 @@ typedef struct {
     char    name[48];
     int64_t launches;
     double  total_ms, min_ms, max_ms;
-    double  work;             /* algorithmic work summed over launches (see work_is_flops) */
-    int32_t work_is_flops;    /* 1: work counts flops; 0: HBM bytes */
-    int32_t reserved;
+    double  bytes;            /* algorithmic HBM bytes summed over launches (0: not stated) */
+    double  flops;            /* algorithmic flops summed over launches (0: not stated) */
 } chaff_kernel_time;
 chaff_status chaff_profile_enable(int32_t on);
 int32_t chaff_profile_read(chaff_kernel_time* out, int32_t max_out);

@@ -56,8 +56,8 @@ class SolveOpts(C.Structure):
 
 class KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
-                ("min_ms", C.c_double), ("max_ms", C.c_double), ("work", C.c_double),
-                ("work_is_flops", C.c_int32), ("reserved", C.c_int32)]
+                ("min_ms", C.c_double), ("max_ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -442,12 +442,13 @@ def profile_enable(on: bool):
 
 
 def profile_read() -> dict:
-    """{kernel: dict(launches, total_ms, min_ms, max_ms, work, unit)} of the tracked launches."""
+    """{kernel: dict(launches, total_ms, min_ms, max_ms, bytes, flops)} of the tracked launches
+    (bytes / flops: algorithmic HBM bytes and flops summed over launches, 0 where not stated)."""
     buf = (KernelTime * 64)()
     n = lib().chaff_profile_read(C.cast(buf, C.c_void_p), 64)
     return {buf[i].name.decode(): dict(launches=int(buf[i].launches), total_ms=buf[i].total_ms,
-                                       min_ms=buf[i].min_ms, max_ms=buf[i].max_ms, work=buf[i].work,
-                                       unit="flop" if buf[i].work_is_flops else "B")
+                                       min_ms=buf[i].min_ms, max_ms=buf[i].max_ms, bytes=buf[i].bytes,
+                                       flops=buf[i].flops)
             for i in range(n)}
 
 

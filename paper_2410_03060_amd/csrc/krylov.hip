@@ -1647,12 +1647,6 @@ static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& 
                        (const int32_t*)c->col_idx, Z, p, q, sh.s, L.tpart);
 }
 
-// One COCG refinement cycle.  L.r holds the FP64 true residual; it replaces the
-// recursive residual (in units of the run's fixed per-system scale), while the
-// search direction p and r^T z carry over from the previous cycle ("reliable
-// updates"): no Krylov information is thrown away at a refinement checkpoint.
-// The cycle ends once every active system's recursive residual fell below its
-// checkpoint (or its final target); then x += scale * (accumulated correction).
 // Column compaction inside a COCG cycle: once at most half of the current
 // RHS tile width still has a system above its checkpoint, the finished
 // columns are dropped -- their accumulated corrections are flushed into the
@@ -1772,7 +1766,8 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         const int wst = spmm_tile_width(cs.s);
         if (clus) {   // r -= alpha q, z = M r (over q), r^T z, ||r||^2
             ProfScope pu(wst == 64 ? "k_cg_update" : "k_cg_update_narrow", st,
-                         (4.0 * rows * cs.s) * sizeof(C) + (double)cluster_count(c) * CLR2 * sizeof(CZ));
+                         ProfWork{(4.0 * rows * cs.s) * sizeof(C) + (double)cluster_count(c) * CLR2 * sizeof(CZ),
+                                  8.0 * CLR2 * (double)cluster_count(c) * cs.s});
             switch (wst) {
                 case 1: launch_cg_update_cl<CZ, C, 1>(cs, Lc, Mb, q, r, st); break;
                 case 2: launch_cg_update_cl<CZ, C, 2>(cs, Lc, Mb, q, r, st); break;
@@ -1868,9 +1863,12 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         CHAFF_LAUNCH_CHECK();
         {   // q = Z p with per-tile p^T q
             // full-width launches are timed apart from the narrower ones after a compaction
+            // algorithmic work: Z with its column indices and row pointers once,
+            // p gathered once and q written once; 8 NB^2 flops per block and column
             ProfScope ps(cs.cocg_st == 64 ? "spmm" : "spmm_narrow", st,
-                         ((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 8.0 * (c->n + 1) +
-                                         3.0 * rows * cs.s * sizeof(C));
+                         ProfWork{((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 4.0 * (c->n + 1) +
+                                      2.0 * rows * cs.s * sizeof(C),
+                                  8.0 * NB2 * (double)c->nnzb * cs.s});
             switch (cs.cocg_st) {
                 case 8: launch_cocg_spmm<CZ, C, 8>(c, cs, Lc, Z, p, q, st); break;
                 case 16: launch_cocg_spmm<CZ, C, 16>(c, cs, Lc, Z, p, q, st); break;

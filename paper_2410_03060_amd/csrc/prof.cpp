@@ -19,8 +19,7 @@ namespace {
 struct Rec {
     int name;
     hipEvent_t a, b;
-    double work;
-    bool flops;
+    ProfWork w;
 };
 std::atomic<int> g_on{0};
 std::mutex g_mu;
@@ -45,14 +44,14 @@ int name_id(const char* n) {
 }
 }  // namespace
 
-ProfScope::ProfScope(const char* name, hipStream_t st, double work, bool flops) : st_(st) {
+ProfScope::ProfScope(const char* name, hipStream_t st, ProfWork w) : st_(st) {
     if (!g_on.load(std::memory_order_relaxed)) return;
     std::lock_guard<std::mutex> lk(g_mu);
     hipEvent_t a = take_event(), b = take_event();
     if (!a || !b) return;
     if (hipEventRecord(a, st) != hipSuccess) return;
     rec_ = (int)g_recs.size();
-    g_recs.push_back(Rec{name_id(name), a, b, work, flops});
+    g_recs.push_back(Rec{name_id(name), a, b, w});
 }
 
 ProfScope::~ProfScope() {
@@ -94,8 +93,8 @@ int32_t chaff_profile_read(chaff_kernel_time* out, int32_t max_out) {
         k.total_ms += ms;
         k.min_ms = std::min(k.min_ms, (double)ms);
         k.max_ms = std::max(k.max_ms, (double)ms);
-        k.work += r.work;
-        k.work_is_flops = r.flops ? 1 : 0;
+        k.bytes += r.w.bytes;
+        k.flops += r.w.flops;
     }
     int32_t n = 0;
     for (auto& k : agg) {
