@@ -6,8 +6,9 @@
 // Everything is FP64 (the phase k r_hat . c_p reaches hundreds of radians).
 //
 //  * monostatic: direction m pairs with RHS m; blocks reduce fixed wire
-//    chunks of one cloud with wave64 shuffles + LDS, then a second pass sums
-//    the chunks of each cloud in order (no atomics, bit-reproducible);
+//    chunks of one cloud, lanes split between RHS columns and wire slots, the
+//    slots folded with wavefront shuffles and the waves through LDS; a second
+//    pass sums the chunks of each cloud in order (no atomics, bit-reproducible);
 //  * bistatic: one thread per direction, the chunk's wires and currents
 //    staged in LDS, partial sums per chunk, same second pass.
 #include "common.hpp"
@@ -48,33 +49,59 @@ __device__ __forceinline__ c128 wire_term(const Wire& w, const c128* __restrict_
 }
 
 // partial[chunk][r] for monostatic pairs (dir r, rhs r); X caller order.
-// Lanes are RHS columns, so each wire row of X is one coalesced load; the four
-// waves take every fourth wire of the chunk and are combined in wave order.
+// A wave is RT RHS columns x (64 / RT) wire slots: lane (g, c) = (lane / RT,
+// lane % RT) sums the terms of wires w0 + (4 wv + g) + 256/RT * k, so a wire
+// row of RT columns is one contiguous load for the RT lanes of a slot.  The
+// slots are then folded with wavefront shuffles (xor over the slot bits) and
+// the four waves combined in wave order through LDS: a fixed summation order
+// (bit-reproducible, no atomics).  RT is the smallest power of two >= R
+// (at most 64), so few RHS columns do not leave lanes idle.
+template <int RT>
 __global__ __launch_bounds__(256) void k_mono(const Wire* __restrict__ wires, const int32_t* __restrict__ perm,
                                               const int64_t* __restrict__ chunk_w0, int n_chunks, int64_t R,
                                               const c128* __restrict__ X, const double* __restrict__ dir,
                                               const double* __restrict__ pol, double k, c128* __restrict__ part) {
-    __shared__ c128 red[4][64];
+    constexpr int G = 64 / RT;   // wire slots per wave
+    __shared__ c128 red[4][RT];
     const int ch = blockIdx.x;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane / RT, c = lane % RT;
+    const int64_t r = (int64_t)blockIdx.y * RT + c;
     const int64_t w0 = chunk_w0[ch], w1 = chunk_w0[ch + 1];
     c128 acc = {0, 0};
     if (r < R) {
         const double rx = dir[3 * r], ry = dir[3 * r + 1], rz = dir[3 * r + 2];
         const double ex = pol[3 * r], ey = pol[3 * r + 1], ez = pol[3 * r + 2];
-        for (int64_t i = w0 + w; i < w1; i += 4) {
+        for (int64_t i = w0 + wv * G + g; i < w1; i += 4 * G) {
             const Wire wr = wires[i];
             const c128* xp = X + (int64_t)perm[i] * NB * R + r;
             acc = cadd(acc, wire_term(wr, xp, R, k, rx, ry, rz, ex, ey, ez));
         }
     }
-    red[w][lane] = acc;
+#pragma unroll
+    for (int off = RT; off < 64; off <<= 1) {
+        acc.re += __shfl_xor(acc.re, off, 64);
+        acc.im += __shfl_xor(acc.im, off, 64);
+    }
+    if (g == 0) red[wv][c] = acc;
     __syncthreads();
-    if (w == 0 && r < R) {
-        c128 t = red[0][lane];
-        for (int q = 1; q < 4; ++q) t = cadd(t, red[q][lane]);
+    if (wv == 0 && g == 0 && r < R) {
+        c128 t = red[0][c];
+        for (int q = 1; q < 4; ++q) t = cadd(t, red[q][c]);
         part[(int64_t)ch * R + r] = t;
+    }
+}
+
+static void launch_mono(dim3 grid_x, int64_t R, hipStream_t st, const Wire* wires, const int32_t* perm,
+                        const int64_t* w0, int nch, const c128* X, const double* dir, const double* pol, double k,
+                        c128* part) {
+    const int rt = R >= 64 ? 64 : R > 16 ? 32 : R > 8 ? 16 : R > 4 ? 8 : R > 2 ? 4 : R > 1 ? 2 : 1;
+    const dim3 grid(grid_x.x, (unsigned)((R + rt - 1) / rt));
+    switch (rt) {
+#define CHAFF_MONO(T) \
+    case T: hipLaunchKernelGGL(k_mono<T>, grid, dim3(256), 0, st, wires, perm, w0, nch, R, X, dir, pol, k, part); break;
+        CHAFF_MONO(1) CHAFF_MONO(2) CHAFF_MONO(4) CHAFF_MONO(8) CHAFF_MONO(16) CHAFF_MONO(32) CHAFF_MONO(64)
+#undef CHAFF_MONO
     }
 }
 
@@ -162,8 +189,8 @@ chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const d
         ProfScope ps(mono ? "rcs_mono" : "rcs_bistatic", st,
                      mono ? 16.0 * NB * (double)c->n * R + 64.0 * c->n : 55.0 * (double)c->n * R * M, !mono);
         if (mono) {
-            hipLaunchKernelGGL(k_mono, dim3(nch, (unsigned)((R + 63) / 64)), dim3(256), 0, st, (const Wire*)c->wires,
-                               (const int32_t*)c->perm, (const int64_t*)d_w0, nch, R, X, dir, pol, k, part);
+            launch_mono(dim3(nch), R, st, (const Wire*)c->wires, (const int32_t*)c->perm, (const int64_t*)d_w0, nch,
+                        X, dir, pol, k, part);
         } else {
             dim3 grid((unsigned)((M + 255) / 256), nch, (unsigned)R);
             hipLaunchKernelGGL(k_bistatic, grid, dim3(256), 0, st, (const Wire*)c->wires, (const int32_t*)c->perm,
