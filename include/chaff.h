@@ -282,6 +282,25 @@ chaff_status chaff_rcs(chaff_cloud c, const void* X, int64_t n_rhs, const double
                        const double* obs_pol, int64_t n_dirs, int32_t monostatic,
                        double* sigma, void* ws, size_t ws_bytes, chaff_stream stream);
 
+/* ------------------------------------------------------------------ rcs without a workspace
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): chaff_rcs with
+ * the same arguments and results but no workspace.  Its scratch (chunk bounds
+ * and per-chunk partial sums, chaff_rcs_workspace_bytes of them) lives in a
+ * fixed device array of CHAFF_RCS_SCRATCH_BYTES inside the library, one copy
+ * per GPU, held until the process ends; the call allocates nothing.  It runs
+ * on the current device (the stream must belong to it) and synchronises the
+ * stream before returning, as chaff_rcs does.
+ * Returns CHAFF_EWORKSPACE if chaff_rcs_workspace_bytes(c, n_rhs, n_dirs,
+ * monostatic) exceeds CHAFF_RCS_SCRATCH_BYTES (then use chaff_rcs).
+ * Every call on one GPU uses that GPU's one array: calls that overlap in time
+ * on one GPU (several host threads or streams) race and must be serialised by
+ * the caller. */
+#define CHAFF_RCS_SCRATCH_BYTES (64u << 20)
+chaff_status chaff_rcs_noalloc(chaff_cloud c, const void* X, int64_t n_rhs, const double* obs_dir,
+                               const double* obs_pol, int64_t n_dirs, int32_t monostatic, double* sigma,
+                               chaff_stream stream);
+
 /* ------------------------------------------------------------------ learned initial guess
  * Not part of the paper's method.  A small network predicts, for each wire p
  * and incidence r, the wire's 7 currents from its neighbourhood; the result

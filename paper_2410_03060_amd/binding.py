@@ -84,6 +84,8 @@ EXPORTS = {
     "chaff_rcs_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int64, C.c_int64, C.c_int32]),
     "chaff_rcs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                             C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "chaff_rcs_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.c_int32, C.c_void_p, C.c_void_p]),
     "chaff_destroy": (None, [C.c_void_p]),
     "chaff_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                  C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_void_p]),
@@ -408,6 +410,19 @@ def rcs(cl: Cloud, X, obs_dir, obs_pol, monostatic: bool):
     sig = torch.empty(shape, dtype=torch.float64, device=cl.device)
     _check(lib().chaff_rcs(cl.handle, _ptr(X), R, _ptr(d), _ptr(p), M, int(monostatic), _ptr(sig),
                            _ptr(ws), need, _stream()))
+    return sig
+
+
+def rcs_noalloc(cl: Cloud, X, obs_dir, obs_pol, monostatic: bool):
+    """sigma per cloud through chaff_rcs_noalloc (no workspace; the library's fixed scratch)."""
+    d = _dev_f64(_2d(obs_dir), cl.device)
+    p = _dev_f64(_2d(obs_pol), cl.device)
+    R = X.shape[1]
+    M = d.shape[0]
+    shape = (cl.n_clouds, R) if monostatic else (cl.n_clouds, R, M)
+    sig = torch.empty(shape, dtype=torch.float64, device=cl.device)
+    _check(lib().chaff_rcs_noalloc(cl.handle, _ptr(X), R, _ptr(d), _ptr(p), M, int(monostatic), _ptr(sig),
+                                   _stream()))
     return sig
 
 

@@ -76,6 +76,8 @@ chaff_status spmm_public(Cloud* c, chaff_prec prec, const void* Z, const void* X
 size_t rcs_workspace_bytes(const Cloud* c, int64_t R, int64_t M, int32_t mono);
 chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const double* pol, int64_t M, int32_t mono,
                  double* sigma, void* ws, size_t ws_bytes, hipStream_t st);
+chaff_status rcs_noalloc(Cloud* c, const void* X, int64_t R, const double* dir, const double* pol, int64_t M,
+                         int32_t mono, double* sigma, hipStream_t st);
 chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y, int64_t s, int32_t* best,
                       double* best_ms, hipStream_t st);
 int32_t tune_report(char* buf, int32_t len);
@@ -422,6 +424,18 @@ chaff_status chaff_rcs(chaff_cloud h, const void* X, int64_t n_rhs, const double
     size_t need = rcs_workspace_bytes(&h->c, n_rhs, n_dirs, monostatic);
     if (ws_bytes < need) return fail(CHAFF_EWORKSPACE, "rcs workspace too small: need " + std::to_string(need));
     return rcs(&h->c, X, n_rhs, obs_dir, obs_pol, n_dirs, monostatic, sigma, ws, ws_bytes, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_rcs_noalloc(chaff_cloud h, const void* X, int64_t n_rhs, const double* obs_dir,
+                               const double* obs_pol, int64_t n_dirs, int32_t monostatic, double* sigma,
+                               chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !X || !obs_dir || !obs_pol || !sigma) return fail(CHAFF_EINVAL, "NULL argument");
+    if (n_rhs < 1 || n_dirs < 1) return fail(CHAFF_EINVAL, "n_rhs and n_dirs must be >= 1");
+    if (monostatic && n_dirs != n_rhs) return fail(CHAFF_EINVAL, "monostatic needs n_dirs == n_rhs");
+    if (!monostatic && n_rhs > 65535) return fail(CHAFF_EINVAL, "bistatic n_rhs must be <= 65535");
+    return rcs_noalloc(&h->c, X, n_rhs, obs_dir, obs_pol, n_dirs, monostatic, sigma, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
 

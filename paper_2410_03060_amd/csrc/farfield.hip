@@ -15,6 +15,7 @@
 #include "prof.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 namespace chaff {
 
@@ -204,6 +205,47 @@ chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const d
     CHAFF_LAUNCH_CHECK();
     CHAFF_HIP(hipStreamSynchronize(st));  // host staging vectors go out of scope
     return CHAFF_OK;
+}
+
+// ------------------------------------------------------------------ far field without a workspace
+// The scratch of chaff_rcs (chunk bounds, cloud chunk offsets, per-chunk
+// partial sums) in a fixed device array of the library, one copy per GPU.  The
+// array's name is only a host-side stand-in: its device address on the current
+// GPU is looked up once per device with hipGetSymbolAddress and used for every
+// kernel argument and copy.
+static __device__ __align__(256) unsigned char scratch[CHAFF_RCS_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+static chaff_status scratch_address(void** out) {
+    int dev = -1;
+    CHAFF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(CHAFF_EINVAL, "device index out of range for the fixed scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        CHAFF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(CHAFF_EHIP, "hipGetSymbolAddress returned no address for the fixed scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CHAFF_OK;
+}
+
+chaff_status rcs_noalloc(Cloud* c, const void* X, int64_t R, const double* dir, const double* pol, int64_t M,
+                         int32_t mono, double* sigma, hipStream_t st) {
+    const size_t need = rcs_workspace_bytes(c, R, M, mono);
+    if (need > (size_t)CHAFF_RCS_SCRATCH_BYTES)
+        return fail(CHAFF_EWORKSPACE, "rcs scratch of " + std::to_string(need) + " bytes exceeds the fixed " +
+                                          std::to_string((size_t)CHAFF_RCS_SCRATCH_BYTES) + " bytes");
+    void* ws = nullptr;
+    chaff_status e = scratch_address(&ws);
+    if (e != CHAFF_OK) return e;
+    return rcs(c, X, R, dir, pol, M, mono, sigma, ws, (size_t)CHAFF_RCS_SCRATCH_BYTES, st);
 }
 
 }  // namespace chaff
