@@ -33,9 +33,9 @@ FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed) peak, TFLOP/s
 
 # profile name -> (kernel symbol prefix in rocprofv3 output, source file)
 KERNEL_SYMBOLS = {
-    "spmm": ("chaff::k_cocg_spmm", "paper_2410_03060_amd/csrc/krylov.hip"),
-    "k_cg_update": ("chaff::k_cg_update", "paper_2410_03060_amd/csrc/krylov.hip"),
-    "k_cg_p": ("chaff::k_cg_p", "paper_2410_03060_amd/csrc/krylov.hip"),
+    "spmm": ("chaff::kr7::k_cocg_spmm", "paper_2410_03060_amd/csrc/krylov_impl.hpp"),
+    "k_cg_update": ("chaff::kr7::k_cg_update", "paper_2410_03060_amd/csrc/krylov_impl.hpp"),
+    "k_cg_p": ("chaff::kr7::k_cg_p", "paper_2410_03060_amd/csrc/krylov_impl.hpp"),
     "fill_mutual": ("chaff::k_mutual", "paper_2410_03060_amd/csrc/fill.hip"),
     "fill_self": ("chaff::k_self", "paper_2410_03060_amd/csrc/fill.hip"),
     "rcs_mono": ("chaff::k_mono", "paper_2410_03060_amd/csrc/farfield.hip"),
@@ -44,10 +44,14 @@ KERNEL_SYMBOLS = {
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
-def source_hash(rel: str) -> str:
+def source_hash(rel: str):
+    """First 16 hex digits of the source's SHA-256, or None if the file is gone."""
     import hashlib
-    with open(os.path.join(ROOT, rel), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    try:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
 
 
 def measured_traffic(config: str, kernel: str):
@@ -516,8 +520,8 @@ def main(argv=None) -> int:
         roof["traffic"] = measured_traffic(a.config, name)
         symbols = dict(KERNEL_SYMBOLS)
         if pc == "cluster":   # the cluster path runs its own update and direction kernels
-            symbols.update({"k_cg_update": ("chaff::k_cg_update_cl", KERNEL_SYMBOLS["k_cg_update"][1]),
-                            "k_cg_p": ("chaff::k_cg_pdir_z", KERNEL_SYMBOLS["k_cg_p"][1])})
+            symbols.update({"k_cg_update": ("chaff::kr7::k_cg_update_cl", KERNEL_SYMBOLS["k_cg_update"][1]),
+                            "k_cg_p": ("chaff::kr7::k_cg_pdir_z", KERNEL_SYMBOLS["k_cg_p"][1])})
         roof.update({"kernel": name, "symbol": symbols.get(name, (name,))[0], "launches": k["launches"],
                      "avg_ms": k["total_ms"] / k["launches"],
                      "timing": "HIP events recorded on the launch stream around every launch in the timed steps"})

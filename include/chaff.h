@@ -5,8 +5,9 @@
  *
  * Problem statement (Sec. II-A): N thin perfectly conducting straight wires of
  * arbitrary centre, orientation, length and radius are illuminated by plane
- * waves.  Each wire is cut into 8 equal segments carrying 7 rooftop unknowns
- * (eq. 2 and its footnote; the paper's own runs use 19 unknowns per wire).
+ * waves.  Each wire is cut into n_seg equal segments carrying n_seg - 1
+ * rooftop unknowns (eq. 2 and its footnote): n_seg = 8 (7 unknowns), or
+ * n_seg = 20 (19 unknowns), the discretisation of the paper's own runs.
  * The Galerkin EFIE system Z x = u (eqs. 3-8) is kept only on wire pairs
  * whose centroid distance is <= d_c (eq. 9) and solved iteratively with a
  * block-diagonal preconditioner (Sec. II-B); the far-field functional then
@@ -18,8 +19,9 @@
  *    (a^2 = (a_p^2 + a_p'^2)/2 between wires of different radius).
  *  - Units are metres; only the wavelength enters (k = 2 pi / wavelength).
  *  - Unknown order is wire-major in the CALLER's wire order:
- *    n = p*7 + q, q = 0..6 counted from the -L/2 end along the tangent.
- *    Multi-RHS vectors are row-major [N*7][R] (element (n, r) at n*R + r).
+ *    n = p*NB + q, q = 0..NB-1 counted from the -L/2 end along the tangent,
+ *    NB = n_seg - 1 unknowns per wire.  Multi-RHS vectors are row-major
+ *    [N*NB][R] (element (n, r) at n*R + r).  Blocks are NB x NB.
  *  - x is the solution of Z x = u with u the tested incident field
  *    u_n = int L_n (t_n . e) exp(-j k k_hat . r) ds (eq. 4 without its
  *    -(j/(w mu0)) factor).  The physical current is -(j/(w mu0)) x, and for a
@@ -60,13 +62,15 @@ typedef enum { CHAFF_C64 = 0, CHAFF_C128 = 1 } chaff_prec;
 
 typedef struct chaff_cloud_s* chaff_cloud;   /* opaque handle, host memory owned by the library */
 
-#define CHAFF_NSEG 8          /* segments per wire */
-#define CHAFF_NB 7            /* unknowns per wire */
+#define CHAFF_NSEG 8          /* segments per wire of the default discretisation */
+#define CHAFF_NB 7            /* its unknowns per wire */
+#define CHAFF_NSEG_PAPER 20   /* the paper's own discretisation: 19 unknowns per wire */
 
 typedef struct {
     int64_t n_wires;          /* total wires over all clouds, >= 1 */
     int32_t n_clouds;         /* independent clouds, >= 1 (pairs never cross clouds) */
-    int32_t n_seg;            /* must be CHAFF_NSEG */
+    int32_t n_seg;            /* CHAFF_NSEG (8) or CHAFF_NSEG_PAPER (20); the cluster
+                                 preconditioner and the learned guess need 8 */
     double  wavelength;       /* metres, > 0 */
     double  d_c;              /* coupling threshold (eq. 9), metres, >= 0; INFINITY = dense */
     int32_t quad_mutual;      /* Gauss-Legendre nodes per segment, different wires (1..8; 4) */
@@ -79,7 +83,7 @@ typedef struct {
  * pair (p, p') of one cloud with ((dx*dx + dy*dy) + dz*dz) <= d_c*d_c in
  * IEEE double without fused multiply-add (dx = c_p'.x - c_p.x, ...).
  * Wires are reordered internally along a Morton curve of a cell grid
- * (cell side >= d_c); the block pattern (CSR of 7x7 blocks) is stored in that
+ * (cell side >= d_c); the block pattern (CSR of NB x NB blocks) is stored in that
  * internal order and its permutation is returned by chaff_get_info.
  *
  * chaff_build_workspace_bytes: [host only] bytes the build workspace needs.
@@ -123,8 +127,8 @@ chaff_status chaff_get_info(chaff_cloud c, chaff_cloud_info* info /* [host out] 
  * static part 1/(4 pi R) of touching and identical segments is integrated in
  * closed form ("analytic singularity extraction").  Z = Z^T block-wise: each
  * unique pair is computed once and stored twice.
- *   Z    [nnzb][7][7] complex (prec), internal block order, row-major blocks.
- *   Pinv [N][7][7] complex (prec) or NULL: inverse of every self block
+ *   Z    [nnzb][NB][NB] complex (prec), internal block order, row-major blocks.
+ *   Pinv [N][NB][NB] complex (prec) or NULL: inverse of every self block
  *        (block-diagonal preconditioner of Sec. II-B), internal wire order.
  * Returns CHAFF_ESINGULAR (after the stream completes) if a self block has a
  * zero pivot.
@@ -163,7 +167,7 @@ typedef struct {
 } chaff_solve_opts;
 
 /* Preconditioner passed to chaff_solve as Pinv.
- *   CHAFF_PRECOND_BLOCK   [N][7][7] inverse self blocks from chaff_fill_Z
+ *   CHAFF_PRECOND_BLOCK   [N][NB][NB] inverse self blocks from chaff_fill_Z
  *                         (the block-diagonal preconditioner of Sec. II-B);
  *   CHAFF_PRECOND_CLUSTER the buffer of chaff_cluster_precond (inverse
  *                         diagonal blocks of groups of 8 nearby wires). */
@@ -195,7 +199,7 @@ size_t chaff_solve_workspace_bytes(chaff_cloud c, const chaff_solve_opts* o, int
  *            (same prec; COCG needs both symmetric: they are).
  *   restart  GMRES cycle length, or the step cap of one COCG cycle.
  *   k_hat, e_hat [R][3] double: propagation direction and polarisation (unit).
- *   X        [N*7][R] complex double, caller order; input guess if use_x0 == 1.
+ *   X        [N*NB][R] complex double, caller order; input guess if use_x0 == 1.
  *   ws       device workspace of chaff_solve_workspace_bytes.
  *   rel_res  [host out, optional] [n_clouds*R] final relative residuals (cloud-major).
  *   Host-synchronising: once per Krylov step the host reads back the count
@@ -214,7 +218,8 @@ chaff_status chaff_solve(chaff_cloud c, const chaff_solve_opts* o, const void* Z
  * shorter.  A cluster's block is the inverse, computed in FP64 with partial
  * pivoting, of the cluster's (7 w x 7 w) diagonal submatrix of Z, padded to
  * CHAFF_CLUSTER_ROWS x CHAFF_CLUSTER_ROWS with the identity.  Each block is
- * complex symmetric, as Z is, so COCG may use it.
+ * complex symmetric, as Z is, so COCG may use it.  Wires of 8 segments only
+ * (CHAFF_EINVAL for a cloud built with n_seg = 20).
  *
  * Buffer M (device, 256-byte aligned, chaff_cluster_precond_bytes):
  *   [n_clusters] { int32 first wire (internal index), int32 wires }, padded
@@ -223,7 +228,7 @@ chaff_status chaff_solve(chaff_cloud c, const chaff_solve_opts* o, const void* Z
  * It is tied to the handle it was built for and to Z of the same prec. */
 #define CHAFF_CLUSTER_WIRES 8
 #define CHAFF_CLUSTER_ROWS 56
-int64_t chaff_cluster_count(chaff_cloud c);   /* number of clusters; -1 for a NULL handle */
+int64_t chaff_cluster_count(chaff_cloud c);   /* number of clusters; -1 for a NULL handle or 20 segments */
 size_t chaff_cluster_precond_bytes(chaff_cloud c, chaff_prec prec);   /* 0 on a bad argument */
 /* Builds M from Z (chaff_fill_Z, same prec).  Host-synchronising; returns
  * CHAFF_ESINGULAR if a cluster block has a zero pivot (M is then unusable). */
@@ -237,14 +242,14 @@ chaff_status chaff_cluster_precond(chaff_cloud c, chaff_prec prec, const void* Z
 chaff_status chaff_cluster_apply(chaff_cloud c, chaff_prec prec, const void* M, const void* X,
                                  void* Y, int64_t s, chaff_stream stream);
 
-/* Excitation alone: U [N*7][R] complex double (caller order), eq. (4) without
+/* Excitation alone: U [N*NB][R] complex double (caller order), eq. (4) without
  * its -(j/(w mu0)) factor, closed-form triangle transform. */
 chaff_status chaff_excitation(chaff_cloud c, const double* k_hat, const double* e_hat,
                               int64_t n_rhs, void* U, chaff_stream stream);
 
 /* Block-sparse product Y = Z X on the internal order (the matvec of the
  * Krylov solver, complexity O(b_mean N) of Sec. II-B).
- *   X, Y [N*7][s] complex (prec), internal order, row-major.
+ *   X, Y [N*NB][s] complex (prec), internal order, row-major.
  *   variant -1 = the tuned/heuristic choice. */
 chaff_status chaff_spmm(chaff_cloud c, chaff_prec prec, const void* Z, const void* X,
                         void* Y, int64_t s, int32_t variant, chaff_stream stream);
@@ -256,7 +261,7 @@ chaff_status chaff_spmm(chaff_cloud c, chaff_prec prec, const void* Z, const voi
  * accumulating up to 16 RHS columns, every Z row loaded once; 6: one wave per
  * block row (4, 2 and 4 rows per wave at 4, 8 and 16 columns), the blocks
  * staged in LDS; 7: 6 in XCD-aware order) for this cloud, precision
- * and RHS count on the caller's Z and two [N*7][s] buffers (contents of Y are
+ * and RHS count on the caller's Z and two [N*NB][s] buffers (contents of Y are
  * overwritten, X is read), and records the fastest in a process-wide table
  * keyed by (N, nnzb, s, prec).  Every later call with variant -1 (chaff_spmm,
  * and the products inside chaff_solve, including the COCG product's tile
@@ -269,7 +274,7 @@ chaff_status chaff_autotune(chaff_cloud c, chaff_prec prec, const void* Z, void*
 int32_t chaff_tune_report(char* buf, int32_t len);
 
 /* ------------------------------------------------------------------ rcs
- * Far field of the currents X (caller order, complex double [N*7][R]):
+ * Far field of the currents X (caller order, complex double [N*NB][R]):
  * S = sum_n w_n(r_hat, e) x_n with w_n = int L_n (t_n . e) exp(+j k r_hat . r) ds,
  * sigma = |S|^2/(4 pi) [m^2], summed separately over each cloud.
  *   monostatic = 1: M == R, observation m pairs with RHS m;
@@ -341,7 +346,8 @@ chaff_status chaff_rcs_noalloc(chaff_cloud c, const void* X, int64_t n_rhs, cons
  *   y[2q] + j y[2q+1] = (x~_{p,q} - b~_{p,q}) exp(+j k k_hat.c_p) / 0.5,
  * b~ the canonical form of b.
  * Loss: mean over rows and the 14 outputs of (y - t)^2.
- * Buffers must be 16-byte aligned.  Requires a finite d_c > 0. */
+ * Buffers must be 16-byte aligned.  Requires a finite d_c > 0 and wires of
+ * 8 segments. */
 #define CHAFF_MLP_K 16
 #define CHAFF_MLP_NFEAT 192
 #define CHAFF_MLP_HIDDEN 128
@@ -409,6 +415,14 @@ chaff_status chaff_profile_enable(int32_t on);
 int32_t chaff_profile_read(chaff_kernel_time* out, int32_t max_out);
 
 /* ------------------------------------------------------------------ misc */
+/* The product-variant tuning table as JSON, written to / merged from a file
+ * (entries keyed by unknowns per wire, wires, stored blocks, RHS count and
+ * precision; a loaded entry replaces a recorded one with the same key).
+ * chaff_tune_load: n_entries [host out, optional] entries read; CHAFF_EINVAL
+ * if the file cannot be read or is not such a table (nothing is changed). */
+chaff_status chaff_tune_save(const char* path);
+chaff_status chaff_tune_load(const char* path, int32_t* n_entries);
+
 void chaff_destroy(chaff_cloud c);
 const char* chaff_last_error(void);
 const char* chaff_version(void);

@@ -90,6 +90,8 @@ EXPORTS = {
     "chaff_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                  C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_void_p]),
     "chaff_tune_report": (C.c_int32, [C.c_char_p, C.c_int32]),
+    "chaff_tune_save": (C.c_int, [C.c_char_p]),
+    "chaff_tune_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_int32)]),
     "chaff_profile_enable": (C.c_int, [C.c_int32]),
     "chaff_profile_read": (C.c_int32, [C.c_void_p, C.c_int32]),
     "chaff_mlp_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
@@ -177,6 +179,12 @@ class Cloud:
     wavelength: float
     d_c: float
     device: torch.device
+    nseg: int = NSEG
+
+    @property
+    def nb(self) -> int:
+        """Rooftop unknowns per wire (n_seg - 1)."""
+        return self.nseg - 1
 
     def info(self) -> CloudInfo:
         inf = CloudInfo()
@@ -238,6 +246,7 @@ class DeviceGeometry:
     cloud_off: np.ndarray
     wavelength: float
     d_c: float
+    n_seg: int = NSEG
 
     @property
     def n(self) -> int:
@@ -253,7 +262,7 @@ def upload(cloud, device="cuda") -> DeviceGeometry:
     return DeviceGeometry(_dev_f64(cloud.center, device), _dev_f64(cloud.tangent, device),
                           _dev_f64(cloud.length, device), _dev_f64(cloud.radius, device),
                           np.asarray(cloud.cloud_off, dtype=np.int64), float(cloud.wavelength),
-                          float(cloud.d_c))
+                          float(cloud.d_c), int(getattr(cloud, "n_seg", NSEG)))
 
 
 def build_cloud(cloud, device="cuda", max_nnzb: int | None = None, quad_mutual: int = 4,
@@ -261,7 +270,8 @@ def build_cloud(cloud, device="cuda", max_nnzb: int | None = None, quad_mutual: 
     """Neighbour search and internal layout for a (multi-)cloud (chaff_build_cloud).
 
     ``cloud`` is a host workload (numpy arrays, uploaded here) or a
-    DeviceGeometry already in device memory.
+    DeviceGeometry already in device memory.  Its ``n_seg`` (8, or 20 for the
+    paper's 19 unknowns per wire) sets the discretisation.
     """
     if not isinstance(cloud, DeviceGeometry):
         cloud = upload(cloud, device)
@@ -273,7 +283,7 @@ def build_cloud(cloud, device="cuda", max_nnzb: int | None = None, quad_mutual: 
     if max_nnzb is None:
         max_nnzb = n * n if not math.isfinite(cloud.d_c) else min(n * n, 24 * n + 64)
     for _ in range(2):
-        p = Params(n, nc, NSEG, float(cloud.wavelength), float(cloud.d_c), quad_mutual, quad_self,
+        p = Params(n, nc, int(cloud.n_seg), float(cloud.wavelength), float(cloud.d_c), quad_mutual, quad_self,
                    int(max_nnzb))
         need = lib().chaff_build_workspace_bytes(n, nc, int(max_nnzb))
         if need == 0:
@@ -287,17 +297,18 @@ def build_cloud(cloud, device="cuda", max_nnzb: int | None = None, quad_mutual: 
             max_nnzb = int(nnzb.value)
             continue
         _check(st)
-        out = Cloud(h, ws, n, nc, int(nnzb.value), 0, float(cloud.wavelength), float(cloud.d_c), device)
+        out = Cloud(h, ws, n, nc, int(nnzb.value), 0, float(cloud.wavelength), float(cloud.d_c), device,
+                    int(cloud.n_seg))
         out.n_pairs = int(out.info().n_pairs)
         return out
     raise ChaffError(EWORKSPACE, last_error())
 
 
 def fill_Z(cl: Cloud, prec: int = C64, with_pinv: bool = True):
-    """Impedance blocks [nnzb,7,7] and inverse self blocks [N,7,7] (chaff_fill_Z)."""
+    """Impedance blocks [nnzb,nb,nb] and inverse self blocks [N,nb,nb] (chaff_fill_Z)."""
     dt = torch.complex64 if prec == C64 else torch.complex128
-    Z = torch.empty((cl.nnzb, NB, NB), dtype=dt, device=cl.device)
-    P = torch.empty((cl.n, NB, NB), dtype=dt, device=cl.device) if with_pinv else None
+    Z = torch.empty((cl.nnzb, cl.nb, cl.nb), dtype=dt, device=cl.device)
+    P = torch.empty((cl.n, cl.nb, cl.nb), dtype=dt, device=cl.device) if with_pinv else None
     _check(lib().chaff_fill_Z(cl.handle, prec, _ptr(Z), _ptr(P), _stream()))
     return Z, P
 
@@ -364,7 +375,7 @@ def solve(cl: Cloud, Z, Pinv, k_hat, e_hat, opts: SolveOpts | None = None, x0=No
         X = x0.to(device=cl.device, dtype=torch.complex128).contiguous().clone()
         opts.use_x0 = 1
     else:
-        X = torch.empty((cl.n * NB, R), dtype=torch.complex128, device=cl.device)
+        X = torch.empty((cl.n * cl.nb, R), dtype=torch.complex128, device=cl.device)
     need = lib().chaff_solve_workspace_bytes(cl.handle, C.byref(opts), R)
     if need == 0:
         raise ChaffError(EINVAL, last_error() or "bad solve options")
@@ -385,13 +396,13 @@ def solve(cl: Cloud, Z, Pinv, k_hat, e_hat, opts: SolveOpts | None = None, x0=No
 def excitation(cl: Cloud, k_hat, e_hat):
     kh = _dev_f64(_2d(k_hat), cl.device)
     eh = _dev_f64(_2d(e_hat), cl.device)
-    U = torch.empty((cl.n * NB, kh.shape[0]), dtype=torch.complex128, device=cl.device)
+    U = torch.empty((cl.n * cl.nb, kh.shape[0]), dtype=torch.complex128, device=cl.device)
     _check(lib().chaff_excitation(cl.handle, _ptr(kh), _ptr(eh), kh.shape[0], _ptr(U), _stream()))
     return U
 
 
 def spmm(cl: Cloud, Z, X, prec: int = C64, variant: int = -1, Y=None):
-    """Y = Z X on the internal order (chaff_spmm); X is [N*7, s]."""
+    """Y = Z X on the internal order (chaff_spmm); X is [N*nb, s]."""
     if Y is None:
         Y = torch.empty_like(X)
     _check(lib().chaff_spmm(cl.handle, prec, _ptr(Z), _ptr(X), _ptr(Y), X.shape[1], variant, _stream()))
@@ -429,7 +440,7 @@ def rcs_noalloc(cl: Cloud, X, obs_dir, obs_pol, monostatic: bool):
 def autotune(cl: Cloud, Z, s: int, prec: int = C64):
     """Time every product variant for this cloud and RHS count; later variant -1 calls use the best."""
     dt = torch.complex64 if prec == C64 else torch.complex128
-    X = torch.ones((cl.n * NB, s), dtype=dt, device=cl.device)
+    X = torch.ones((cl.n * cl.nb, s), dtype=dt, device=cl.device)
     Y = torch.empty_like(X)
     best = C.c_int32(-1)
     ms = C.c_double(0.0)
@@ -444,6 +455,18 @@ def tune_report() -> list:
     buf = C.create_string_buffer(n)
     lib().chaff_tune_report(buf, n)
     return json.loads(buf.value.decode())
+
+
+def tune_save(path: str):
+    """Write the product-variant tuning table to a JSON file (chaff_tune_save)."""
+    _check(lib().chaff_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str) -> int:
+    """Merge a tuning table written by tune_save into this process's table (chaff_tune_load)."""
+    n = C.c_int32(0)
+    _check(lib().chaff_tune_load(os.fsencode(path), C.byref(n)))
+    return int(n.value)
 
 
 def destroy(cl: Cloud):

@@ -20,7 +20,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchaff.so")
-SOURCES = ["abi.cpp", "prof.cpp", "neighbors.hip", "fill.hip", "krylov.hip", "farfield.hip", "mlp.hip", "precond.hip"]
+SOURCES = ["abi.cpp", "prof.cpp", "tune.cpp", "neighbors.hip", "fill.hip", "krylov7.hip", "krylov19.hip", "farfield.hip",
+           "mlp.hip", "precond.hip"]
 ARCH = "gfx950"
 
 

@@ -7,6 +7,10 @@
 #include <new>
 
 #include "common.hpp"
+#include "tune.hpp"
+
+#include <fstream>
+#include <sstream>
 
 namespace chaff {
 
@@ -66,21 +70,25 @@ chaff_status build_cloud(const chaff_params* p, const int64_t* cloud_off, const 
                          const double* tangent, const double* length, const double* radius, void* ws,
                          size_t ws_bytes, int64_t* nnzb_out, hipStream_t st, Cloud** out);
 chaff_status fill_Z(Cloud* c, chaff_prec prec, void* Z, void* Pinv, hipStream_t st);
-size_t solve_workspace_bytes(const Cloud* c, const chaff_solve_opts* o, int64_t s);
-chaff_status solve(Cloud* c, const chaff_solve_opts* o, const void* Z, const void* Pinv, const double* k_hat,
-                   const double* e_hat, int64_t s, void* X, void* ws, size_t ws_bytes, chaff_solve_stats* st_out,
-                   double* rel_res, hipStream_t st);
-chaff_status excitation(Cloud* c, const double* k_hat, const double* e_hat, int64_t s, void* U, hipStream_t st);
-chaff_status spmm_public(Cloud* c, chaff_prec prec, const void* Z, const void* X, void* Y, int64_t s, int variant,
-                         hipStream_t st);
+// Krylov solvers, products and excitation, one instantiation per rooftop count
+#define CHAFF_KRYLOV_DECLS                                                                                          \
+    size_t solve_workspace_bytes(const Cloud* c, const chaff_solve_opts* o, int64_t s);                             \
+    chaff_status solve(Cloud* c, const chaff_solve_opts* o, const void* Z, const void* Pinv, const double* k_hat,   \
+                       const double* e_hat, int64_t s, void* X, void* ws, size_t ws_bytes,                          \
+                       chaff_solve_stats* st_out, double* rel_res, hipStream_t st);                                 \
+    chaff_status excitation(Cloud* c, const double* k_hat, const double* e_hat, int64_t s, void* U, hipStream_t st); \
+    chaff_status spmm_public(Cloud* c, chaff_prec prec, const void* Z, const void* X, void* Y, int64_t s,           \
+                             int variant, hipStream_t st);                                                          \
+    chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y, int64_t s, int32_t* best,     \
+                          double* best_ms, hipStream_t st);
+namespace kr7 { CHAFF_KRYLOV_DECLS }
+namespace kr19 { CHAFF_KRYLOV_DECLS }
+#undef CHAFF_KRYLOV_DECLS
 size_t rcs_workspace_bytes(const Cloud* c, int64_t R, int64_t M, int32_t mono);
 chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const double* pol, int64_t M, int32_t mono,
                  double* sigma, void* ws, size_t ws_bytes, hipStream_t st);
 chaff_status rcs_noalloc(Cloud* c, const void* X, int64_t R, const double* dir, const double* pol, int64_t M,
                          int32_t mono, double* sigma, hipStream_t st);
-chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y, int64_t s, int32_t* best,
-                      double* best_ms, hipStream_t st);
-int32_t tune_report(char* buf, int32_t len);
 size_t mlp_workspace_bytes(int64_t rows, int32_t train);
 chaff_status mlp_forward(const float* theta, const uint16_t* feat, int64_t M, float* Y, void* ws, size_t ws_bytes,
                          hipStream_t st);
@@ -130,7 +138,8 @@ static chaff_status check_params(const chaff_params* p, const int64_t* cloud_off
     if (p->n_wires < 1 || p->n_wires > (int64_t)INT32_MAX / 8)
         return fail(CHAFF_EINVAL, "n_wires must be in [1, 2^28)");
     if (p->n_clouds < 1 || p->n_clouds > 65535) return fail(CHAFF_EINVAL, "n_clouds must be in [1, 65535]");
-    if (p->n_seg != NSEG) return fail(CHAFF_EINVAL, "n_seg must be 8 (7 unknowns per wire)");
+    if (p->n_seg != NSEG && p->n_seg != NSEG_PAPER)
+        return fail(CHAFF_EINVAL, "n_seg must be 8 (7 unknowns per wire) or 20 (19 unknowns per wire)");
     if (!(p->wavelength > 0) || !std::isfinite(p->wavelength)) return fail(CHAFF_EINVAL, "wavelength must be > 0");
     if (!(p->d_c >= 0)) return fail(CHAFF_EINVAL, "d_c must be >= 0 (INFINITY for the dense matrix)");
     if (p->quad_mutual < 1 || p->quad_mutual > MAXQ) return fail(CHAFF_EINVAL, "quad_mutual must be in [1, 8]");
@@ -152,6 +161,7 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 static chaff_status check_mlp_cloud(chaff_cloud h, const double* k_hat, const double* e_hat, int64_t n_rhs) {
     if (!h || !k_hat || !e_hat) return fail(CHAFF_EINVAL, "NULL argument");
     if (n_rhs < 1) return fail(CHAFF_EINVAL, "n_rhs must be >= 1");
+    if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the learned guess needs wires of 8 segments");
     if (!(h->c.d_c > 0) || !std::isfinite(h->c.d_c))
         return fail(CHAFF_EINVAL, "the learned guess needs a finite d_c > 0");
     if (h->c.n > INT64_MAX / n_rhs / CHAFF_MLP_NFEAT) return fail(CHAFF_EINVAL, "n_wires * n_rhs too large");
@@ -299,7 +309,7 @@ chaff_status chaff_get_info(chaff_cloud h, chaff_cloud_info* info) {
     info->nnzb = c.nnzb;
     info->n_pairs = c.n_pairs;
     info->n_clouds = c.n_clouds;
-    info->n_seg = NSEG;
+    info->n_seg = c.nseg;
     info->wavelength = c.wavelength;
     info->d_c = c.d_c;
     info->row_ptr = c.row_ptr;
@@ -340,7 +350,8 @@ static chaff_status check_opts(const chaff_solve_opts* o) {
 
 size_t chaff_solve_workspace_bytes(chaff_cloud h, const chaff_solve_opts* o, int64_t n_rhs) {
     if (!h || !o || n_rhs < 1 || check_opts(o) != CHAFF_OK) return 0;
-    return solve_workspace_bytes(&h->c, o, n_rhs);
+    return h->c.nseg == NSEG ? kr7::solve_workspace_bytes(&h->c, o, n_rhs)
+                             : kr19::solve_workspace_bytes(&h->c, o, n_rhs);
 }
 
 chaff_status chaff_solve(chaff_cloud h, const chaff_solve_opts* o, const void* Z, const void* Pinv,
@@ -355,16 +366,20 @@ chaff_status chaff_solve(chaff_cloud h, const chaff_solve_opts* o, const void* Z
         return fail(CHAFF_EINVAL, "the cluster preconditioner buffer must be 256-byte aligned");
     if (!k_hat || !e_hat || !X || !ws) return fail(CHAFF_EINVAL, "NULL k_hat/e_hat/X/ws");
     if (n_rhs < 1 || n_rhs > 65535) return fail(CHAFF_EINVAL, "n_rhs must be in [1, 65535]");
-    size_t need = solve_workspace_bytes(&h->c, o, n_rhs);
+    if (h->c.nseg != NSEG && o->precond == CHAFF_PRECOND_CLUSTER)
+        return fail(CHAFF_EINVAL, "the cluster preconditioner needs wires of 8 segments");
+    const bool k7 = h->c.nseg == NSEG;
+    size_t need = k7 ? kr7::solve_workspace_bytes(&h->c, o, n_rhs) : kr19::solve_workspace_bytes(&h->c, o, n_rhs);
     if (ws_bytes < need) return fail(CHAFF_EWORKSPACE, "solve workspace too small: need " + std::to_string(need));
-    return solve(&h->c, o, Z, Pinv, k_hat, e_hat, n_rhs, X, ws, ws_bytes, st, rel_res, (hipStream_t)stream);
+    if (k7) return kr7::solve(&h->c, o, Z, Pinv, k_hat, e_hat, n_rhs, X, ws, ws_bytes, st, rel_res, (hipStream_t)stream);
+    return kr19::solve(&h->c, o, Z, Pinv, k_hat, e_hat, n_rhs, X, ws, ws_bytes, st, rel_res, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
 
-int64_t chaff_cluster_count(chaff_cloud h) { return h ? cluster_count(&h->c) : -1; }
+int64_t chaff_cluster_count(chaff_cloud h) { return h && h->c.nseg == NSEG ? cluster_count(&h->c) : -1; }
 
 size_t chaff_cluster_precond_bytes(chaff_cloud h, chaff_prec prec) {
-    if (!h || (prec != CHAFF_C64 && prec != CHAFF_C128)) return 0;
+    if (!h || h->c.nseg != NSEG || (prec != CHAFF_C64 && prec != CHAFF_C128)) return 0;
     return cluster_buffer_bytes(&h->c, prec);
 }
 
@@ -373,6 +388,7 @@ chaff_status chaff_cluster_precond(chaff_cloud h, chaff_prec prec, const void* Z
     if (!h || !Z || !M) return fail(CHAFF_EINVAL, "NULL argument");
     if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
     if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
+    if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the cluster preconditioner needs wires of 8 segments");
     return cluster_precond(&h->c, prec, Z, M, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
@@ -384,6 +400,7 @@ chaff_status chaff_cluster_apply(chaff_cloud h, chaff_prec prec, const void* M, 
     if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
     if (s < 1 || s > 65535) return fail(CHAFF_EINVAL, "s must be in [1, 65535]");
     if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
+    if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the cluster preconditioner needs wires of 8 segments");
     return cluster_apply_public(&h->c, prec, M, X, Y, s, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
@@ -393,7 +410,8 @@ chaff_status chaff_excitation(chaff_cloud h, const double* k_hat, const double* 
     CHAFF_GUARD_BEGIN
     if (!h || !k_hat || !e_hat || !U) return fail(CHAFF_EINVAL, "NULL argument");
     if (n_rhs < 1) return fail(CHAFF_EINVAL, "n_rhs must be >= 1");
-    return excitation(&h->c, k_hat, e_hat, n_rhs, U, (hipStream_t)stream);
+    if (h->c.nseg == NSEG) return kr7::excitation(&h->c, k_hat, e_hat, n_rhs, U, (hipStream_t)stream);
+    return kr19::excitation(&h->c, k_hat, e_hat, n_rhs, U, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
 
@@ -404,7 +422,8 @@ chaff_status chaff_spmm(chaff_cloud h, chaff_prec prec, const void* Z, const voi
     if (s < 1 || s > 65535) return fail(CHAFF_EINVAL, "s must be in [1, 65535]");
     if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "bad prec");
     if (variant < -1 || variant > 7) return fail(CHAFF_EINVAL, "variant must be in [-1, 7]");
-    return spmm_public(&h->c, prec, Z, X, Y, s, variant, (hipStream_t)stream);
+    if (h->c.nseg == NSEG) return kr7::spmm_public(&h->c, prec, Z, X, Y, s, variant, (hipStream_t)stream);
+    return kr19::spmm_public(&h->c, prec, Z, X, Y, s, variant, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
 
@@ -445,11 +464,44 @@ chaff_status chaff_autotune(chaff_cloud h, chaff_prec prec, const void* Z, void*
     if (!h || !Z || !X || !Y) return fail(CHAFF_EINVAL, "NULL argument");
     if (s < 1 || s > 65535) return fail(CHAFF_EINVAL, "s must be in [1, 65535]");
     if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "bad prec");
-    return autotune(&h->c, prec, Z, X, Y, s, best_variant, best_ms, (hipStream_t)stream);
+    if (h->c.nseg == NSEG) return kr7::autotune(&h->c, prec, Z, X, Y, s, best_variant, best_ms, (hipStream_t)stream);
+    return kr19::autotune(&h->c, prec, Z, X, Y, s, best_variant, best_ms, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
 
-int32_t chaff_tune_report(char* buf, int32_t len) { return tune_report(buf, len); }
+int32_t chaff_tune_report(char* buf, int32_t len) {
+    const std::string out = tune_json();
+    if (buf && len > 0) {
+        std::strncpy(buf, out.c_str(), (size_t)len - 1);
+        buf[len - 1] = 0;
+    }
+    return (int32_t)out.size() + 1;
+}
+
+chaff_status chaff_tune_save(const char* path) {
+    CHAFF_GUARD_BEGIN
+    if (!path) return fail(CHAFF_EINVAL, "path is NULL");
+    std::ofstream f(path, std::ios::out | std::ios::trunc);
+    if (!f) return fail(CHAFF_EINVAL, std::string("cannot write ") + path);
+    f << tune_json() << "\n";
+    if (!f) return fail(CHAFF_EINVAL, std::string("write failed: ") + path);
+    return CHAFF_OK;
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_tune_load(const char* path, int32_t* n_entries) {
+    CHAFF_GUARD_BEGIN
+    if (!path) return fail(CHAFF_EINVAL, "path is NULL");
+    std::ifstream f(path);
+    if (!f) return fail(CHAFF_EINVAL, std::string("cannot read ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const int n = tune_merge_json(ss.str());
+    if (n < 0) return fail(CHAFF_EINVAL, std::string("not a tuning table: ") + path);
+    if (n_entries) *n_entries = n;
+    return CHAFF_OK;
+    CHAFF_GUARD_END
+}
 
 void chaff_destroy(chaff_cloud h) { delete h; }
 

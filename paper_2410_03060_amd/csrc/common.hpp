@@ -13,9 +13,13 @@
 
 namespace chaff {
 
+// Segments per wire of the 8-segment kernels (neighbour features of the learned
+// guess, cluster preconditioner); the fill, products, solvers and far field
+// also run the paper's 20 segments (Cloud::nseg).
 constexpr int NSEG = 8;      // segments per wire
 constexpr int NB = 7;        // rooftop unknowns per wire
 constexpr int NB2 = NB * NB; // complex entries per block
+constexpr int NSEG_PAPER = 20;  // the discretisation of the paper's own runs (19 unknowns per wire)
 constexpr int MAXQ = 8;      // largest Gauss-Legendre order supported
 
 // ------------------------------------------------------------------ complex
@@ -101,6 +105,7 @@ struct Cloud {
     int32_t n_clouds = 1;
     double wavelength = 0, d_c = 0;
     int32_t q_mutual = 4, q_self = 8;
+    int32_t nseg = NSEG;                 // segments per wire: 8 or 20
     std::vector<int64_t> cloud_off;      // host copy
     // device arrays (inside the caller's build workspace)
     Wire* wires = nullptr;               // [N] internal order

@@ -20,19 +20,22 @@
 namespace chaff {
 
 constexpr double PI_F = 3.14159265358979323846;
-constexpr int FF_CHUNK = 256;   // wires per chunk
+// wires per chunk: 256 for 7 unknowns per wire, 64 for 19 (the bistatic
+// kernel stages a chunk's currents in LDS)
+constexpr int ff_chunk(int nb) { return nb <= 7 ? 256 : 64; }
 
 __device__ __forceinline__ double sinc_ff(double x) {
     return fabs(x) < 1e-4 ? 1.0 - x * x / 6.0 : sin(x) / x;
 }
 
 // one wire's contribution for direction (rx,ry,rz), polarisation (ex,ey,ez)
+template <int NBW>
 __device__ __forceinline__ c128 wire_term(const Wire& w, const c128* __restrict__ x, int64_t xstride, double k,
                                           double rx, double ry, double rz, double ex, double ey, double ez) {
     const double tp = w.tx * ex + w.ty * ey + w.tz * ez;
     const double b = k * (rx * w.tx + ry * w.ty + rz * w.tz);
     const double ph0 = k * (rx * w.cx + ry * w.cy + rz * w.cz);
-    const double D = w.len / NSEG;
+    const double D = w.len / (NBW + 1);
     const double sc = sinc_ff(0.5 * b * D);
     const double env = tp * D * sc * sc;
     // exp(j b s_q), s_q = -L/2 + (q+1) D, by recurrence in q
@@ -42,7 +45,7 @@ __device__ __forceinline__ c128 wire_term(const Wire& w, const c128* __restrict_
     c128 ph = {c1, s1};
     const c128 step = {cd, sd};
     c128 acc = {0, 0};
-    for (int q = 0; q < NB; ++q) {
+    for (int q = 0; q < NBW; ++q) {
         cfma(acc, ph, x[q * xstride]);
         ph = cmul(ph, step);
     }
@@ -57,7 +60,7 @@ __device__ __forceinline__ c128 wire_term(const Wire& w, const c128* __restrict_
 // the four waves combined in wave order through LDS: a fixed summation order
 // (bit-reproducible, no atomics).  RT is the smallest power of two >= R
 // (at most 64), so few RHS columns do not leave lanes idle.
-template <int RT>
+template <int RT, int NBW>
 __global__ __launch_bounds__(256) void k_mono(const Wire* __restrict__ wires, const int32_t* __restrict__ perm,
                                               const int64_t* __restrict__ chunk_w0, int n_chunks, int64_t R,
                                               const c128* __restrict__ X, const double* __restrict__ dir,
@@ -75,8 +78,8 @@ __global__ __launch_bounds__(256) void k_mono(const Wire* __restrict__ wires, co
         const double ex = pol[3 * r], ey = pol[3 * r + 1], ez = pol[3 * r + 2];
         for (int64_t i = w0 + wv * G + g; i < w1; i += 4 * G) {
             const Wire wr = wires[i];
-            const c128* xp = X + (int64_t)perm[i] * NB * R + r;
-            acc = cadd(acc, wire_term(wr, xp, R, k, rx, ry, rz, ex, ey, ez));
+            const c128* xp = X + (int64_t)perm[i] * NBW * R + r;
+            acc = cadd(acc, wire_term<NBW>(wr, xp, R, k, rx, ry, rz, ex, ey, ez));
         }
     }
 #pragma unroll
@@ -93,6 +96,7 @@ __global__ __launch_bounds__(256) void k_mono(const Wire* __restrict__ wires, co
     }
 }
 
+template <int NBW>
 static void launch_mono(dim3 grid_x, int64_t R, hipStream_t st, const Wire* wires, const int32_t* perm,
                         const int64_t* w0, int nch, const c128* X, const double* dir, const double* pol, double k,
                         c128* part) {
@@ -100,19 +104,21 @@ static void launch_mono(dim3 grid_x, int64_t R, hipStream_t st, const Wire* wire
     const dim3 grid(grid_x.x, (unsigned)((R + rt - 1) / rt));
     switch (rt) {
 #define CHAFF_MONO(T) \
-    case T: hipLaunchKernelGGL(k_mono<T>, grid, dim3(256), 0, st, wires, perm, w0, nch, R, X, dir, pol, k, part); break;
+    case T: hipLaunchKernelGGL((k_mono<T, NBW>), grid, dim3(256), 0, st, wires, perm, w0, nch, R, X, dir, pol, k, part); break;
         CHAFF_MONO(1) CHAFF_MONO(2) CHAFF_MONO(4) CHAFF_MONO(8) CHAFF_MONO(16) CHAFF_MONO(32) CHAFF_MONO(64)
 #undef CHAFF_MONO
     }
 }
 
 // partial[chunk][r][m] for every (rhs r, direction m)
+template <int NBW>
 __global__ __launch_bounds__(256) void k_bistatic(const Wire* __restrict__ wires, const int32_t* __restrict__ perm,
                                                   const int64_t* __restrict__ chunk_w0, int64_t R, int64_t M,
                                                   const c128* __restrict__ X, const double* __restrict__ dir,
                                                   const double* __restrict__ pol, double k, c128* __restrict__ part) {
-    __shared__ Wire sw[FF_CHUNK];
-    __shared__ c128 sx[FF_CHUNK * NB];
+    constexpr int CH = ff_chunk(NBW);
+    __shared__ Wire sw[CH];
+    __shared__ c128 sx[CH * NBW];
     const int ch = blockIdx.y;
     const int64_t r = blockIdx.z;
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -121,14 +127,14 @@ __global__ __launch_bounds__(256) void k_bistatic(const Wire* __restrict__ wires
     for (int t = threadIdx.x; t < nw; t += blockDim.x) {
         sw[t] = wires[w0 + t];
         const int64_t p = perm[w0 + t];
-        for (int q = 0; q < NB; ++q) sx[t * NB + q] = X[(p * NB + q) * R + r];
+        for (int q = 0; q < NBW; ++q) sx[t * NBW + q] = X[(p * NBW + q) * R + r];
     }
     __syncthreads();
     if (m >= M) return;
     const double rx = dir[3 * m], ry = dir[3 * m + 1], rz = dir[3 * m + 2];
     const double ex = pol[3 * m], ey = pol[3 * m + 1], ez = pol[3 * m + 2];
     c128 acc = {0, 0};
-    for (int t = 0; t < nw; ++t) acc = cadd(acc, wire_term(sw[t], &sx[t * NB], 1, k, rx, ry, rz, ex, ey, ez));
+    for (int t = 0; t < nw; ++t) acc = cadd(acc, wire_term<NBW>(sw[t], &sx[t * NBW], 1, k, rx, ry, rz, ex, ey, ez));
     part[((int64_t)ch * R + r) * M + m] = acc;
 }
 
@@ -149,7 +155,7 @@ static void ff_chunks(const Cloud* c, std::vector<int64_t>& w0, std::vector<int3
     coff.assign(c->n_clouds + 1, 0);
     for (int k = 0; k < c->n_clouds; ++k) {
         coff[k] = (int32_t)w0.size();
-        for (int64_t a = c->cloud_off[k]; a < c->cloud_off[k + 1]; a += FF_CHUNK) w0.push_back(a);
+        for (int64_t a = c->cloud_off[k]; a < c->cloud_off[k + 1]; a += ff_chunk(c->nseg - 1)) w0.push_back(a);
     }
     coff[c->n_clouds] = (int32_t)w0.size();
 }
@@ -188,14 +194,23 @@ chaff_status rcs(Cloud* c, const void* Xv, int64_t R, const double* dir, const d
     if (nch > 0) {
         // monostatic: X read once + wire records; bistatic: 55 flops per wire and direction
         ProfScope ps(mono ? "rcs_mono" : "rcs_bistatic", st,
-                     mono ? 16.0 * NB * (double)c->n * R + 64.0 * c->n : 55.0 * (double)c->n * R * M, !mono);
+                     mono ? 16.0 * (c->nseg - 1) * (double)c->n * R + 64.0 * c->n
+                          : 55.0 * (double)c->n * R * M, !mono);
         if (mono) {
-            launch_mono(dim3(nch), R, st, (const Wire*)c->wires, (const int32_t*)c->perm, (const int64_t*)d_w0, nch,
-                        X, dir, pol, k, part);
+            if (c->nseg == NSEG)
+                launch_mono<NSEG - 1>(dim3(nch), R, st, (const Wire*)c->wires, (const int32_t*)c->perm,
+                                      (const int64_t*)d_w0, nch, X, dir, pol, k, part);
+            else
+                launch_mono<NSEG_PAPER - 1>(dim3(nch), R, st, (const Wire*)c->wires, (const int32_t*)c->perm,
+                                            (const int64_t*)d_w0, nch, X, dir, pol, k, part);
         } else {
             dim3 grid((unsigned)((M + 255) / 256), nch, (unsigned)R);
-            hipLaunchKernelGGL(k_bistatic, grid, dim3(256), 0, st, (const Wire*)c->wires, (const int32_t*)c->perm,
-                               (const int64_t*)d_w0, R, M, X, dir, pol, k, part);
+            if (c->nseg == NSEG)
+                hipLaunchKernelGGL(k_bistatic<NSEG - 1>, grid, dim3(256), 0, st, (const Wire*)c->wires,
+                                   (const int32_t*)c->perm, (const int64_t*)d_w0, R, M, X, dir, pol, k, part);
+            else
+                hipLaunchKernelGGL(k_bistatic<NSEG_PAPER - 1>, grid, dim3(256), 0, st, (const Wire*)c->wires,
+                                   (const int32_t*)c->perm, (const int64_t*)d_w0, R, M, X, dir, pol, k, part);
         }
         CHAFF_LAUNCH_CHECK();
     }

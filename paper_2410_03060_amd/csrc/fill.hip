@@ -337,6 +337,248 @@ __global__ __launch_bounds__(256) void k_mutual(const Wire* __restrict__ wires,
     }
 }
 
+// ------------------------------------------------------------------ any segment count (20: the paper's own runs)
+// The same quadrature and assembly for NS segments (NS - 1 rooftops) where a
+// block no longer fits one lane per entry or per segment pair: lanes loop over
+// the work items, and the per-item results meet in LDS.
+
+// Self blocks: one wave per wire.  Items (d, k) = (segment offset, test node)
+// run in passes of 64 with k fastest, so each pass reduces over the test nodes
+// with xor shuffles inside groups of 8 lanes; T_ab(d) goes to LDS, the block
+// is assembled from it (Toeplitz, exactly symmetric) and inverted by
+// Gauss-Jordan with partial pivoting, lane c < 2 (NS - 1) owning column c of
+// the augmented [Z | I].
+constexpr int SELFW_WAVES = 2;
+template <typename R, int NS>
+__global__ __launch_bounds__(64 * SELFW_WAVES) void k_self_w(const Wire* __restrict__ wires, int64_t n,
+                                                             const int64_t* __restrict__ diag_pos,
+                                                             cplx<R>* __restrict__ Z, cplx<R>* __restrict__ Pinv,
+                                                             FillParams prm, int32_t* __restrict__ status) {
+    using C = cplx<R>;
+    constexpr int NBW = NS - 1, NBW2 = NBW * NBW;
+    static_assert(2 * NBW <= 64, "one lane per column of the augmented matrix");
+    __shared__ C Ts[SELFW_WAVES][NS][2][2];        // T_ab(d), d = 0..NS-1
+    __shared__ C Abs[SELFW_WAVES][NBW][2 * NBW];   // augmented [Z | I]
+    __shared__ Anti As[SELFW_WAVES][4];            // static antiderivatives at v = -1, 0, 1, 2
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * SELFW_WAVES + wv;
+    if (w >= n) return;   // uniform over the wave
+    auto& T = Ts[wv];
+    auto& Ab = Abs[wv];
+    const Wire wr = wires[w];
+    const double Dd = wr.len / NS;
+    const R D = (R)Dd;
+    const R a2 = (R)(wr.rad * wr.rad);
+    const R inv_lam = (R)prm.inv_lambda;
+    const int q = prm.q;
+    if (lane < 4) As[wv][lane] = anti((double)(lane - 1), wr.rad / Dd);
+    wave_sync();
+    const int kk = lane & 7;
+    for (int d0 = 0; d0 < NS; d0 += 8) {   // wave-uniform passes over 8 offsets
+        const int d = d0 + (lane >> 3);
+        C m00 = {0, 0}, m01 = {0, 0}, m10 = {0, 0}, m11 = {0, 0};
+        if (d < NS && kk < q) {
+            const R xk = (R)prm.xq[kk];
+            C s0 = {0, 0}, s1 = {0, 0};
+            for (int l = 0; l < q; ++l) {
+                const R xl = (R)prm.xq[l];
+                const R gl = (R)prm.wq[l];
+                R u = D * ((R)d + (xk - xl));
+                R r2 = u * u + a2;
+                R ir = rsq(r2);
+                R rev = r2 * ir * inv_lam;
+                R gre, gim, c, sn;
+                phase_cs(rev, c, sn);
+                if (d <= 1) {   // (exp(-jkR) - 1)/R = (-2 sin^2(kR/2) - j sin kR)/R
+                    R hs = half_sin(rev);
+                    gre = (R)-2 * hs * hs * ir;
+                } else {
+                    gre = c * ir;
+                }
+                gim = -sn * ir;
+                s0.re += gl * gre; s0.im += gl * gim;
+                s1.re += gl * xl * gre; s1.im += gl * xl * gim;
+            }
+            const R gk = (R)prm.wq[kk];
+            m00 = cscale(s0, gk);
+            m01 = cscale(s1, gk);
+            m10 = cscale(s0, gk * xk);
+            m11 = cscale(s1, gk * xk);
+        }
+        for (int o = 1; o < 8; o <<= 1) {
+            m00.re += __shfl_xor(m00.re, o); m00.im += __shfl_xor(m00.im, o);
+            m01.re += __shfl_xor(m01.re, o); m01.im += __shfl_xor(m01.im, o);
+            m10.re += __shfl_xor(m10.re, o); m10.im += __shfl_xor(m10.im, o);
+            m11.re += __shfl_xor(m11.re, o); m11.im += __shfl_xor(m11.im, o);
+        }
+        if (kk == 0 && d < NS) {
+            const R sc = (R)(Dd * Dd / (4.0 * PI));
+            C A[2][2];
+            A[0][0] = cscale(m11, sc);
+            A[0][1] = cscale(csub(m10, m11), sc);
+            A[1][0] = cscale(csub(m01, m11), sc);
+            A[1][1] = cscale(cadd(csub(csub(m00, m10), m01), m11), sc);
+            if (d <= 1) {   // v = d + 1, d, d - 1 sit at As[d + 2], As[d + 1], As[d]
+                double K[2][2];
+                static_self(As[wv][d + 2], As[wv][d + 1], As[wv][d], K);
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) A[a][b].re += (R)(Dd / (4.0 * PI) * K[a][b]);
+            }
+            C B = cadd(cadd(A[0][0], A[0][1]), cadd(A[1][0], A[1][1]));
+            const R sz = (R)(1.0 / (prm.k * prm.k * Dd * Dd));
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    R sg = (a == b) ? (R)1 : (R)-1;
+                    T[d][a][b] = csub(A[a][b], cscale(B, sg * sz));
+                }
+        }
+    }
+    wave_sync();
+    C* Zb = Z + diag_pos[w] * NBW2;
+    for (int e = lane; e < NBW2; e += 64) {
+        const int qi = e / NBW, qj = e % NBW;
+        const int qa = qi < qj ? qi : qj, qb = qi < qj ? qj : qi;   // upper triangle: exact symmetry
+        C acc = {0, 0};
+        for (int da = 0; da < 2; ++da)
+            for (int db = 0; db < 2; ++db) {
+                const int dd = (qa + da) - (qb + db);
+                acc = cadd(acc, dd >= 0 ? T[dd][da][db] : T[-dd][db][da]);
+            }
+        Zb[e] = acc;
+        Ab[qi][qj] = acc;
+        Ab[qi][NBW + qj] = (qi == qj) ? C{1, 0} : C{0, 0};
+    }
+    wave_sync();
+    if (Pinv == nullptr) return;
+    bool singular = false;
+    for (int piv = 0; piv < NBW; ++piv) {
+        int best = piv;
+        R bm = Ab[piv][piv].re * Ab[piv][piv].re + Ab[piv][piv].im * Ab[piv][piv].im;
+        for (int r = piv + 1; r < NBW; ++r) {
+            R m = Ab[r][piv].re * Ab[r][piv].re + Ab[r][piv].im * Ab[r][piv].im;
+            if (m > bm) { bm = m; best = r; }
+        }
+        if (!(bm > (R)0)) { singular = true; break; }
+        const C pv = Ab[best][piv];
+        wave_sync();
+        if (lane < 2 * NBW) {
+            C tmp = Ab[piv][lane];
+            Ab[piv][lane] = Ab[best][lane];
+            Ab[best][lane] = tmp;
+        }
+        wave_sync();
+        const R inv_m = (R)1 / bm;
+        const C ip = {pv.re * inv_m, -pv.im * inv_m};
+        C rowp = {0, 0};
+        if (lane < 2 * NBW) rowp = cmul(Ab[piv][lane], ip);
+        // every lane reads column piv of the rows (after the swap) before any lane overwrites it
+        for (int r = 0; r < NBW; ++r) {
+            const C f = Ab[r][piv];
+            wave_sync();
+            if (lane < 2 * NBW) Ab[r][lane] = (r == piv) ? rowp : csub(Ab[r][lane], cmul(f, rowp));
+            wave_sync();
+        }
+    }
+    if (singular) {
+        if (lane == 0) atomicOr(status, 1);
+        return;
+    }
+    for (int e = lane; e < NBW2; e += 64) Pinv[w * NBW2 + e] = Ab[e / NBW][NBW + e % NBW];
+}
+
+// Mutual blocks: one wave per unique pair.  Items = the NS x NS segment pairs
+// (alpha, beta), lane l taking items l, l + 64, ...; each runs the Q x Q
+// samples and leaves its four rooftop-half terms T_ab in LDS, from which the
+// lanes assemble the (NS - 1)^2 block entries (each needs the four segment
+// pairs its two rooftops overlap), stored as Z_ij and Z_ji = Z_ij^T.
+constexpr int MUTW_WAVES = 2;
+template <typename R, int Q, int NS>
+__global__ __launch_bounds__(64 * MUTW_WAVES) void k_mutual_w(const Wire* __restrict__ wires,
+                                                              const Pair* __restrict__ pairs, int64_t n_pairs,
+                                                              cplx<R>* __restrict__ Z, FillParams prm) {
+    using C = cplx<R>;
+    constexpr int NBW = NS - 1, NBW2 = NBW * NBW;
+    __shared__ C Tsh[MUTW_WAVES][NS * NS][4];   // T_pp, T_pm, T_mp, T_mm of segment pair (alpha, beta)
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t e = (int64_t)blockIdx.x * MUTW_WAVES + wv;
+    if (e >= n_pairs) return;
+    auto& T = Tsh[wv];
+    const Pair pr = pairs[e];
+    const Wire wi = wires[pr.i];
+    const Wire wj = wires[pr.j];
+    const double Di = wi.len / NS, Dj = wj.len / NS;
+    const double sep[3] = {wj.cx - wi.cx, wj.cy - wi.cy, wj.cz - wi.cz};
+    const R uix = (R)(Di * wi.tx), uiy = (R)(Di * wi.ty), uiz = (R)(Di * wi.tz);
+    const R ujx = (R)(Dj * wj.tx), ujy = (R)(Dj * wj.ty), ujz = (R)(Dj * wj.tz);
+    const R a2 = (R)(0.5 * (wi.rad * wi.rad + wj.rad * wj.rad));
+    const R inv_lam = (R)prm.inv_lambda;
+    const R sc = (R)(Di * Dj / (4.0 * PI));
+    const R tt = (R)(wi.tx * wj.tx + wi.ty * wj.ty + wi.tz * wj.tz);
+    const R sz = (R)(1.0 / (prm.k * prm.k * Di * Dj));
+    R xq[Q], wq[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        xq[k] = (R)prm.xq[k];
+        wq[k] = (R)prm.wq[k];
+    }
+    for (int it = lane; it < NS * NS; it += 64) {
+        const int al = it / NS, be = it % NS;
+        const double s0i = -0.5 * wi.len + al * Di;
+        const double s0j = -0.5 * wj.len + be * Dj;
+        const R bx = (R)(s0i * wi.tx - sep[0] - s0j * wj.tx);
+        const R by = (R)(s0i * wi.ty - sep[1] - s0j * wj.ty);
+        const R bz = (R)(s0i * wi.tz - sep[2] - s0j * wj.tz);
+        C m00 = {0, 0}, m01 = {0, 0}, m10 = {0, 0}, m11 = {0, 0};
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const R ox = xq[k] * uix, oy = xq[k] * uiy, oz = xq[k] * uiz;
+            C s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+            for (int l = 0; l < Q; ++l) {
+                R dx = (bx - xq[l] * ujx) + ox, dy = (by - xq[l] * ujy) + oy, dz = (bz - xq[l] * ujz) + oz;
+                R r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, a2)));
+                R ir = rsq(r2);
+                R rev = r2 * ir * inv_lam;
+                R c, s;
+                phase_cs(rev, c, s);
+                R gre = c * ir, gim = -s * ir;
+                s0.re = fma(wq[l], gre, s0.re);
+                s0.im = fma(wq[l], gim, s0.im);
+                R wl = wq[l] * xq[l];
+                s1.re = fma(wl, gre, s1.re);
+                s1.im = fma(wl, gim, s1.im);
+            }
+            const R wk = wq[k], wkx = wq[k] * xq[k];
+            m00.re = fma(wk, s0.re, m00.re); m00.im = fma(wk, s0.im, m00.im);
+            m01.re = fma(wk, s1.re, m01.re); m01.im = fma(wk, s1.im, m01.im);
+            m10.re = fma(wkx, s0.re, m10.re); m10.im = fma(wkx, s0.im, m10.im);
+            m11.re = fma(wkx, s1.re, m11.re); m11.im = fma(wkx, s1.im, m11.im);
+        }
+        C App = cscale(m11, sc);
+        C Apm = cscale(csub(m10, m11), sc);
+        C Amp = cscale(csub(m01, m11), sc);
+        C Amm = cscale(cadd(csub(csub(m00, m10), m01), m11), sc);
+        C Bs = cscale(cadd(cadd(App, Apm), cadd(Amp, Amm)), sz);
+        T[it][0] = csub(cscale(App, tt), Bs);
+        T[it][1] = cadd(cscale(Apm, tt), Bs);
+        T[it][2] = cadd(cscale(Amp, tt), Bs);
+        T[it][3] = csub(cscale(Amm, tt), Bs);
+    }
+    wave_sync();
+    for (int o = lane; o < NBW2; o += 64) {
+        const int qi = o / NBW, qj = o % NBW;
+        const int l00 = qi * NS + qj;
+        C z = T[l00][0];
+        z = cadd(z, T[l00 + 1][1]);
+        z = cadd(z, T[l00 + NS][2]);
+        z = cadd(z, T[l00 + NS + 1][3]);
+        Z[pr.pos_ij * NBW2 + qi * NBW + qj] = z;
+        Z[pr.pos_ji * NBW2 + qj * NBW + qi] = z;
+    }
+}
+
 // ------------------------------------------------------------------ host
 
 __global__ void k_fill_status(int32_t* __restrict__ status) {
@@ -358,7 +600,32 @@ static chaff_status fill_impl(Cloud* c, void* Zv, void* Pinv, hipStream_t st) {
 
     hipLaunchKernelGGL(k_fill_status, dim3(1), dim3(64), 0, st, c->d_status);
     CHAFF_LAUNCH_CHECK();
-    if (c->n_pairs > 0) {
+    if (c->nseg == NSEG_PAPER) {   // 20 segments, 19 x 19 blocks
+        constexpr int NS = NSEG_PAPER;
+        if (c->n_pairs > 0) {
+            dim3 grid((unsigned)((c->n_pairs + MUTW_WAVES - 1) / MUTW_WAVES));
+            ProfScope ps("fill_mutual", st, 24.0 * NS * NS * c->q_mutual * c->q_mutual * (double)c->n_pairs, true);
+            switch (c->q_mutual) {
+#define CHAFF_QW(QQ)                                                                                          \
+    case QQ:                                                                                                  \
+        hipLaunchKernelGGL((k_mutual_w<R, QQ, NS>), grid, dim3(64 * MUTW_WAVES), 0, st, (const Wire*)c->wires, \
+                           (const Pair*)c->pairs, c->n_pairs, Z, pm);                                         \
+        break;
+                CHAFF_QW(1) CHAFF_QW(2) CHAFF_QW(3) CHAFF_QW(4) CHAFF_QW(5) CHAFF_QW(6) CHAFF_QW(7) CHAFF_QW(8)
+#undef CHAFF_QW
+                default:
+                    return fail(CHAFF_EINVAL, "quad_mutual out of range");
+            }
+            CHAFF_LAUNCH_CHECK();
+        }
+        {
+            ProfScope pss("fill_self", st, 24.0 * NS * c->q_self * c->q_self * (double)c->n, true);
+            hipLaunchKernelGGL((k_self_w<R, NS>), dim3((unsigned)((c->n + SELFW_WAVES - 1) / SELFW_WAVES)),
+                               dim3(64 * SELFW_WAVES), 0, st, (const Wire*)c->wires, c->n,
+                               (const int64_t*)c->diag_pos, Z, static_cast<C*>(Pinv), ps, c->d_status);
+        }
+        CHAFF_LAUNCH_CHECK();
+    } else if (c->n_pairs > 0) {
         const int wpb = 4;
         dim3 grid((unsigned)((c->n_pairs + wpb - 1) / wpb));
         // 24 flops per Green sample, (8 Q)^2 samples per pair
@@ -376,7 +643,7 @@ static chaff_status fill_impl(Cloud* c, void* Zv, void* Pinv, hipStream_t st) {
         }
         CHAFF_LAUNCH_CHECK();
     }
-    {
+    if (c->nseg == NSEG) {
         ProfScope pss("fill_self", st, 24.0 * 8.0 * c->q_self * c->q_self * (double)c->n, true);
         hipLaunchKernelGGL((k_self<R>), dim3((unsigned)((c->n + SELF_WAVES - 1) / SELF_WAVES)), dim3(64 * SELF_WAVES), 0,
                            st, (const Wire*)c->wires, c->n,

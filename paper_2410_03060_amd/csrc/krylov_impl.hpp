@@ -1,9 +1,15 @@
-// Block-sparse products and the multi-RHS restarted GMRES with FP64
+// Block-sparse products and the multi-RHS Krylov solvers with FP64
 // iterative refinement (Sec. II-B: iterative solve of the S-NFC system with a
 // block-diagonal preconditioner; matvec cost O(b_mean N)).
 //
-// Layout: every vector block is row-major [N*7][s] in the internal (Morton)
-// wire order, so the 7 x s slab of one wire is contiguous and a column tile
+// Included by krylov7.hip and krylov19.hip, once per rooftop count per wire:
+// CHAFF_KNB unknowns per wire (7 for 8 segments, 19 for the 20 segments of
+// the paper's own discretisation), inside namespace chaff::CHAFF_KNS.  The
+// matrix-core forms of the product and the cluster preconditioner exist for
+// 7 unknowns per wire only.
+//
+// Layout: every vector block is row-major [N*NB][s] in the internal (Morton)
+// wire order, so the NB x s slab of one wire is contiguous and a column tile
 // of s right-hand sides is read with unit stride.  Systems are independent
 // per (cloud, RHS); all of them advance in lockstep so that each sparse
 // product reads Z once for every right-hand side, while dot products are
@@ -11,6 +17,7 @@
 #include "common.hpp"
 #include "precond.hpp"
 #include "prof.hpp"
+#include "tune.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -19,7 +26,16 @@
 #include <cstdio>
 #include <cstdlib>
 
+#ifndef CHAFF_KNB
+#error "define CHAFF_KNB (unknowns per wire) and CHAFF_KNS (namespace) before including krylov_impl.hpp"
+#endif
+
 namespace chaff {
+namespace CHAFF_KNS {
+
+constexpr int NB = CHAFF_KNB;         // rooftop unknowns per wire
+constexpr int NSEG = NB + 1;          // segments per wire
+constexpr int NB2 = NB * NB;          // complex entries per block
 
 constexpr double PI_K = 3.14159265358979323846;
 constexpr int NXCD = 8;   // XCDs per MI355X; workgroup ids are dealt to them round-robin
@@ -342,34 +358,6 @@ __global__ __launch_bounds__(256) void k_spmm_xcd(const int64_t* __restrict__ ro
     }
 }
 
-// ------------------------------------------------------------------ autotuning table
-// Process-wide record of the fastest block-sparse product variant per
-// (wires, stored blocks, RHS count, precision), filled by chaff_autotune and
-// consulted whenever a caller passes variant -1.
-struct TuneEntry {
-    int64_t n, nnzb, s;
-    int prec;
-    int best;
-    double ms[8];
-};
-static std::mutex g_tune_mu;
-static std::vector<TuneEntry> g_tune;
-
-static int tuned_variant(int64_t n, int64_t nnzb, int64_t s, int prec) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (const TuneEntry& e : g_tune)
-        if (e.n == n && e.nnzb == nnzb && e.s == s && e.prec == prec) return e.best;
-    return -1;
-}
-static void record_tuning(const TuneEntry& t) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (TuneEntry& e : g_tune)
-        if (e.n == t.n && e.nnzb == t.nnzb && e.s == t.s && e.prec == t.prec) {
-            e = t;
-            return;
-        }
-    g_tune.push_back(t);
-}
 // default when nothing was tuned: one row per lane for a single RHS, else the
 // XCD-aware tile order
 static int default_variant(int64_t s) { return s == 1 ? 0 : 3; }
@@ -398,7 +386,7 @@ static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, 
     ProfScope ps(tag, st, zb + vb, false);
     if (variant < 0) {
         const int t = (!DIAG && MODE == 0 && std::is_same<CZ, CX>::value && std::is_same<CX, CY>::value)
-                          ? tuned_variant(n, nnzb, s, std::is_same<CZ, c64>::value ? CHAFF_C64 : CHAFF_C128)
+                          ? tuned_variant(NB, n, nnzb, s, std::is_same<CZ, c64>::value ? CHAFF_C64 : CHAFF_C128)
                           : -1;
         variant = t >= 0 ? t : (DIAG ? (s == 1 ? 0 : 1) : default_variant(s));
     }
@@ -409,7 +397,10 @@ static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, 
         CHAFF_LAUNCH_CHECK();
         return CHAFF_OK;
     }
-    if ((variant == 6 || variant == 7) && !DIAG) {
+    if constexpr (NB2 > 64) {   // the wave-per-row variants stage a block with one load per lane
+        if (variant == 6 || variant == 7) variant = 3;
+    }
+    if constexpr (NB2 <= 64) if ((variant == 6 || variant == 7) && !DIAG) {
         // S columns per tile, several block rows per wave below 32 columns; 7 = XCD-aware order
         const int sw = spmm_tile_width(s) < 4 ? 4 : spmm_tile_width(s);
         // block rows per wave (several independent gather chains per wave at small widths)
@@ -937,13 +928,14 @@ __global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 constexpr int COCG_TILE_ROWS = RB / 64;
 template <typename CZ, typename C, int S>
-__global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(sizeof(C) == sizeof(c64) ? 6 : 1)))
+__global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(sizeof(C) == sizeof(c64) && NB == 7 ? 6 : 1)))
 void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles, int xcd_order,
                  const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx, const CZ* __restrict__ Z,
                  const C* __restrict__ P, C* __restrict__ Q, int64_t s, c128* __restrict__ tpart) {
     using R = typename real_of<C>::type;
     constexpr int G = 64 / S;
     constexpr int KK = (NB + G - 1) / G;
+    constexpr int ZPL = (NB2 + 63) / 64;
     __shared__ CZ zs[COCG_TILE_ROWS][2][NB2];
     __shared__ c128 red[RB];
     const int64_t id = blockIdx.x;
@@ -975,7 +967,7 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
     // the block are two 4-row tiles, row 7 zero; four MFMAs per depth step for
     // the real form of the complex product, in the order of cfma, so the
     // result rounds exactly as the vector form's)
-    constexpr bool PMFMA = sizeof(C) == sizeof(c64) && sizeof(CZ) == sizeof(c64);
+    constexpr bool PMFMA = sizeof(C) == sizeof(c64) && sizeof(CZ) == sizeof(c64) && NB == 7;
     static_assert(!PMFMA || S % 4 == 0, "an MFMA block of 4 lanes stays inside one depth group");
     if (i < tl.w1) {   // wave-uniform
         cplx<R> acc[NB];
@@ -984,11 +976,21 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
         f32x4_t mr[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         f32x4_t mi[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
-        CZ zn = (lane < NB2 && e0 < e1) ? Z[e0 * NB2 + lane] : CZ{0, 0};
+        // lane l stages entries l, l + 64, ... of each block (ZPL per lane)
+        CZ zn[ZPL];
+#pragma unroll
+        for (int u = 0; u < ZPL; ++u)
+            zn[u] = (lane + 64 * u < NB2 && e0 < e1) ? Z[e0 * NB2 + lane + 64 * u] : CZ{0, 0};
         for (int64_t e = e0; e < e1; ++e) {
             const int buf = (int)((e - e0) & 1);
-            if (lane < NB2) zs[w][buf][lane] = zn;
-            if (e + 1 < e1 && lane < NB2) zn = Z[(e + 1) * NB2 + lane];
+#pragma unroll
+            for (int u = 0; u < ZPL; ++u)
+                if (lane + 64 * u < NB2) zs[w][buf][lane + 64 * u] = zn[u];
+            if (e + 1 < e1) {
+#pragma unroll
+                for (int u = 0; u < ZPL; ++u)
+                    if (lane + 64 * u < NB2) zn[u] = Z[(e + 1) * NB2 + lane + 64 * u];
+            }
             const C* xb = P + (int64_t)col_idx[e] * NB * s + rc;
             cplx<R> x[KK];
 #pragma unroll
@@ -1503,7 +1505,7 @@ static SolveShape solve_shape(const Cloud* c, int m, int64_t s, chaff_prec prec,
     sh.cocg_st = cocg_width(s);
     sh.cocg_xcd = 1;
     {   // the COCG product follows the tuned public variant's workgroup order (1, 2, 6: linear)
-        int v = tuned_variant(c->n, c->nnzb, s, prec);
+        int v = tuned_variant(NB, c->n, c->nnzb, s, prec);
         if (v < 0) v = default_variant(s);
         sh.cocg_xcd = (v == 1 || v == 2 || v == 6) ? 0 : 1;
     }
@@ -1625,9 +1627,11 @@ static void launch_cg_pdir(const SolveShape& sh, SolveLayout& L, const CZ* Pinv,
 }
 template <typename CZ, typename C, int ST>
 static void launch_cg_update_cl(const SolveShape& sh, SolveLayout& L, const CZ* Mb, C* qz, C* r, hipStream_t st) {
-    const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
-    hipLaunchKernelGGL((k_cg_update_cl<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks,
-                       (const CgState*)L.cg, Mb, qz, r, sh.s, L.part, sh.nslot, 0);
+    if constexpr (NB == 7) {   // clusters of 8 wires x 7 unknowns (solve_impl refuses them otherwise)
+        const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
+        hipLaunchKernelGGL((k_cg_update_cl<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks,
+                           (const CgState*)L.cg, Mb, qz, r, sh.s, L.part, sh.nslot, 0);
+    }
 }
 template <typename C, int ST>
 static void launch_cg_pdir_z(const SolveShape& sh, SolveLayout& L, const C* z, C* p, C* x, int pend,
@@ -2076,6 +2080,8 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     SolveLayout L = carve_solve(ws, ws_bytes, sh);
     if (L.bytes > ws_bytes)
         return fail(CHAFF_EWORKSPACE, "solve workspace too small: need " + std::to_string(L.bytes));
+    if (o->precond == CHAFF_PRECOND_CLUSTER && NB != 7)
+        return fail(CHAFF_EINVAL, "the cluster preconditioner needs wires of 8 segments");
     if (o->precond == CHAFF_PRECOND_CLUSTER) {
         chaff_status ck = cluster_check_table(c, Pinv, st);
         if (ck != CHAFF_OK) return ck;
@@ -2358,6 +2364,7 @@ chaff_status solve(Cloud* c, const chaff_solve_opts* o, const void* Z, const voi
 chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y, int64_t s, int32_t* best,
                       double* best_ms, hipStream_t st) {
     TuneEntry t{};
+    t.nb = NB;
     t.n = c->n;
     t.nnzb = c->nnzb;
     t.s = s;
@@ -2372,8 +2379,8 @@ chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y
             if (rep == 2) CHAFF_HIP(hipEventRecord(a, st));
             chaff_status r = spmm_public(c, prec, Z, X, Y, s, v, st);
             if (r != CHAFF_OK) {
-                hipEventDestroy(a);
-                hipEventDestroy(b);
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
                 return r;
             }
         }
@@ -2387,33 +2394,13 @@ chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y
             bv = v;
         }
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     t.best = bv;
     record_tuning(t);
     if (best) *best = bv;
     if (best_ms) *best_ms = bms;
     return CHAFF_OK;
-}
-
-int32_t tune_report(char* buf, int32_t len) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    std::string out = "[";
-    for (size_t i = 0; i < g_tune.size(); ++i) {
-        const TuneEntry& e = g_tune[i];
-        char line[512];
-        std::snprintf(line, sizeof line,
-                      "%s{\"n\":%lld,\"nnzb\":%lld,\"s\":%lld,\"prec\":%d,\"best\":%d,\"ms\":[%.4f,%.4f,%.4f,%.4f,%.4f,%.4f,%.4f,%.4f]}",
-                      i ? "," : "", (long long)e.n, (long long)e.nnzb, (long long)e.s, e.prec, e.best, e.ms[0],
-                      e.ms[1], e.ms[2], e.ms[3], e.ms[4], e.ms[5], e.ms[6], e.ms[7]);
-        out += line;
-    }
-    out += "]";
-    if (buf && len > 0) {
-        std::strncpy(buf, out.c_str(), (size_t)len - 1);
-        buf[len - 1] = 0;
-    }
-    return (int32_t)out.size() + 1;
 }
 
 chaff_status excitation(Cloud* c, const double* k_hat, const double* e_hat, int64_t s, void* U, hipStream_t st) {
@@ -2424,4 +2411,5 @@ chaff_status excitation(Cloud* c, const double* k_hat, const double* e_hat, int6
     return CHAFF_OK;
 }
 
+}  // namespace CHAFF_KNS
 }  // namespace chaff

@@ -69,7 +69,7 @@ constexpr int BBOX_BLOCKS = 64;
 __global__ void k_bbox(const double* __restrict__ center, const double* __restrict__ tangent,
                        const double* __restrict__ length, const double* __restrict__ radius,
                        const int64_t* __restrict__ cloud_off, double* __restrict__ part,
-                       int32_t* __restrict__ bad) {
+                       int32_t* __restrict__ bad, int nseg) {
     const int c = blockIdx.y;
     const int64_t w0 = cloud_off[c], w1 = cloud_off[c + 1];
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -81,7 +81,7 @@ __global__ void k_bbox(const double* __restrict__ center, const double* __restri
         double L = length[p], a = radius[p];
         double tn = tx * tx + ty * ty + tz * tz;
         bool ok = isfinite(x) && isfinite(y) && isfinite(z) && fabs(tn - 1.0) <= 1e-10 &&
-                  isfinite(L) && L > 0.0 && isfinite(a) && a > 0.0 && a < L / NSEG;
+                  isfinite(L) && L > 0.0 && isfinite(a) && a > 0.0 && a < L / nseg;
         nbad += ok ? 0 : 1;
         if (ok) {
             mn[0] = fmin(mn[0], x); mn[1] = fmin(mn[1], y); mn[2] = fmin(mn[2], z);
@@ -516,7 +516,7 @@ chaff_status build_cloud(const chaff_params* p, const int64_t* cloud_off, const 
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, L.bad, (int64_t)1, 0);
     CHAFF_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_bbox, dim3(BBOX_BLOCKS, nc), dim3(256), 0, st, center, tangent, length, radius,
-                       (const int64_t*)L.d_off, L.bbox_part, L.bad);
+                       (const int64_t*)L.d_off, L.bbox_part, L.bad, (int)p->n_seg);
     CHAFF_LAUNCH_CHECK();
     std::vector<double> part((size_t)nc * BBOX_BLOCKS * 6);
     int32_t bad = 0;
@@ -527,7 +527,7 @@ chaff_status build_cloud(const chaff_params* p, const int64_t* cloud_off, const 
         return fail(CHAFF_EINVAL, std::to_string(bad) +
                                       " wires have a non-finite centre, a tangent that is not unit "
                                       "length (|t|^2 off by > 1e-10), length <= 0 or a radius outside "
-                                      "(0, length/8)");
+                                      "(0, length/n_seg)");
 
     // --- cell grid per cloud: side strictly above d_c, bounded table size
     int64_t cell_base = 0;
@@ -676,6 +676,7 @@ chaff_status build_cloud(const chaff_params* p, const int64_t* cloud_off, const 
     c->d_c = p->d_c;
     c->q_mutual = p->quad_mutual;
     c->q_self = p->quad_self;
+    c->nseg = p->n_seg;
     c->cloud_off = offv;
     c->wires = L.wires;
     c->perm = L.perm;

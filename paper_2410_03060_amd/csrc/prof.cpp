@@ -57,7 +57,7 @@ ProfScope::ProfScope(const char* name, hipStream_t st, ProfWork w) : st_(st) {
 ProfScope::~ProfScope() {
     if (rec_ < 0) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    if (rec_ < (int)g_recs.size()) hipEventRecord(g_recs[rec_].b, st_);
+    if (rec_ < (int)g_recs.size()) (void)hipEventRecord(g_recs[rec_].b, st_);
 }
 
 }  // namespace chaff

@@ -54,6 +54,7 @@ class Cloud:
     cloud_off: np.ndarray         # [C+1] int64
     wavelength: float = WAVELENGTH
     d_c: float = math.inf
+    n_seg: int = N_SEG            # segments per wire (n_seg - 1 rooftop unknowns)
 
     @property
     def n(self) -> int:
@@ -99,7 +100,7 @@ def _uniform_ball(rng: np.random.Generator, n: int, radius: float) -> np.ndarray
 
 
 def single_cloud(center, tangent, length, wavelength=WAVELENGTH, d_c=math.inf,
-                 radius=None) -> Cloud:
+                 radius=None, n_seg: int = N_SEG) -> Cloud:
     center = np.ascontiguousarray(center, dtype=np.float64).reshape(-1, 3)
     tangent = np.ascontiguousarray(tangent, dtype=np.float64).reshape(-1, 3)
     length = np.ascontiguousarray(length, dtype=np.float64).reshape(-1)
@@ -108,7 +109,7 @@ def single_cloud(center, tangent, length, wavelength=WAVELENGTH, d_c=math.inf,
         radius = np.full(n, RADIUS_FRAC * wavelength)
     radius = np.ascontiguousarray(np.broadcast_to(radius, (n,)), dtype=np.float64)
     return Cloud(center, tangent, length, radius,
-                 np.array([0, n], dtype=np.int64), wavelength, d_c)
+                 np.array([0, n], dtype=np.int64), wavelength, d_c, n_seg)
 
 
 def concat_clouds(clouds: list[Cloud]) -> Cloud:
@@ -117,12 +118,13 @@ def concat_clouds(clouds: list[Cloud]) -> Cloud:
         off.append(off[-1] + c.n)
     lam = clouds[0].wavelength
     dc = clouds[0].d_c
-    assert all(c.wavelength == lam and c.d_c == dc for c in clouds)
+    ns = clouds[0].n_seg
+    assert all(c.wavelength == lam and c.d_c == dc and c.n_seg == ns for c in clouds)
     return Cloud(np.concatenate([c.center for c in clouds]),
                  np.concatenate([c.tangent for c in clouds]),
                  np.concatenate([c.length for c in clouds]),
                  np.concatenate([c.radius for c in clouds]),
-                 np.array(off, dtype=np.int64), lam, dc)
+                 np.array(off, dtype=np.int64), lam, dc, ns)
 
 
 def theta_hat(theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
@@ -274,17 +276,46 @@ def c5(n: int = 1_000_000, n_angles: int = 64) -> Workload:
 
 
 def random_cloud(seed: int, n: int, box_lam: float = 4.0, d_c_lam: float = math.inf,
-                 L_lo: float = 0.4, L_hi: float = 0.6) -> Cloud:
+                 L_lo: float = 0.4, L_hi: float = 0.6, n_seg: int = N_SEG) -> Cloud:
     """Small helper for tests: n wires uniform in a cube of side box_lam wavelengths."""
     lam = WAVELENGTH
     rng = np.random.default_rng(seed)
     c = rng.uniform(-0.5 * box_lam * lam, 0.5 * box_lam * lam, (n, 3))
     t = _isotropic(rng, n)
     L = rng.uniform(L_lo * lam, L_hi * lam, n)
-    return single_cloud(c, t, L, lam, d_c_lam * lam)
+    return single_cloud(c, t, L, lam, d_c_lam * lam, n_seg=n_seg)
 
 
-CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4_eval": c4_eval, "c5": c5}
+# --------------------------------------------------------------------------- the paper's discretisation
+
+# Sec. IV (computational statistics): clouds of 10^2 .. 10^6 chaffs uniform in a
+# sphere at 119.37 chaffs per cubic metre, 13 GHz, chaff diameter 20 um and 19
+# rooftop unknowns per chaff (Sec. II-A).  The chaff length is not printed
+# there; the half-wave length at 13 GHz (c/(2 f), the 11.53 mm chaffs of
+# Sec. III-C) is used, and d_c = 2 wavelengths, the paper's default.
+PAPER_DENSITY = 119.37        # chaffs per m^3
+PAPER_FREQ = 13.0e9           # Hz
+PAPER_NSEG = 20               # N_v = 19 unknowns per chaff
+
+
+def paper_cloud(n: int = 100_000, seed: int = 7, d_c_lam: float = 2.0) -> Cloud:
+    """n identical half-wave chaffs (13 GHz) uniform in the sphere of the paper's density."""
+    lam = C0 / PAPER_FREQ
+    a = (3.0 * n / (4.0 * math.pi * PAPER_DENSITY)) ** (1.0 / 3.0)
+    rng = np.random.default_rng(seed)
+    c = _uniform_ball(rng, n, a)
+    t = _isotropic(rng, n)
+    L = np.full(n, C0 / (2.0 * PAPER_FREQ))
+    return single_cloud(c, t, L, lam, d_c_lam * lam, np.full(n, WIRE_RADIUS), PAPER_NSEG)
+
+
+def n2(n: int = 100_000, n_angles: int = 64) -> Workload:
+    """The paper's 10^5-chaff, 2-million-unknown case with its N_v = 19 discretisation,
+    64 V-polarised azimuth incidences (5.625 degree step)."""
+    return Workload("n2", paper_cloud(n), azimuth_incidences(n_angles, 360.0 / n_angles))
+
+
+CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4_eval": c4_eval, "c5": c5, "n2": n2}
 
 
 # --------------------------------------------------------------------------- ensembles

@@ -8,6 +8,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -67,7 +68,8 @@ def _build(B, p, off=None, ws_bytes=1 << 30, geom=True):
 @pytest.mark.parametrize("kw,msg", [
     (dict(n_wires=0), "n_wires"),
     (dict(n_clouds=0), "n_clouds"),
-    (dict(n_seg=20), "n_seg"),
+    (dict(n_seg=12), "n_seg"),
+    (dict(n_seg=7), "n_seg"),
     (dict(wavelength=0.0), "wavelength"),
     (dict(wavelength=float("nan")), "wavelength"),
     (dict(d_c=-1.0), "d_c"),
@@ -194,3 +196,33 @@ def test_cluster_entry_points_validate_before_any_launch(B):
     assert "aligned" in B.last_error()
     assert L.chaff_cluster_apply(H, B.C64, P, P, P, 0, None) == B.EINVAL
     assert L.chaff_cluster_apply(H, B.C64, None, P, P, 1, None) == B.EINVAL
+
+
+def test_tuning_table_round_trip_through_json(B, tmp_path):
+    """chaff_tune_load merges a JSON table; chaff_tune_save writes it back with the same entries."""
+    import json
+    src = tmp_path / "tune_in.json"
+    rows = [{"nb": 7, "n": 1000, "nnzb": 5000, "s": 8, "prec": 0, "best": 6,
+             "ms": [0.5, 0.4, 0.45, 0.41, 0.43, 0.6, 0.3, 0.31]},
+            {"nb": 19, "n": 500, "nnzb": 520, "s": 1, "prec": 1, "best": 0,
+             "ms": [0.1, 0.2, 0.2, 0.2, 0.2, 0.3, 0.0, 0.0]}]
+    src.write_text(json.dumps(rows))
+    assert B.tune_load(str(src)) == 2
+    table = {(e["nb"], e["n"], e["nnzb"], e["s"], e["prec"]): e for e in B.tune_report()}
+    for r in rows:
+        e = table[(r["nb"], r["n"], r["nnzb"], r["s"], r["prec"])]
+        assert e["best"] == r["best"] and np.allclose(e["ms"], r["ms"])
+    out = tmp_path / "tune_out.json"
+    B.tune_save(str(out))
+    back = {(e["nb"], e["n"], e["nnzb"], e["s"], e["prec"]): e["best"] for e in json.loads(out.read_text())}
+    assert back[(7, 1000, 5000, 8, 0)] == 6 and back[(19, 500, 520, 1, 1)] == 0
+
+
+def test_tuning_table_rejects_other_files(B, tmp_path):
+    bad = tmp_path / "bad.json"
+    bad.write_text('[{"nb": 7, "n": 10}]')
+    with pytest.raises(B.ChaffError) as ei:
+        B.tune_load(str(bad))
+    assert ei.value.status == B.EINVAL
+    with pytest.raises(B.ChaffError):
+        B.tune_load(str(tmp_path / "missing.json"))
