@@ -76,11 +76,7 @@ __device__ void static_self(const Anti& p1, const Anti& p0, const Anti& m1, doub
     K[1][1] = k00 - k10 - k01 + k11;
 }
 
-// ------------------------------------------------------------------ self blocks
-
-// One wave per wire, four wires per workgroup; each wave works in its own LDS
-// slot and synchronises only with itself.
-constexpr int SELF_WAVES = 4;
+// ------------------------------------------------------------------ self blocks (8 segments)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -88,33 +84,34 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Self blocks, sampling and assembly.  A wave takes 8 wires; lane (g, d) =
+// (lane / 8, lane % 8) runs the Q x Q samples of segment offset d of wire g
+// (the block is Toeplitz in d = alpha - beta) and, for d <= 1, adds the
+// closed-form static part from its own three FP64 antiderivative values.
+// The four rooftop-half terms T_ab(d) of the 8 offsets meet in LDS, and the 8
+// lanes of a wire assemble its 49 entries (upper triangle evaluated for both
+// (q, q') and (q', q): exactly symmetric), written in place of the diagonal
+// block.  No lane idles through a serial step.
+constexpr int SELF_WAVES = 4;
 template <typename R>
 __global__ __launch_bounds__(64 * SELF_WAVES) void k_self(const Wire* __restrict__ wires, int64_t n,
                                                           const int64_t* __restrict__ diag_pos,
-                                                          cplx<R>* __restrict__ Z, cplx<R>* __restrict__ Pinv,
-                                                          FillParams prm, int32_t* __restrict__ status) {
+                                                          cplx<R>* __restrict__ Z, FillParams prm) {
     using C = cplx<R>;
-    __shared__ C Ts[SELF_WAVES][8][2][2];    // T_ab(d), d = 0..7
-    __shared__ C Abs[SELF_WAVES][7][14];     // augmented [Z | I] for the inverse
-    __shared__ Anti As[SELF_WAVES][4];       // static antiderivatives at v = -1, 0, 1, 2
+    __shared__ C Ts[SELF_WAVES][8][NSEG][2][2];   // T_ab(d) of the wave's 8 wires
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * SELF_WAVES + wv;
-    if (w >= n) return;   // uniform over the wave; waves never wait for each other
-    auto& T = Ts[wv];
-    auto& Ab = Abs[wv];
-    const Wire wr = wires[w];
-    const int d = lane >> 3, kk = lane & 7;
+    const int g = lane >> 3, d = lane & 7;
+    const int64_t w = ((int64_t)blockIdx.x * SELF_WAVES + wv) * 8 + g;
+    const bool live = w < n;
+    const Wire wr = wires[live ? w : n - 1];
     const double Dd = wr.len / NSEG;
     const R D = (R)Dd;
     const R a2 = (R)(wr.rad * wr.rad);
     const R inv_lam = (R)prm.inv_lambda;
     const int q = prm.q;
-    // the four FP64 antiderivative evaluations of the closed-form static part, one lane each
-    if (lane < 4) As[wv][lane] = anti((double)(lane - 1), wr.rad / Dd);
-
     C m00 = {0, 0}, m01 = {0, 0}, m10 = {0, 0}, m11 = {0, 0};
-    if (kk < q) {
+    for (int kk = 0; kk < q; ++kk) {
         const R xk = (R)prm.xq[kk];
         C s0 = {0, 0}, s1 = {0, 0};
         for (int l = 0; l < q; ++l) {
@@ -123,114 +120,225 @@ __global__ __launch_bounds__(64 * SELF_WAVES) void k_self(const Wire* __restrict
             R u = D * ((R)d + (xk - xl));
             R r2 = u * u + a2;
             R ir = rsq(r2);
-            R rr = r2 * ir;
-            R rev = rr * inv_lam;
-            R gre, gim;
-            if (d <= 1) {  // (exp(-jkR) - 1)/R = (-2 sin^2(kR/2) - j sin kR)/R
-                R hs = half_sin(rev);
-                R c, s;
-                phase_cs(rev, c, s);
+            R rev = r2 * ir * inv_lam;
+            R c, sn, gre;
+            phase_cs(rev, c, sn);
+            if (d <= 1) {   // (exp(-jkR) - 1)/R = (-2 sin^2(kR/2) - j sin kR)/R
+                const R hs = half_sin(rev);
                 gre = (R)-2 * hs * hs * ir;
-                gim = -s * ir;
             } else {
-                R c, s;
-                phase_cs(rev, c, s);
                 gre = c * ir;
-                gim = -s * ir;
             }
+            const R gim = -sn * ir;
             s0.re += gl * gre; s0.im += gl * gim;
             s1.re += gl * xl * gre; s1.im += gl * xl * gim;
         }
         const R gk = (R)prm.wq[kk];
-        m00 = cscale(s0, gk);
-        m01 = cscale(s1, gk);
-        m10 = cscale(s0, gk * xk);
-        m11 = cscale(s1, gk * xk);
+        m00 = cadd(m00, cscale(s0, gk));
+        m01 = cadd(m01, cscale(s1, gk));
+        m10 = cadd(m10, cscale(s0, gk * xk));
+        m11 = cadd(m11, cscale(s1, gk * xk));
     }
-    // sum over the 8 test nodes of each offset
-    for (int o = 1; o < 8; o <<= 1) {
-        m00.re += __shfl_xor(m00.re, o); m00.im += __shfl_xor(m00.im, o);
-        m01.re += __shfl_xor(m01.re, o); m01.im += __shfl_xor(m01.im, o);
-        m10.re += __shfl_xor(m10.re, o); m10.im += __shfl_xor(m10.im, o);
-        m11.re += __shfl_xor(m11.re, o); m11.im += __shfl_xor(m11.im, o);
-    }
-    wave_sync();   // As visible
-    if (kk == 0) {
-        const R sc = (R)(Dd * Dd / (4.0 * PI));
-        C A[2][2];
-        A[0][0] = cscale(m11, sc);
-        A[0][1] = cscale(csub(m10, m11), sc);
-        A[1][0] = cscale(csub(m01, m11), sc);
-        A[1][1] = cscale(cadd(csub(csub(m00, m10), m01), m11), sc);
-        if (d <= 1) {   // v = d + 1, d, d - 1 sit at As[d + 2], As[d + 1], As[d]
-            double K[2][2];
-            static_self(As[wv][d + 2], As[wv][d + 1], As[wv][d], K);
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) A[a][b].re += (R)(Dd / (4.0 * PI) * K[a][b]);
-        }
-        C B = cadd(cadd(A[0][0], A[0][1]), cadd(A[1][0], A[1][1]));
-        const R sz = (R)(1.0 / (prm.k * prm.k * Dd * Dd));
+    const R sc = (R)(Dd * Dd / (4.0 * PI));
+    C A[2][2];
+    A[0][0] = cscale(m11, sc);
+    A[0][1] = cscale(csub(m10, m11), sc);
+    A[1][0] = cscale(csub(m01, m11), sc);
+    A[1][1] = cscale(cadd(csub(csub(m00, m10), m01), m11), sc);
+    if (d <= 1) {   // closed-form static part, antiderivatives at v = d + 1, d, d - 1
+        const double b = wr.rad / Dd;
+        double K[2][2];
+        static_self(anti((double)(d + 1), b), anti((double)d, b), anti((double)(d - 1), b), K);
         for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                R sg = (a == b) ? (R)1 : (R)-1;
-                T[d][a][b] = csub(A[a][b], cscale(B, sg * sz));
-            }
+            for (int bb = 0; bb < 2; ++bb) A[a][bb].re += (R)(Dd / (4.0 * PI) * K[a][bb]);
     }
+    const C B = cadd(cadd(A[0][0], A[0][1]), cadd(A[1][0], A[1][1]));
+    const R sz = (R)(1.0 / (prm.k * prm.k * Dd * Dd));
+    auto& T = Ts[wv][g];
+    for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb) T[d][a][bb] = csub(A[a][bb], cscale(B, (a == bb ? (R)1 : (R)-1) * sz));
     wave_sync();
+    if (!live) return;
     C* Zb = Z + diag_pos[w] * NB2;
-    if (lane < NB2) {
-        const int qi = lane / NB, qj = lane % NB;
-        // evaluate the upper-triangle entry for both (qi,qj) and (qj,qi): exact symmetry
+    for (int e = d; e < NB2; e += 8) {
+        const int qi = e / NB, qj = e % NB;
         const int qa = qi < qj ? qi : qj, qb = qi < qj ? qj : qi;
         C acc = {0, 0};
         for (int da = 0; da < 2; ++da)
             for (int db = 0; db < 2; ++db) {
-                int dd = (qa + da) - (qb + db);
-                C t = dd >= 0 ? T[dd][da][db] : T[-dd][db][da];
-                acc = cadd(acc, t);
+                const int dd = (qa + da) - (qb + db);
+                acc = cadd(acc, dd >= 0 ? T[dd][da][db] : T[-dd][db][da]);
             }
-        Zb[lane] = acc;
-        Ab[qi][qj] = acc;
-        Ab[qi][NB + qj] = (qi == qj) ? C{1, 0} : C{0, 0};
+        Zb[e] = acc;
     }
-    wave_sync();
-    if (Pinv == nullptr) return;
-    // Gauss-Jordan with partial pivoting; lane c < 14 owns column c
-    bool singular = false;
-    for (int piv = 0; piv < NB; ++piv) {
-        int best = piv;
-        R bm = Ab[piv][piv].re * Ab[piv][piv].re + Ab[piv][piv].im * Ab[piv][piv].im;
-        for (int r = piv + 1; r < NB; ++r) {
-            R m = Ab[r][piv].re * Ab[r][piv].re + Ab[r][piv].im * Ab[r][piv].im;
-            if (m > bm) { bm = m; best = r; }
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting of one 7 x 7 block held
+// in registers (a[i][j]), every index static: the pivot row is found with
+// compares and moved with selects, and the column swaps of the pivoting are
+// undone the same way at the end.  Returns false for a zero pivot.
+template <typename R>
+__device__ __forceinline__ bool inverse7_regs(cplx<R> (&a)[NB][NB]) {
+    using C = cplx<R>;
+    int piv[NB];
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+        int b = p;
+        R bm = a[p][p].re * a[p][p].re + a[p][p].im * a[p][p].im;
+#pragma unroll
+        for (int i = p + 1; i < NB; ++i) {
+            const R m = a[i][p].re * a[i][p].re + a[i][p].im * a[i][p].im;
+            if (m > bm) { bm = m; b = i; }
         }
-        if (!(bm > (R)0)) { singular = true; break; }
-        C pv = Ab[best][piv];
-        C f[NB];
-        for (int r = 0; r < NB; ++r) f[r] = Ab[r][piv];
-        wave_sync();
-        if (lane < 2 * NB) {
-            C tmp = Ab[piv][lane];
-            Ab[piv][lane] = Ab[best][lane];
-            Ab[best][lane] = tmp;
+        piv[p] = b;
+        if (!(bm > (R)0)) return false;
+#pragma unroll
+        for (int i = p + 1; i < NB; ++i) {
+            const bool sw = i == b;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const C t = a[p][j];
+                a[p][j] = sw ? a[i][j] : t;
+                a[i][j] = sw ? t : a[i][j];
+            }
         }
-        wave_sync();
-        if (best != piv) { C t = f[piv]; f[piv] = f[best]; f[best] = t; }
-        R inv_m = (R)1 / bm;
-        C ip = {pv.re * inv_m, -pv.im * inv_m};
-        if (lane < 2 * NB) {
-            C rowp = cmul(Ab[piv][lane], ip);
-            Ab[piv][lane] = rowp;
-            for (int r = 0; r < NB; ++r)
-                if (r != piv) Ab[r][lane] = csub(Ab[r][lane], cmul(f[r], rowp));
+        const R inv_m = (R)1 / bm;
+        const C ip = {a[p][p].re * inv_m, -a[p][p].im * inv_m};
+        a[p][p] = C{1, 0};
+#pragma unroll
+        for (int j = 0; j < NB; ++j) a[p][j] = cmul(a[p][j], ip);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (i == p) continue;
+            const C f = a[i][p];
+            a[i][p] = C{0, 0};
+#pragma unroll
+            for (int j = 0; j < NB; ++j) a[i][j] = csub(a[i][j], cmul(f, a[p][j]));
         }
-        wave_sync();
     }
-    if (singular) {
-        if (lane == 0) atomicOr(status, 1);
-        return;
+#pragma unroll
+    for (int p = NB - 1; p >= 0; --p) {
+#pragma unroll
+        for (int c = p + 1; c < NB; ++c) {
+            const bool sw = c == piv[p];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const C t = a[i][p];
+                a[i][p] = sw ? a[i][c] : t;
+                a[i][c] = sw ? t : a[i][c];
+            }
+        }
     }
-    if (lane < NB2) Pinv[w * NB2 + lane] = Ab[lane / NB][NB + lane % NB];
+    return true;
+}
+
+// Inverse self blocks (block-diagonal preconditioner of Sec. II-B): one lane
+// per wire, WPW wires per wave.  The wave stages its wires' diagonal blocks
+// in LDS as A[entry][lane] (consecutive lanes, consecutive words) with
+// coalesced loads; each lane inverts its own block by
+// Gauss-Jordan with partial pivoting -- in registers for complex64, in place
+// in LDS for complex128 (rows swapped in LDS, the column swaps undone at the
+// end) -- and the inverses are stored with coalesced writes.
+template <typename R, int WPW>
+__global__ __launch_bounds__(64) void k_self_inverse(int64_t n, const int64_t* __restrict__ diag_pos,
+                                                     const cplx<R>* __restrict__ Z, cplx<R>* __restrict__ Pinv,
+                                                     int32_t* __restrict__ status) {
+    using C = cplx<R>;
+    // one spare column: the staging loops (lanes along the entries of a block)
+    // then step 65 words per lane instead of 64, so they do not all hit one bank
+    __shared__ C A[NB2][WPW + 1];
+    __shared__ int64_t dpos[WPW];
+    const int lane = threadIdx.x;
+    const int64_t w0 = (int64_t)blockIdx.x * WPW;
+    const int nw = (int)(n - w0 < WPW ? n - w0 : WPW);
+    if (lane < nw) dpos[lane] = diag_pos[w0 + lane];
+    __syncthreads();
+    // a fixed trip count unrolled by 8: eight loads of the staging pass in flight per lane
+    constexpr int PASSES = (NB2 * WPW + 63) / 64;
+#pragma unroll 8
+    for (int j = 0; j < PASSES; ++j) {
+        const int it = lane + 64 * j;
+        const int wl = it / NB2, e = it - wl * NB2;
+        if (wl < nw) A[e][wl] = Z[dpos[wl] * NB2 + e];
+    }
+    __syncthreads();
+    if (lane < nw) {
+        bool ok = true;
+        if constexpr (sizeof(R) == sizeof(float)) {
+            C a[NB][NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) a[i][j] = A[i * NB + j][lane];
+            ok = inverse7_regs<R>(a);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) A[i * NB + j][lane] = a[i][j];
+        } else {
+            int piv[NB];
+#pragma unroll
+            for (int p = 0; p < NB; ++p) {
+                int b = p;
+                R bm = A[p * NB + p][lane].re * A[p * NB + p][lane].re +
+                       A[p * NB + p][lane].im * A[p * NB + p][lane].im;
+#pragma unroll
+                for (int i = p + 1; i < NB; ++i) {
+                    const C v = A[i * NB + p][lane];
+                    const R m = v.re * v.re + v.im * v.im;
+                    if (m > bm) { bm = m; b = i; }
+                }
+                piv[p] = b;
+                if (!(bm > (R)0)) { ok = false; break; }
+                C rowp[NB];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    rowp[j] = A[b * NB + j][lane];
+                    if (b != p) A[b * NB + j][lane] = A[p * NB + j][lane];
+                }
+                const R inv_m = (R)1 / bm;
+                const C ip = {rowp[p].re * inv_m, -rowp[p].im * inv_m};
+                rowp[p] = C{1, 0};
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    rowp[j] = cmul(rowp[j], ip);
+                    A[p * NB + j][lane] = rowp[j];
+                }
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    if (i == p) continue;
+                    const C f = A[i * NB + p][lane];
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        const C cur = (j == p) ? C{0, 0} : A[i * NB + j][lane];
+                        A[i * NB + j][lane] = csub(cur, cmul(f, rowp[j]));
+                    }
+                }
+            }
+            if (ok) {
+#pragma unroll
+                for (int p = NB - 1; p >= 0; --p) {
+                    const int b = piv[p];
+                    if (b != p) {
+#pragma unroll
+                        for (int i = 0; i < NB; ++i) {
+                            const C t = A[i * NB + p][lane];
+                            A[i * NB + p][lane] = A[i * NB + b][lane];
+                            A[i * NB + b][lane] = t;
+                        }
+                    }
+                }
+            }
+        }
+        if (!ok) atomicOr(status, 1);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int j = 0; j < PASSES; ++j) {
+        const int it = lane + 64 * j;
+        const int wl = it / NB2, e = it - wl * NB2;
+        if (wl < nw) Pinv[(w0 + wl) * NB2 + e] = A[e][wl];
+    }
 }
 
 // ------------------------------------------------------------------ mutual blocks
@@ -644,10 +752,21 @@ static chaff_status fill_impl(Cloud* c, void* Zv, void* Pinv, hipStream_t st) {
         CHAFF_LAUNCH_CHECK();
     }
     if (c->nseg == NSEG) {
-        ProfScope pss("fill_self", st, 24.0 * 8.0 * c->q_self * c->q_self * (double)c->n, true);
-        hipLaunchKernelGGL((k_self<R>), dim3((unsigned)((c->n + SELF_WAVES - 1) / SELF_WAVES)), dim3(64 * SELF_WAVES), 0,
-                           st, (const Wire*)c->wires, c->n,
-                           (const int64_t*)c->diag_pos, Z, static_cast<C*>(Pinv), ps, c->d_status);
+        {
+            ProfScope pss("fill_self", st, 24.0 * 8.0 * c->q_self * c->q_self * (double)c->n, true);
+            const int64_t wpb = 8 * SELF_WAVES;
+            hipLaunchKernelGGL((k_self<R>), dim3((unsigned)((c->n + wpb - 1) / wpb)), dim3(64 * SELF_WAVES), 0, st,
+                               (const Wire*)c->wires, c->n, (const int64_t*)c->diag_pos, Z, ps);
+        }
+        CHAFF_LAUNCH_CHECK();
+        if (Pinv) {
+            // Gauss-Jordan: about 8 NB^3 flops per block
+            ProfScope psi("fill_self_inverse", st,
+                          ProfWork{2.0 * NB2 * sizeof(C) * (double)c->n, 8.0 * NB * NB2 * (double)c->n});
+            constexpr int WPW = sizeof(R) == 4 ? 64 : 32;
+            hipLaunchKernelGGL((k_self_inverse<R, WPW>), dim3((unsigned)((c->n + WPW - 1) / WPW)), dim3(64), 0, st,
+                               c->n, (const int64_t*)c->diag_pos, (const C*)Z, static_cast<C*>(Pinv), c->d_status);
+        }
     }
     CHAFF_LAUNCH_CHECK();
     if (Pinv) {
