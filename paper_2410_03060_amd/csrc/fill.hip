@@ -8,12 +8,14 @@
 //    the block precision R.  The 7 x 7 block is assembled with cross-lane
 //    permutes (each output needs the four segment pairs its two rooftops
 //    overlap) and stored twice: Z_ij and Z_ji = Z_ij^T.
-//  * Self blocks: one wave64 per wire.  They are Toeplitz in the segment
-//    offset d = alpha - beta, so lanes (d, k) cover the 8 offsets x 8 test
-//    nodes; for d <= 1 the static part 1/(4 pi R) is added in closed form
-//    (FP64 iterated antiderivatives) and only (exp(-jkR) - 1)/(4 pi R) is
-//    sampled.  The same wave inverts the block (Gauss-Jordan, partial
-//    pivoting) for the block-diagonal preconditioner.
+//  * Self blocks: eight wires per wave64.  They are Toeplitz in the segment
+//    offset d = alpha - beta, so lane (wire g, offset d) runs the samples of
+//    one offset; for d <= 1 the static part 1/(4 pi R) is added in closed
+//    form (FP64 iterated antiderivatives) and only (exp(-jkR) - 1)/(4 pi R)
+//    is sampled.  A separate pass inverts the blocks for the block-diagonal
+//    preconditioner, one lane per wire (Gauss-Jordan, partial pivoting).
+//  * 20 segments (the paper's own discretisation): one wave per pair or wire,
+//    lanes looping over the segment pairs or offsets (k_mutual_w, k_self_w).
 #include "common.hpp"
 #include "prof.hpp"
 

@@ -920,7 +920,9 @@ __global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_
 // HBM latency of the Z stream overlaps the arithmetic; lane (group g, column
 // c) applies block columns k = g, g + G, ... (G = 64/S) to RHS column c, and
 // the G partial sums are combined with cross-lane adds.  sigma = p^T q is
-// reduced per tile in FP64 (tpart[tile][r]); two fixed-order passes then sum
+// reduced per tile in FP64 (tpart[tile][r]), with the row's own p taken from
+// the registers that gathered its diagonal block (no second read of p); two
+// fixed-order passes then sum
 // tiles per group and groups per cloud.  The gathers of p are latency bound:
 // complex64 tiles ask the compiler for at least six waves per SIMD (the
 // 64-column MFMA tile fits 60 registers: eight waves); complex128 tiles would
@@ -975,6 +977,11 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
         for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
         f32x4_t mr[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         f32x4_t mi[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        // the row's own p slab, kept from the gather of the diagonal block for p^T q
+        // (the lane writing row q holds p_q there: q % G == g, at kk = q / G)
+        cplx<R> xd[KK];
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) xd[kk] = {0, 0};
         const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
         // lane l stages entries l, l + 64, ... of each block (ZPL per lane)
         CZ zn[ZPL];
@@ -991,12 +998,17 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
                 for (int u = 0; u < ZPL; ++u)
                     if (lane + 64 * u < NB2) zn[u] = Z[(e + 1) * NB2 + lane + 64 * u];
             }
-            const C* xb = P + (int64_t)col_idx[e] * NB * s + rc;
+            const int64_t ce = col_idx[e];
+            const C* xb = P + ce * NB * s + rc;
             cplx<R> x[KK];
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 const int k = g + kk * G;
                 x[kk] = k < NB ? ccast<cplx<R>>(xb[k * s]) : cplx<R>{0, 0};
+            }
+            if (ce == i) {   // wave-uniform: the diagonal block
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) xd[kk] = x[kk];
             }
             // the block written above by this wave's lanes is visible to all of its lanes
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1044,7 +1056,7 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
                 if (q % G != g) continue;
                 const int64_t o = (i * NB + q) * s + r;
                 Q[o] = ccast<C>(acc[q]);
-                cfma(dot, ccast<c128>(P[o]), ccast<c128>(acc[q]));
+                cfma(dot, ccast<c128>(xd[q / G]), ccast<c128>(acc[q]));
             }
         }
     }
