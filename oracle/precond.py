@@ -17,6 +17,13 @@ not below the cloud's extent.  The last group of a cloud may be shorter.
 
 Every function here is a plain definition: a stable sort for the order, a
 dense inverse per group for the preconditioner, dense products to apply it.
+
+The neighbourhood-inverse preconditioner is the same idea centred on every
+wire: wire p's neighbourhood is p and its nearest near-set neighbours (at most
+`size` wires); its row of the preconditioner is p's row block of the inverse
+of the neighbourhood's submatrix, and the rows are symmetrised
+(M_pq = (W_p[p,q] + W_q[q,p]^T)/2) so that M is complex symmetric like Z.
+A dense inverse per wire, plainly written, again.
 """
 from __future__ import annotations
 
@@ -137,3 +144,72 @@ def condition_numbers(Zs, groups) -> np.ndarray:
         D = D.toarray() if hasattr(D, "toarray") else np.asarray(D)
         out[k] = np.linalg.cond(D)
     return out
+
+
+# --------------------------------------------------------------------------- neighbourhood inverse
+
+def neighbourhoods(cloud, size: int):
+    """For every wire p (caller order): [p] followed by at most size - 1 wires of
+    p's near set (eq. 9: same cloud, centroid distance <= d_c), nearest first.
+
+    Order: the FP64 squared centroid distance ((dx*dx + dy*dy) + dz*dz), each
+    operation rounded (the near-set test of eq. 9), then the lower caller index.
+    """
+    from . import mom
+    if size < 1:
+        raise ValueError("a neighbourhood holds at least the wire itself")
+    c = np.asarray(cloud.center, dtype=np.float64)
+    I, J = mom.near_pairs(c, cloud.cloud_off, float(cloud.d_c))
+    d2 = mom._d2(c[I], c[J])
+    out = []
+    starts = np.searchsorted(I, np.arange(cloud.n + 1))
+    for p in range(cloud.n):
+        a, b = int(starts[p]), int(starts[p + 1])
+        js, ds = J[a:b], d2[a:b]
+        order = np.lexsort((js, ds))        # distance first, then caller index
+        out.append(np.concatenate([[p], js[order][:size - 1]]).astype(np.int64))
+    return out
+
+
+def neighbourhood_raw_blocks(Zs, nbhd, nb: int = NB) -> dict:
+    """{(p, q): W_p[p, q]} for q in nbhd[p]: the row block of wire p of W_p, the
+    inverse of the sparsified matrix restricted to the wires of nbhd[p] (their
+    diagonal blocks and every near-pair block between them)."""
+    Zc = Zs.tocsr() if hasattr(Zs, "tocsr") else np.asarray(Zs)
+    out = {}
+    for p, g in enumerate(nbhd):
+        r = (nb * np.asarray(g)[:, None] + np.arange(nb)[None, :]).reshape(-1)
+        A = Zc[r][:, r]
+        A = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+        W = np.linalg.inv(A)
+        for k, q in enumerate(g):
+            out[(p, int(q))] = W[:nb, nb * k:nb * k + nb]
+    return out
+
+
+def neighbourhood_inverse(Zs, nbhd, nb: int = NB):
+    """The neighbourhood-inverse preconditioner M (scipy BSR, caller order).
+
+    M_pq = (W_p[p, q] + W_q[q, p]^T) / 2, a raw block that does not exist (q not
+    in nbhd[p]) counting as zero; M is complex symmetric like Z, with blocks
+    only on pairs where one wire is in the other's neighbourhood (a subset of
+    the near set).  One wire per neighbourhood gives the block-diagonal
+    preconditioner of Sec. II-B; neighbourhoods that contain whole groups of
+    mutually coupled wires give the exact inverse on those groups."""
+    import scipy.sparse as sp
+    raw = neighbourhood_raw_blocks(Zs, nbhd, nb)
+    keys = set(raw) | {(q, p) for (p, q) in raw}
+    n = len(nbhd)
+    I = np.array(sorted(keys), dtype=np.int64).reshape(-1, 2)
+    blocks = np.zeros((I.shape[0], nb, nb), dtype=np.complex128)
+    for t, (p, q) in enumerate(I):
+        a = raw.get((int(p), int(q)))
+        b = raw.get((int(q), int(p)))
+        v = np.zeros((nb, nb), dtype=np.complex128)
+        if a is not None:
+            v = v + a
+        if b is not None:
+            v = v + b.T
+        blocks[t] = 0.5 * v
+    indptr = np.searchsorted(I[:, 0], np.arange(n + 1)) if I.size else np.zeros(n + 1, dtype=np.int64)
+    return sp.bsr_matrix((blocks, I[:, 1], indptr), shape=(nb * n, nb * n), blocksize=(nb, nb))
