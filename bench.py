@@ -40,6 +40,9 @@ KERNEL_SYMBOLS = {
     "fill_self": ("chaff::k_self", "paper_2410_03060_amd/csrc/fill.hip"),
     "rcs_mono": ("chaff::k_mono", "paper_2410_03060_amd/csrc/farfield.hip"),
     "cluster_build": ("chaff::k_cluster_build", "paper_2410_03060_amd/csrc/precond.hip"),
+    "nbhd_apply": ("chaff::kr7::k_cocg_spmm", "paper_2410_03060_amd/csrc/krylov_impl.hpp"),
+    "k_cg_rupd": ("chaff::kr7::k_cg_rupd", "paper_2410_03060_amd/csrc/krylov_impl.hpp"),
+    "nbhd_build": ("chaff::k_nbhd_build", "paper_2410_03060_amd/csrc/precond.hip"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
@@ -98,7 +101,8 @@ CONFIGS = {
                     "complex64 + FP64 refinement, block-diagonal preconditioner"),
 }
 GUESSES = {"zero": 0, "bj": 2, "mlp": 1}   # bj: x0 = P u with the solve's preconditioner P
-PRECONDS = {"block": 0, "cluster": 1}
+PRECONDS = {"block": 0, "cluster": 1, "nbhd": 2}
+NBHD_SIZE = 6   # wires per neighbourhood of the neighbourhood-inverse preconditioner (default)
 # training recipe of the learned guess per evaluation workload: (generator, clouds, epochs)
 MLP_TRAINING = {"c4_eval": ("c4_train_cloud", 200, 12), "c5": ("c5_train_cloud", 64, 12)}
 METHODS = {"gmres": 0, "cocg": 1, "cocg_rr": 2, "gcr": 3}
@@ -414,6 +418,8 @@ def main(argv=None) -> int:
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
     ap.add_argument("--guess", default=None, choices=sorted(GUESSES),
                     help="initial guess: zero, bj (block-Jacobi) or mlp (learned; trained before timing)")
+    ap.add_argument("--nbhd-size", type=int, default=None,
+                    help="wires per neighbourhood of the neighbourhood-inverse preconditioner (1..8)")
     ap.add_argument("--precond", default=None, choices=sorted(PRECONDS),
                     help="preconditioner: block (inverse self blocks) or cluster (inverse diagonal "
                          "blocks of groups of 8 nearby wires)")
@@ -471,11 +477,20 @@ def main(argv=None) -> int:
     if guess == "mlp":
         theta, mlp_report = train_guess(a.config, B)
 
+    nbhd_size = a.nbhd_size or cfg.get("nbhd_size", NBHD_SIZE)
+
+    def make_precond(cl, Z, P):
+        if pc == "cluster":
+            return B.cluster_precond(cl, Z, prec)
+        if pc == "nbhd":
+            return B.nbhd_precond(cl, Z, nbhd_size, prec)
+        return P
+
     def step(guess_kind=None):
         gk = guess_kind or guess
         cl = B.build_cloud(geom)
         Z, P = B.fill_Z(cl, prec)
-        M = B.cluster_precond(cl, Z, prec) if pc == "cluster" else P
+        M = make_precond(cl, Z, P)
         x0 = B.mlp_guess(cl, P, theta, kh, eh, prec=prec) if gk == "mlp" else None
         opts.use_x0 = GUESSES[gk]
         X, info = B.solve(cl, Z, M, kh, eh, opts, x0=x0)
@@ -524,7 +539,7 @@ def main(argv=None) -> int:
         ranked = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])
         name, k = ranked[0]
         # kernels whose complex64 products run on the FP32 matrix cores
-        mfma = {"spmm", "spmm_narrow"} | ({"k_cg_update"} if pc == "cluster" else set())
+        mfma = {"spmm", "spmm_narrow", "nbhd_apply", "nbhd_apply_narrow"} | ({"k_cg_update"} if pc == "cluster" else set())
         roof = roofline_of(k, prec == B.C64 and name in mfma)
         roof["traffic"] = measured_traffic(a.config, name)
         symbols = dict(KERNEL_SYMBOLS)
@@ -564,7 +579,8 @@ def main(argv=None) -> int:
                    "clouds": int(wl.cloud.n_clouds), "rhs": int(R), "unknowns": int(wl.cloud.n * (wl.cloud.n_seg - 1)),
                    "unknowns_per_wire": int(wl.cloud.n_seg - 1),
                    "nnzb": int(cl.nnzb), "pairs": int(cl.n_pairs), "method": method, "restart": restart,
-                   "tol": a.tol, "initial_guess": guess, "preconditioner": pc},
+                   "tol": a.tol, "initial_guess": guess, "preconditioner": pc,
+                   "neighbourhood_size": nbhd_size if pc == "nbhd" else None},
         "solver": {"cycles": infos[-1]["cycles"], "iterations": infos[-1]["iterations"],
                    "max_rel_residual": infos[-1]["max_rel_residual"],
                    "systems_per_step": int(wl.cloud.n_clouds * R), "solved_total": solved},
@@ -588,7 +604,7 @@ def main(argv=None) -> int:
     geom_h = B.upload(wl.cloud)
     cl_h = B.build_cloud(geom_h)
     Z_h, P_h = B.fill_Z(cl_h, prec)
-    M_h = B.cluster_precond(cl_h, Z_h, prec) if pc == "cluster" else P_h
+    M_h = make_precond(cl_h, Z_h, P_h)
     x0_h = B.mlp_guess(cl_h, P_h, theta, kh, eh, prec=prec) if guess == "mlp" else None
     opts.use_x0 = GUESSES[guess]
     X_h, info_h = B.solve(cl_h, Z_h, M_h, kh, eh, opts, x0=x0_h)

@@ -158,7 +158,7 @@ typedef struct {
     int32_t max_cycles;       /* restart/refinement cycles (50) */
     int32_t use_x0;           /* 0: x0 = 0; 1: X holds an initial guess on entry;
                                  2: preconditioner guess x0 = P u (P the preconditioner
-                                    passed as Pinv: block or cluster) */
+                                    passed as Pinv: block, cluster or neighbourhood) */
     int32_t prec;             /* chaff_prec of Z, Pinv and the Krylov vectors */
     int32_t spmm_variant;     /* -1: tuned (chaff_autotune) or default choice; else variant 0..7 */
     int32_t method;           /* chaff_method */
@@ -170,8 +170,11 @@ typedef struct {
  *   CHAFF_PRECOND_BLOCK   [N][NB][NB] inverse self blocks from chaff_fill_Z
  *                         (the block-diagonal preconditioner of Sec. II-B);
  *   CHAFF_PRECOND_CLUSTER the buffer of chaff_cluster_precond (inverse
- *                         diagonal blocks of groups of 8 nearby wires). */
-typedef enum { CHAFF_PRECOND_BLOCK = 0, CHAFF_PRECOND_CLUSTER = 1 } chaff_precond;
+ *                         diagonal blocks of groups of 8 nearby wires);
+ *   CHAFF_PRECOND_NBHD    the buffer of chaff_nbhd_precond (each wire's row
+ *                         of the inverse of its neighbourhood's submatrix,
+ *                         on Z's block pattern). */
+typedef enum { CHAFF_PRECOND_BLOCK = 0, CHAFF_PRECOND_CLUSTER = 1, CHAFF_PRECOND_NBHD = 2 } chaff_precond;
 
 /* Krylov method of each refinement cycle.  GMRES(m) with classical
  * Gram-Schmidt applied twice; COCG = conjugate-orthogonal CG, valid because
@@ -241,6 +244,41 @@ chaff_status chaff_cluster_precond(chaff_cloud c, chaff_prec prec, const void* Z
  * chaff_solve makes the same check when o->precond is CHAFF_PRECOND_CLUSTER. */
 chaff_status chaff_cluster_apply(chaff_cloud c, chaff_prec prec, const void* M, const void* X,
                                  void* Y, int64_t s, chaff_stream stream);
+
+/* ------------------------------------------------------------------ neighbourhood-inverse preconditioner
+ * The block-diagonal preconditioner of Sec. II-B centred on every wire.  Wire
+ * p's neighbourhood N(p) is p followed by at most size - 1 wires of its near
+ * set (eq. 9), nearest first: by the FP64 squared centroid distance
+ * ((dx*dx + dy*dy) + dz*dz), each operation rounded, then the lower caller
+ * index.  With A_p the submatrix of Z on the wires of N(p) (their self
+ * blocks and every near-pair block between them) and W_p = A_p^-1, the
+ * preconditioner is
+ *     M_pq = (W_p[p,q] + W_q[q,p]^T) / 2,
+ * a raw block W_p[p,q] with q outside N(p) counting as zero: M is complex
+ * symmetric like Z (so COCG may use it) and has blocks only on near pairs.
+ * size = 1 gives the block-diagonal preconditioner; a group of mutually near
+ * wires that is every member's whole neighbourhood is inverted exactly.
+ * Each W_p[p, .] is computed by Gauss-Jordan elimination with partial
+ * pivoting in complex FP32 (also for CHAFF_C128 buffers), so M holds FP32
+ * accuracy: it changes how fast the solver converges, never the solution.
+ * Wires of 8 segments only (CHAFF_EINVAL for n_seg = 20).
+ *
+ * Buffer M (device, 256-byte aligned, chaff_nbhd_precond_bytes):
+ *   a 256-byte header {int64 tag, int64 N, int64 nnzb, int32 size, int32 prec},
+ *   then [N][size] int32 neighbourhoods (internal wire indices, slot 0 the
+ *   wire itself, -1 where the near set has fewer wires) padded to a multiple
+ *   of 256 bytes, then [nnzb][7][7] complex (prec): M in Z's block order
+ *   (zero blocks where neither wire is in the other's neighbourhood).
+ * It is tied to the handle it was built for and to Z of the same prec. */
+#define CHAFF_NBHD_MAX 8
+size_t chaff_nbhd_precond_bytes(chaff_cloud c, chaff_prec prec, int32_t size);   /* 0 on a bad argument */
+/* Builds M from Z (chaff_fill_Z, same prec); 1 <= size <= CHAFF_NBHD_MAX.
+ * Host-synchronising; returns CHAFF_ESINGULAR if a neighbourhood system has a
+ * zero pivot (M is then unusable).  chaff_solve reads M's header back and
+ * checks it against the handle and prec when o->precond is CHAFF_PRECOND_NBHD
+ * (CHAFF_EINVAL for another buffer). */
+chaff_status chaff_nbhd_precond(chaff_cloud c, chaff_prec prec, int32_t size, const void* Z, void* M,
+                                chaff_stream stream);
 
 /* Excitation alone: U [N*NB][R] complex double (caller order), eq. (4) without
  * its -(j/(w mu0)) factor, closed-form triangle transform. */

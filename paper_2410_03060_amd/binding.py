@@ -114,6 +114,8 @@ EXPORTS = {
     "chaff_cluster_count": (C.c_int64, [C.c_void_p]),
     "chaff_cluster_precond_bytes": (C.c_size_t, [C.c_void_p, C.c_int]),
     "chaff_cluster_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chaff_nbhd_precond_bytes": (C.c_size_t, [C.c_void_p, C.c_int, C.c_int32]),
+    "chaff_nbhd_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "chaff_cluster_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                       C.c_void_p]),
     "chaff_last_error": (C.c_char_p, []),
@@ -314,8 +316,9 @@ def fill_Z(cl: Cloud, prec: int = C64, with_pinv: bool = True):
 
 
 GMRES, COCG, COCG_RR, GCR = 0, 1, 2, 3
-PRECOND_BLOCK, PRECOND_CLUSTER = 0, 1
+PRECOND_BLOCK, PRECOND_CLUSTER, PRECOND_NBHD = 0, 1, 2
 CLUSTER_WIRES, CLUSTER_ROWS = 8, 56
+NBHD_MAX, NBHD_HEADER = 8, 256
 
 
 def solve_opts(tol=1e-6, inner_tol=1e-4, restart=30, max_cycles=50, use_x0=0, prec=C64,
@@ -351,6 +354,29 @@ def cluster_blocks(cl: Cloud, M, prec: int = C64):
     dt = torch.complex64 if prec == C64 else torch.complex128
     esz = 8 if prec == C64 else 16
     return M[off:off + n * CLUSTER_ROWS * CLUSTER_ROWS * esz].view(dt).view(n, CLUSTER_ROWS, CLUSTER_ROWS)
+
+
+def nbhd_precond(cl: Cloud, Z, size: int, prec: int = C64):
+    """Neighbourhood-inverse preconditioner buffer (chaff_nbhd_precond): uint8 [bytes]."""
+    nbytes = lib().chaff_nbhd_precond_bytes(cl.handle, prec, int(size))
+    if nbytes == 0:
+        raise ChaffError(EINVAL, last_error() or "bad neighbourhood preconditioner arguments")
+    M = torch.empty(nbytes, dtype=torch.uint8, device=cl.device)
+    _check(lib().chaff_nbhd_precond(cl.handle, prec, int(size), _ptr(Z), _ptr(M), _stream()))
+    return M
+
+
+def nbhd_table(cl: Cloud, M, size: int):
+    """[N, size] int32 view of the neighbourhoods (internal indices, -1 unused) of a buffer."""
+    return M[NBHD_HEADER:NBHD_HEADER + cl.n * size * 4].view(torch.int32).view(cl.n, size)
+
+
+def nbhd_blocks(cl: Cloud, M, size: int, prec: int = C64):
+    """[nnzb, 7, 7] complex view of the preconditioner's blocks (Z's block order)."""
+    off = NBHD_HEADER + (cl.n * size * 4 + 255) // 256 * 256
+    dt = torch.complex64 if prec == C64 else torch.complex128
+    esz = 8 if prec == C64 else 16
+    return M[off:off + cl.nnzb * cl.nb * cl.nb * esz].view(dt).view(cl.nnzb, cl.nb, cl.nb)
 
 
 def cluster_apply(cl: Cloud, M, X, prec: int = C64, Y=None):

@@ -111,6 +111,9 @@ size_t cluster_buffer_bytes(const Cloud* c, chaff_prec prec);
 chaff_status cluster_precond(Cloud* c, chaff_prec prec, const void* Z, void* M, hipStream_t st);
 chaff_status cluster_apply_public(Cloud* c, chaff_prec prec, const void* M, const void* X, void* Y, int64_t s,
                                   hipStream_t st);
+constexpr int NBH_MAX = 8;   // wires per neighbourhood at most (CHAFF_NBHD_MAX)
+size_t nbhd_buffer_bytes(const Cloud* c, chaff_prec prec, int size);
+chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, void* M, hipStream_t st);
 
 }  // namespace chaff
 
@@ -343,8 +346,8 @@ static chaff_status check_opts(const chaff_solve_opts* o) {
         return fail(CHAFF_EINVAL, "method must be CHAFF_GMRES, CHAFF_COCG, CHAFF_COCG_RR or CHAFF_GCR");
     if (!restarted && o->restart > 1000000) return fail(CHAFF_EINVAL, "restart too large");
     if (o->reserved != 0) return fail(CHAFF_EINVAL, "reserved must be 0");
-    if (o->precond != CHAFF_PRECOND_BLOCK && o->precond != CHAFF_PRECOND_CLUSTER)
-        return fail(CHAFF_EINVAL, "precond must be CHAFF_PRECOND_BLOCK or CHAFF_PRECOND_CLUSTER");
+    if (o->precond != CHAFF_PRECOND_BLOCK && o->precond != CHAFF_PRECOND_CLUSTER && o->precond != CHAFF_PRECOND_NBHD)
+        return fail(CHAFF_EINVAL, "precond must be CHAFF_PRECOND_BLOCK, CHAFF_PRECOND_CLUSTER or CHAFF_PRECOND_NBHD");
     return CHAFF_OK;
 }
 
@@ -364,10 +367,14 @@ chaff_status chaff_solve(chaff_cloud h, const chaff_solve_opts* o, const void* Z
     if (!Z || !Pinv) return fail(CHAFF_EINVAL, "Z and Pinv are required");
     if (o->precond == CHAFF_PRECOND_CLUSTER && ((uintptr_t)Pinv % 256) != 0)
         return fail(CHAFF_EINVAL, "the cluster preconditioner buffer must be 256-byte aligned");
+    if (o->precond == CHAFF_PRECOND_NBHD && ((uintptr_t)Pinv % 256) != 0)
+        return fail(CHAFF_EINVAL, "the neighbourhood-inverse preconditioner buffer must be 256-byte aligned");
     if (!k_hat || !e_hat || !X || !ws) return fail(CHAFF_EINVAL, "NULL k_hat/e_hat/X/ws");
     if (n_rhs < 1 || n_rhs > 65535) return fail(CHAFF_EINVAL, "n_rhs must be in [1, 65535]");
     if (h->c.nseg != NSEG && o->precond == CHAFF_PRECOND_CLUSTER)
         return fail(CHAFF_EINVAL, "the cluster preconditioner needs wires of 8 segments");
+    if (h->c.nseg != NSEG && o->precond == CHAFF_PRECOND_NBHD)
+        return fail(CHAFF_EINVAL, "the neighbourhood-inverse preconditioner needs wires of 8 segments");
     const bool k7 = h->c.nseg == NSEG;
     size_t need = k7 ? kr7::solve_workspace_bytes(&h->c, o, n_rhs) : kr19::solve_workspace_bytes(&h->c, o, n_rhs);
     if (ws_bytes < need) return fail(CHAFF_EWORKSPACE, "solve workspace too small: need " + std::to_string(need));
@@ -402,6 +409,23 @@ chaff_status chaff_cluster_apply(chaff_cloud h, chaff_prec prec, const void* M, 
     if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
     if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the cluster preconditioner needs wires of 8 segments");
     return cluster_apply_public(&h->c, prec, M, X, Y, s, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+size_t chaff_nbhd_precond_bytes(chaff_cloud h, chaff_prec prec, int32_t size) {
+    if (!h || (prec != CHAFF_C64 && prec != CHAFF_C128) || size < 1 || size > NBH_MAX || h->c.nseg != NSEG) return 0;
+    return nbhd_buffer_bytes(&h->c, prec, size);
+}
+
+chaff_status chaff_nbhd_precond(chaff_cloud h, chaff_prec prec, int32_t size, const void* Z, void* M,
+                                chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !Z || !M) return fail(CHAFF_EINVAL, "NULL argument");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
+    if (size < 1 || size > NBH_MAX) return fail(CHAFF_EINVAL, "size must be in [1, CHAFF_NBHD_MAX]");
+    if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
+    if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the neighbourhood-inverse preconditioner needs wires of 8 segments");
+    return nbhd_precond(&h->c, prec, size, Z, M, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
 

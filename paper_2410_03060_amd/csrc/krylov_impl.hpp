@@ -1166,6 +1166,41 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
     if (threadIdx.x < ST && r < s) part[((int64_t)blockIdx.x * nslot + slot0 + 1) * s + r] = v2;
 }
 
+// r -= alpha q ; partial ||r||^2 (slot0).  The neighbourhood-inverse
+// preconditioner forms z = M r and r^T z in a block-sparse product of its own.
+template <typename C, int ST>
+__global__ __launch_bounds__(RB) void k_cg_rupd(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
+                                                const C* __restrict__ q, C* __restrict__ rv, int64_t s,
+                                                c128* __restrict__ part, int nslot, int slot0) {
+    using R = typename real_of<C>::type;
+    __shared__ c128 red[RB];
+    const Chunk ch = chunks[blockIdx.x];
+    const int rsub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
+    const int64_t r = (int64_t)blockIdx.y * ST + threadIdx.x % ST;
+    c128 rr = {0, 0};
+    if (r < s) {
+        const CgState& S = cg[(int64_t)ch.cloud * s + r];
+        const cplx<R> na = {-(R)S.alpha_re, -(R)S.alpha_im};
+        for (int64_t i = ch.w0 + rsub; i < ch.w1; i += RB / ST) {
+            cplx<R> res[NB], qv[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {   // issue all loads before any arithmetic
+                const int64_t o = (i * NB + k) * s + r;
+                res[k] = rv[o];
+                qv[k] = q[o];
+            }
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                cfma(res[k], na, qv[k]);
+                rv[(i * NB + k) * s + r] = res[k];
+                rr.re += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
+            }
+        }
+    }
+    c128 v = block_col_reduce(rr, ST, red);
+    if (threadIdx.x < ST && r < s) part[((int64_t)blockIdx.x * nslot + slot0) * s + r] = v;
+}
+
 // z = M r for one cluster on the FP32 matrix cores (v_mfma_f32_16x16x4_f32,
 // full FP32 products and sums): wave w forms the 16-column tile
 // [16 w, 16 w + 16) of z for the four 16-row tiles of the block (rows 56-63
@@ -1637,6 +1672,12 @@ static void launch_cg_pdir(const SolveShape& sh, SolveLayout& L, const CZ* Pinv,
     hipLaunchKernelGGL((k_cg_pdir<CZ, C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const CgState*)L.cg,
                        Pinv, r, p, x, sh.s, pend);
 }
+template <typename C, int ST>
+static void launch_cg_rupd(const SolveShape& sh, SolveLayout& L, const C* q, C* r, hipStream_t st) {
+    const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
+    hipLaunchKernelGGL((k_cg_rupd<C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const CgState*)L.cg, q, r,
+                       sh.s, L.part, sh.nslot, 1);
+}
 template <typename CZ, typename C, int ST>
 static void launch_cg_update_cl(const SolveShape& sh, SolveLayout& L, const CZ* Mb, C* qz, C* r, hipStream_t st) {
     if constexpr (NB == 7) {   // clusters of 8 wires x 7 unknowns (solve_impl refuses them otherwise)
@@ -1752,6 +1793,9 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     const CZ* Mb = clus ? reinterpret_cast<const CZ*>(reinterpret_cast<const char*>(Pinv) +
                                                       cluster_table_bytes(cluster_count(c)))
                         : nullptr;
+    // neighbourhood inverse: Pinv is M on Z's block pattern; z = M r is a product of its own, kept in q
+    const bool nbhd = o->precond == CHAFF_PRECOND_NBHD;
+    const bool zq = clus || nbhd;   // z lives in q between the update and the direction pass
     SolveShape cs = sh;            // current shape (columns shrink under compaction)
     SolveLayout Lc = L;            // current tile set
     std::vector<int32_t> colmap(s);
@@ -1780,7 +1824,40 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     std::vector<int32_t> flags;
     for (int k = 0; k <= o->restart; ++k) {
         const int wst = spmm_tile_width(cs.s);
-        if (clus) {   // r -= alpha q, z = M r (over q), r^T z, ||r||^2
+        if (nbhd) {   // r -= alpha q, ||r||^2; then z = M r (over q) with per-tile r^T z
+            {
+                ProfScope pu(wst == 64 ? "k_cg_rupd" : "k_cg_rupd_narrow", st, (3.0 * rows * cs.s) * sizeof(C));
+                switch (wst) {
+                    case 1: launch_cg_rupd<C, 1>(cs, Lc, q, r, st); break;
+                    case 2: launch_cg_rupd<C, 2>(cs, Lc, q, r, st); break;
+                    case 4: launch_cg_rupd<C, 4>(cs, Lc, q, r, st); break;
+                    case 8: launch_cg_rupd<C, 8>(cs, Lc, q, r, st); break;
+                    case 16: launch_cg_rupd<C, 16>(cs, Lc, q, r, st); break;
+                    case 32: launch_cg_rupd<C, 32>(cs, Lc, q, r, st); break;
+                    default: launch_cg_rupd<C, 64>(cs, Lc, q, r, st); break;
+                }
+            }
+            CHAFF_LAUNCH_CHECK();
+            {
+                ProfScope pm(cs.cocg_st == 64 ? "nbhd_apply" : "nbhd_apply_narrow", st,
+                             ProfWork{((double)sizeof(CZ) * NB2 + 4.0) * c->nnzb + 4.0 * (c->n + 1) +
+                                          2.0 * rows * cs.s * sizeof(C),
+                                      8.0 * NB2 * (double)c->nnzb * cs.s});
+                switch (cs.cocg_st) {
+                    case 8: launch_cocg_spmm<CZ, C, 8>(c, cs, Lc, Pinv, r, q, st); break;
+                    case 16: launch_cocg_spmm<CZ, C, 16>(c, cs, Lc, Pinv, r, q, st); break;
+                    case 32: launch_cocg_spmm<CZ, C, 32>(c, cs, Lc, Pinv, r, q, st); break;
+                    default: launch_cocg_spmm<CZ, C, 64>(c, cs, Lc, Pinv, r, q, st); break;
+                }
+            }
+            CHAFF_LAUNCH_CHECK();
+            group_sum(L.tpart, cs.s, 0, 0, 1, Lc.group_tile_off, cs.n_groups, cs.s, L.gpart, st);
+            CHAFF_LAUNCH_CHECK();
+            group_sum(L.gpart, cs.s, 0, 0, 1, Lc.cloud_group_off, cs.n_clouds, cs.s, L.h1, st);   // r^T z
+            CHAFF_LAUNCH_CHECK();
+            chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, cs.n_clouds, cs.nslot, 1, 1, cs.s,
+                      L.h1 + cs.nsys, st);   // ||r||^2
+        } else if (clus) {   // r -= alpha q, z = M r (over q), r^T z, ||r||^2
             ProfScope pu(wst == 64 ? "k_cg_update" : "k_cg_update_narrow", st,
                          ProfWork{(4.0 * rows * cs.s) * sizeof(C) + (double)cluster_count(c) * CLR2 * sizeof(CZ),
                                   8.0 * CLR2 * (double)cluster_count(c) * cs.s});
@@ -1808,8 +1885,9 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
             }
         }
         CHAFF_LAUNCH_CHECK();
-        chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, cs.n_clouds, cs.nslot, 0, 2, cs.s, L.h1,
-                  st);
+        if (!nbhd)
+            chunk_sum((const c128*)L.part, (const int32_t*)L.cloud_chunk_off, cs.n_clouds, cs.nslot, 0, 2, cs.s,
+                      L.h1, st);
         CHAFF_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)L.counter, (int64_t)1);
         CHAFF_LAUNCH_CHECK();
@@ -1835,7 +1913,7 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
                 if (live) keep.push_back((int32_t)j);
             }
             if (!keep.empty() && (int64_t)keep.size() <= wst / 2) {
-                chaff_status cst = cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, p, q, clus, st);
+                chaff_status cst = cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, p, q, zq, st);
                 if (cst != CHAFF_OK) return cst;
                 pending_applied = true;
                 if (g_verbose)
@@ -1844,7 +1922,7 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         }
         mode = 1;
         ++iters;
-        if (clus) {   // x += alpha p_old (deferred), p = z + beta p_old
+        if (zq) {   // x += alpha p_old (deferred), p = z + beta p_old
             const int pend = pending_applied ? 0 : 1;
             pending_applied = false;
             ProfScope pp(spmm_tile_width(cs.s) == 64 ? "k_cg_p" : "k_cg_p_narrow", st,
@@ -2013,6 +2091,9 @@ static chaff_status gcr_cycle(Cloud* c, const chaff_solve_opts* o, const SolveSh
         if (o->precond == CHAFF_PRECOND_CLUSTER)
             sst = cluster_apply_launch(c, (chaff_prec)o->prec, Pinv, rho, sizeof(C) == 16, uj, sizeof(C) == 16,
                                        false, s, st, "precond");
+        else if (o->precond == CHAFF_PRECOND_NBHD)
+            sst = spmm_launch<CZ, C, C, 0, false>(c->row_ptr, c->col_idx, Pinv, rho, (const C*)nullptr, uj, c->n,
+                                                  c->nnzb, s, o->spmm_variant, st, "precond");
         else
             sst = spmm_launch<CZ, C, C, 0, true>(nullptr, nullptr, Pinv, rho, (const C*)nullptr, uj, c->n, c->n, s,
                                                  -1, st, "precond");
@@ -2098,6 +2179,13 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         chaff_status ck = cluster_check_table(c, Pinv, st);
         if (ck != CHAFF_OK) return ck;
     }
+    if (o->precond == CHAFF_PRECOND_NBHD) {   // from here on Pinv points at M's blocks (Z's pattern)
+        if (NB != 7) return fail(CHAFF_EINVAL, "the neighbourhood-inverse preconditioner needs wires of 8 segments");
+        int size = 0;
+        chaff_status ck = nbhd_check(c, (chaff_prec)o->prec, Pinv, &size, st);
+        if (ck != CHAFF_OK) return ck;
+        Pinv = reinterpret_cast<const CZ*>(reinterpret_cast<const char*>(Pinv) + nbhd_blocks_offset(c->n, size));
+    }
     const int64_t rows = sh.rows, vs = rows * s, nsys = sh.nsys;
     C* V = static_cast<C*>(L.V);
     C* W = static_cast<C*>(L.W);
@@ -2147,6 +2235,12 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     if (o->use_x0 == 1) {
         hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)Xout,
                            (const int32_t*)c->perm, c->n, s, L.x, 0);
+    } else if (o->use_x0 == 2 && o->precond == CHAFF_PRECOND_NBHD) {
+        // neighbourhood-inverse guess x0 = M u (FP64 vectors, stored blocks on Z's pattern)
+        sst0 = spmm_launch<CZ, c128, c128, 0, false>(c->row_ptr, c->col_idx, Pinv, (const c128*)L.b,
+                                                     (const c128*)nullptr, L.x, c->n, c->nnzb, s, -1, st,
+                                                     "guess_nbhd");
+        if (sst0 != CHAFF_OK) return sst0;
     } else if (o->use_x0 == 2 && o->precond == CHAFF_PRECOND_CLUSTER) {
         // cluster guess x0 = M u (FP64 vectors, stored blocks)
         sst0 = cluster_apply_launch(c, (chaff_prec)o->prec, Pinv, L.b, true, L.x, true, false, s, st,
@@ -2262,6 +2356,9 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
             if (o->precond == CHAFF_PRECOND_CLUSTER)
                 sst = cluster_apply_launch(c, (chaff_prec)o->prec, Pinv, vj, sizeof(C) == 16, T, sizeof(C) == 16,
                                            false, s, st, "precond");
+            else if (o->precond == CHAFF_PRECOND_NBHD)
+                sst = spmm_launch<CZ, C, C, 0, false>(c->row_ptr, c->col_idx, Pinv, vj, (const C*)nullptr, T, c->n,
+                                                      c->nnzb, s, o->spmm_variant, st, "precond");
             else
                 sst = spmm_launch<CZ, C, C, 0, true>(nullptr, nullptr, Pinv, vj, (const C*)nullptr, T, c->n, c->n, s,
                                                      -1, st, "precond");
@@ -2336,6 +2433,9 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         if (o->precond == CHAFF_PRECOND_CLUSTER)
             sst = cluster_apply_launch(c, (chaff_prec)o->prec, Pinv, T, sizeof(C) == 16, L.x, true, true, s, st,
                                        "precond_update_fp64");
+        else if (o->precond == CHAFF_PRECOND_NBHD)
+            sst = spmm_launch<CZ, C, c128, 2, false>(c->row_ptr, c->col_idx, Pinv, T, (const c128*)nullptr, L.x,
+                                                     c->n, c->nnzb, s, -1, st, "precond_update_fp64");
         else
             sst = spmm_launch<CZ, C, c128, 2, true>(nullptr, nullptr, Pinv, T, (const c128*)nullptr, L.x, c->n, c->n,
                                                     s, -1, st, "precond_update_fp64");

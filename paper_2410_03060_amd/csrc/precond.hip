@@ -366,4 +366,302 @@ chaff_status cluster_apply_public(Cloud* c, chaff_prec prec, const void* M, cons
     return cluster_apply_launch(c, prec, M, X, w, Y, w, false, s, st, "cluster_apply");
 }
 
+
+// ==================================================================== neighbourhood inverse
+//
+// Design (gfx950):
+//  * selection: one lane per wire walks its row of the pattern (all near-set
+//    neighbours) and keeps the size - 1 nearest in a sorted register list
+//    (FP64 squared centroid distance formed as in the near-set test, ties to
+//    the lower caller index);
+//  * build: one wave per wire.  Lane r owns row r of the local system
+//    [A | E] (A the neighbourhood's 7 m x 7 m submatrix of Z padded to
+//    7 KM rows with the identity, E the wire's own 7 unit columns) in FP32
+//    registers; Gauss-Jordan with partial pivoting: the pivot row is chosen
+//    by a wave reduction over the unused rows, normalised by its lane, and
+//    broadcast column by column with readlane, so no row is ever moved.  The
+//    pivot row of unknown u ends holding row u of A^-1 E, i.e. column u of
+//    p's row block of A^-1 (A is complex symmetric), which is written at the
+//    block position of (p, member) in Z's pattern;
+//  * symmetrisation: one wave per unique pair (and per diagonal block), lane
+//    = block entry: M_pq = (raw_pq + raw_qp^T) / 2, M_qp = M_pq^T.
+size_t nbhd_table_bytes(int64_t n, int size) { return align_up((size_t)n * size * sizeof(int32_t), 256); }
+
+size_t nbhd_buffer_bytes(const Cloud* c, chaff_prec prec, int size) {
+    return nbhd_blocks_offset(c->n, size) + (size_t)c->nnzb * NB2 * (prec == CHAFF_C64 ? sizeof(c64) : sizeof(c128));
+}
+
+namespace {
+
+constexpr int NBH_WAVES = 4;
+
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* __restrict__ a, int64_t n) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        a[t] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_nbhd_select(int64_t n, int size, const Wire* __restrict__ wires,
+                                                     const int32_t* __restrict__ perm,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col_idx, int32_t* __restrict__ nbt) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    constexpr int L = NBH_MAX - 1;
+    double bd[L];
+    int32_t bk[L], bj[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        bd[t] = INFINITY;
+        bk[t] = 0x7fffffff;
+        bj[t] = -1;
+    }
+    const Wire wi = wires[i];
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        const int32_t j = col_idx[e];
+        if (j == i) continue;
+        const Wire& wj = wires[j];
+        const double dx = wj.cx - wi.cx;
+        const double dy = wj.cy - wi.cy;
+        const double dz = wj.cz - wi.cz;
+        const double xx = dx * dx;
+        const double yy = dy * dy;
+        const double zz = dz * dz;
+        double d2 = xx + yy;
+        d2 = d2 + zz;
+        double cd = d2;
+        int32_t ck = perm[j], cj = j;
+        // one insertion pass: the list stays sorted by (distance, caller index)
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            const bool lt = cd < bd[t] || (cd == bd[t] && ck < bk[t]);
+            const double td = bd[t];
+            const int32_t tk = bk[t], tj = bj[t];
+            bd[t] = lt ? cd : td;
+            bk[t] = lt ? ck : tk;
+            bj[t] = lt ? cj : tj;
+            cd = lt ? td : cd;
+            ck = lt ? tk : ck;
+            cj = lt ? tj : cj;
+        }
+    }
+    int32_t* out = nbt + i * size;
+    out[0] = (int32_t)i;
+#pragma unroll
+    for (int t = 0; t < L; ++t)
+        if (t + 1 < size) out[t + 1] = bj[t];
+}
+
+template <typename CZ, int KM>
+__global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int size, const int32_t* __restrict__ nbt,
+                                                               const int64_t* __restrict__ row_ptr,
+                                                               const int32_t* __restrict__ col_idx,
+                                                               const CZ* __restrict__ Z, CZ* __restrict__ M,
+                                                               int32_t* __restrict__ status) {
+    constexpr int NR = NB * KM;   // rows of the padded local system
+    constexpr int NC = NR + NB;   // its columns and the wire's own unit vectors
+    static_assert(NR <= 64 && KM * KM <= 64, "one lane per row and per block of the local system");
+    __shared__ int64_t pos_s[NBH_WAVES][KM * KM];
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t i = (int64_t)blockIdx.x * NBH_WAVES + w;
+    if (i >= n) return;   // wave-uniform; the waves of a workgroup never wait for each other
+    int32_t mem[KM];
+    int m = 0;
+#pragma unroll
+    for (int s = 0; s < KM; ++s) {
+        mem[s] = s < size ? nbt[i * size + s] : -1;
+        m += mem[s] >= 0 ? 1 : 0;
+    }
+    // block position of (member a, member b) in Z's pattern, -1 if the pair is not near
+    if (lane < KM * KM) {
+        const int a = lane / KM, b = lane % KM;
+        int64_t p = -1;
+        if (a < m && b < m) {
+            const int32_t row = mem[a], target = mem[b];
+            for (int64_t e = row_ptr[row]; e < row_ptr[row + 1]; ++e)
+                if (col_idx[e] == target) p = e;
+        }
+        pos_s[w][lane] = p;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    const int ra = lane / NB, rq = lane % NB;
+    c64 A[NC];
+#pragma unroll
+    for (int b = 0; b < KM; ++b) {
+        int64_t p = -1;
+        if (lane < NR && ra < m && b < m) p = pos_s[w][ra * KM + b];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int col = NB * b + c;
+            c64 v = {0.f, 0.f};
+            if (p >= 0)
+                v = ccast<c64>(Z[p * NB2 + rq * NB + c]);
+            else if (lane < NR && ra >= m && lane == col)
+                v = c64{1.f, 0.f};   // padding rows and columns: the identity
+            A[col] = v;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) A[NR + c] = c64{lane == c ? 1.f : 0.f, 0.f};
+
+    bool used = lane >= NR;
+    int my_u = -1;
+    bool bad = false;
+    for (int k = 0; k < NR; ++k) {
+        c64 v = A[0];
+#pragma unroll
+        for (int j = 1; j < NR; ++j)
+            if (j == k) v = A[j];
+        // pivot: the largest |a_rk| among rows not yet used, lowest row on ties (NaN counts as 0)
+        float mag = -1.f;
+        if (!used) {
+            mag = v.re * v.re + v.im * v.im;
+            if (!(mag >= 0.f)) mag = 0.f;
+        }
+        int idx = lane;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const float om = __shfl_xor(mag, off, 64);
+            const int oi = __shfl_xor(idx, off, 64);
+            if (om > mag || (om == mag && oi < idx)) {
+                mag = om;
+                idx = oi;
+            }
+        }
+        const int piv = __builtin_amdgcn_readfirstlane(idx);
+        const float pre = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.re), piv));
+        const float pim = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.im), piv));
+        const float d = pre * pre + pim * pim;
+        c64 inv = {0.f, 0.f};
+        if (d > 0.f && d < INFINITY) inv = c64{pre / d, -pim / d};
+        else bad = true;
+        if (lane == piv) {
+            used = true;
+            my_u = k;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) A[j] = cmul(A[j], inv);
+        }
+        const c64 l = (lane == piv || lane >= NR) ? c64{0.f, 0.f} : v;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const c64 pj = {__int_as_float(__builtin_amdgcn_readlane(__float_as_int(A[j].re), piv)),
+                            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(A[j].im), piv))};
+            A[j].re = fmaf(-l.re, pj.re, A[j].re);
+            A[j].re = fmaf(l.im, pj.im, A[j].re);
+            A[j].im = fmaf(-l.re, pj.im, A[j].im);
+            A[j].im = fmaf(-l.im, pj.re, A[j].im);
+        }
+    }
+    // the pivot row of unknown u holds row u of A^-1 E: raw_{p, mem[s]}[c][a] with u = 7 s + a
+    if (my_u >= 0) {
+        const int s = my_u / NB, a = my_u % NB;
+        if (s < m) {
+            const int64_t p = pos_s[w][s];   // (p, mem[s]) in row p
+#pragma unroll
+            for (int c = 0; c < NB; ++c) M[p * NB2 + c * NB + a] = ccast<CZ>(A[NR + c]);
+        }
+    }
+    if (bad && lane == 0) status[0] = 1;
+}
+
+template <typename CZ>
+__global__ __launch_bounds__(256) void k_nbhd_symm(int64_t n_pairs, const Pair* __restrict__ pairs, int64_t n,
+                                                   const int64_t* __restrict__ diag_pos, CZ* __restrict__ M) {
+    using R = typename real_of<CZ>::type;
+    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;   // one wave per unit
+    const int e = (int)(threadIdx.x & 63);
+    if (u >= n_pairs + n || e >= NB2) return;
+    const int r = e / NB, c = e % NB, et = c * NB + r;
+    if (u < n_pairs) {
+        const Pair pr = pairs[u];
+        const CZ a = M[pr.pos_ij * NB2 + e], b = M[pr.pos_ji * NB2 + et];
+        const CZ v = {(a.re + b.re) * (R)0.5, (a.im + b.im) * (R)0.5};
+        M[pr.pos_ij * NB2 + e] = v;    // M_pq[r][c]
+        M[pr.pos_ji * NB2 + et] = v;   // M_qp[c][r]
+    } else {
+        const int64_t p = diag_pos[u - n_pairs];
+        const CZ a = M[p * NB2 + e], b = M[p * NB2 + et];   // every lane reads before any writes (one wave)
+        M[p * NB2 + e] = CZ{(a.re + b.re) * (R)0.5, (a.im + b.im) * (R)0.5};
+    }
+}
+
+template <typename CZ>
+void nbhd_build_launch(Cloud* c, int size, const int32_t* nbt, const CZ* Z, CZ* M, hipStream_t st) {
+    const unsigned g = (unsigned)((c->n + NBH_WAVES - 1) / NBH_WAVES);
+    if (size <= 2)
+        hipLaunchKernelGGL((k_nbhd_build<CZ, 2>), dim3(g), dim3(64 * NBH_WAVES), 0, st, c->n, size, nbt,
+                           (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, Z, M, c->d_status);
+    else if (size <= 4)
+        hipLaunchKernelGGL((k_nbhd_build<CZ, 4>), dim3(g), dim3(64 * NBH_WAVES), 0, st, c->n, size, nbt,
+                           (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, Z, M, c->d_status);
+    else
+        hipLaunchKernelGGL((k_nbhd_build<CZ, 8>), dim3(g), dim3(64 * NBH_WAVES), 0, st, c->n, size, nbt,
+                           (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, Z, M, c->d_status);
+}
+
+}  // namespace
+
+chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, void* M, hipStream_t st) {
+    if (size < 1 || size > NBH_MAX) return fail(CHAFF_EINVAL, "neighbourhood size must be in [1, 8]");
+    NbhdHeader h{};
+    h.magic = NBH_MAGIC;
+    h.n = c->n;
+    h.nnzb = c->nnzb;
+    h.size = size;
+    h.prec = (int32_t)prec;
+    CHAFF_HIP(hipMemcpyAsync(M, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    int32_t* nbt = reinterpret_cast<int32_t*>(static_cast<char*>(M) + NBH_HEADER);
+    char* vals = static_cast<char*>(M) + nbhd_blocks_offset(c->n, size);
+    if (c->n > 0) {
+        const size_t zb = prec == CHAFF_C64 ? sizeof(c64) : sizeof(c128);
+        const int64_t words = (int64_t)((size_t)c->nnzb * NB2 * zb / 4);
+        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0,
+                           st, (uint32_t*)vals, words);
+        hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, c->d_status);
+        hipLaunchKernelGGL(k_nbhd_select, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, st, c->n, size,
+                           (const Wire*)c->wires, (const int32_t*)c->perm, (const int64_t*)c->row_ptr,
+                           (const int32_t*)c->col_idx, nbt);
+        CHAFF_LAUNCH_CHECK();
+        {
+            const int km = size <= 2 ? 2 : size <= 4 ? 4 : 8;
+            const double nr = (double)NB * km;
+            ProfScope ps("nbhd_build", st, ProfWork{(double)c->nnzb * NB2 * zb, (double)c->n * nr * nr * (nr + NB) * 8.0});
+            if (prec == CHAFF_C64)
+                nbhd_build_launch<c64>(c, size, nbt, (const c64*)Z, (c64*)vals, st);
+            else
+                nbhd_build_launch<c128>(c, size, nbt, (const c128*)Z, (c128*)vals, st);
+            CHAFF_LAUNCH_CHECK();
+        }
+        const int64_t units = c->n_pairs + c->n;
+        const unsigned gs = (unsigned)((units * 64 + 255) / 256);
+        if (prec == CHAFF_C64)
+            hipLaunchKernelGGL((k_nbhd_symm<c64>), dim3(gs), dim3(256), 0, st, c->n_pairs, (const Pair*)c->pairs, c->n,
+                               (const int64_t*)c->diag_pos, (c64*)vals);
+        else
+            hipLaunchKernelGGL((k_nbhd_symm<c128>), dim3(gs), dim3(256), 0, st, c->n_pairs, (const Pair*)c->pairs, c->n,
+                               (const int64_t*)c->diag_pos, (c128*)vals);
+        CHAFF_LAUNCH_CHECK();
+    }
+    int32_t flag = 0;
+    if (c->n > 0) CHAFF_HIP(hipMemcpyAsync(&flag, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CHAFF_HIP(hipStreamSynchronize(st));   // also keeps the host header alive until copied
+    if (flag) return fail(CHAFF_ESINGULAR, "a neighbourhood system has a zero pivot");
+    return CHAFF_OK;
+}
+
+chaff_status nbhd_check(const Cloud* c, chaff_prec prec, const void* M, int* size, hipStream_t st) {
+    NbhdHeader h{};
+    CHAFF_HIP(hipMemcpyAsync(&h, M, sizeof(h), hipMemcpyDeviceToHost, st));
+    CHAFF_HIP(hipStreamSynchronize(st));
+    if (h.magic != NBH_MAGIC || h.n != c->n || h.nnzb != c->nnzb || h.prec != (int32_t)prec || h.size < 1 ||
+        h.size > NBH_MAX)
+        return fail(CHAFF_EINVAL, "the preconditioner buffer is not a neighbourhood-inverse preconditioner of this "
+                                  "cloud and precision (build it with chaff_nbhd_precond)");
+    *size = h.size;
+    return CHAFF_OK;
+}
+
 }  // namespace chaff

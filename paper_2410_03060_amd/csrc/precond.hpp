@@ -31,6 +31,30 @@ chaff_status cluster_check_table(const Cloud* c, const void* M, hipStream_t st);
 chaff_status cluster_apply_launch(const Cloud* c, chaff_prec prec, const void* M, const void* X, bool x64, void* Y,
                                   bool y64, bool accumulate, int64_t s, hipStream_t st, const char* prof_name);
 
+// ------------------------------------------------------------------ neighbourhood inverse
+// The block-diagonal preconditioner of Sec. II-B centred on every wire: wire
+// p's neighbourhood is p and its nearest near-set neighbours (at most `size`
+// wires); p's row of M is its row block of the inverse of the neighbourhood's
+// submatrix of Z, and M_pq = (W_p[p,q] + W_q[q,p]^T) / 2 keeps M complex
+// symmetric.  M is stored on Z's block pattern.
+constexpr int NBH_MAX = 8;                         // wires per neighbourhood at most
+constexpr size_t NBH_HEADER = 256;                 // bytes of the buffer header
+constexpr int64_t NBH_MAGIC = 0x3148424e46464843ll;   // "CHFFNBH1"
+struct NbhdHeader {
+    int64_t magic, n, nnzb;
+    int32_t size, prec;
+};
+// Buffer: header (256 B), [N][size] int32 neighbourhood table (internal
+// indices, slot 0 the wire itself, -1 unused) padded to 256 B, then
+// [nnzb][NB][NB] complex (prec) in Z's block order.
+size_t nbhd_table_bytes(int64_t n, int size);
+size_t nbhd_buffer_bytes(const Cloud* c, chaff_prec prec, int size);
+chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, void* M, hipStream_t st);
+// Host check of M's header against the cloud (host-synchronising); returns
+// the neighbourhood size through *size.
+chaff_status nbhd_check(const Cloud* c, chaff_prec prec, const void* M, int* size, hipStream_t st);
+inline size_t nbhd_blocks_offset(int64_t n, int size) { return NBH_HEADER + nbhd_table_bytes(n, size); }
+
 // Rows of one cluster product y = M x for the calling lane: rows
 // rho = rsub * RPT + j (j < RPT) of the 56 x 56 block, column col of the
 // LDS tile xs [56][ST].  The block comes from LDS (ms, row-major, when it was

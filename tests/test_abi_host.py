@@ -165,7 +165,7 @@ def test_solve_rejects_bad_initial_guess_mode(B):
 
 def test_solve_rejects_bad_preconditioner_and_reserved_field(B):
     L = B.lib()
-    o = B.solve_opts(precond=2)
+    o = B.solve_opts(precond=3)
     assert L.chaff_solve_workspace_bytes(C.c_void_p(0x1000), C.byref(o), 1) == 0
     assert "precond" in B.last_error()
     o = B.solve_opts()
@@ -226,3 +226,19 @@ def test_tuning_table_rejects_other_files(B, tmp_path):
     assert ei.value.status == B.EINVAL
     with pytest.raises(B.ChaffError):
         B.tune_load(str(tmp_path / "missing.json"))
+
+
+def test_nbhd_entry_points_validate_before_any_launch(B):
+    L = B.lib()
+    H = C.c_void_p(0x1000)          # never dereferenced: every call below fails validation
+    P = C.c_void_p(0x1000)
+    assert L.chaff_nbhd_precond_bytes(None, B.C64, 4) == 0
+    assert L.chaff_nbhd_precond_bytes(H, B.C64, 0) == 0
+    assert L.chaff_nbhd_precond_bytes(H, B.C64, 9) == 0
+    assert L.chaff_nbhd_precond(None, B.C64, 4, P, P, None) == B.EINVAL
+    assert L.chaff_nbhd_precond(H, 7, 4, P, P, None) == B.EINVAL
+    assert L.chaff_nbhd_precond(H, B.C64, 0, P, P, None) == B.EINVAL
+    assert "size" in B.last_error()
+    assert L.chaff_nbhd_precond(H, B.C64, 9, P, P, None) == B.EINVAL
+    assert L.chaff_nbhd_precond(H, B.C64, 4, P, C.c_void_p(0x1010), None) == B.EINVAL
+    assert "aligned" in B.last_error()

@@ -1,0 +1,195 @@
+"""GPU parity of the neighbourhood-inverse preconditioner (chaff_nbhd_precond)
+against the oracle's plain definition (oracle.precond.neighbourhoods /
+neighbourhood_inverse), and of solves that use it against the oracle's
+solution of the S-NFC system.
+
+* neighbourhood table: the library's (internal indices, mapped to caller
+  indices) equals the oracle's exactly, for several sizes, a ragged cloud and
+  several clouds with an empty one;
+* blocks: each block row of M within kappa * 3e-5 + 1e-6 (relative to the
+  oracle's block row) of the oracle's, kappa the largest condition number of
+  the neighbourhood systems that row draws on — the library solves them in
+  complex FP32 with partial pivoting (first-order perturbation of an
+  inverse); blocks outside every neighbourhood exactly zero; M exactly
+  symmetric; size 1 within the same bound of the block-Jacobi inverses;
+* solves: COCG (complex64 with FP64 refinement, and complex128), GMRES and
+  GCR with it reach the oracle's currents to 1e-4 (FP32) / 1e-10 (FP64) and
+  sigma to 0.1 dB, in fewer steps than with the block-diagonal
+  preconditioner.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mom, precond, solve as osolve
+from paper_2410_03060_amd import workloads as W
+from parity_util import say
+
+pytestmark = pytest.mark.gpu
+
+NB = 7
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_03060_amd import binding
+    binding.lib()
+    return binding
+
+
+def _clouds():
+    a = W.random_cloud(21, 120, box_lam=3.0, d_c_lam=1.0)
+    b = W.random_cloud(22, 37, box_lam=2.0, d_c_lam=1.0)
+    empty = W.random_cloud(23, 0, box_lam=2.0, d_c_lam=1.0)
+    c = W.random_cloud(24, 80, box_lam=2.5, d_c_lam=1.0)
+    return {"one": a, "multi": W.concat_clouds([b, empty, c])}
+
+
+def _mapped_table(B, cl, M, size):
+    row_ptr, col_idx, perm, _ = cl.pattern()
+    t = B.nbhd_table(cl, M, size).cpu().numpy().astype(np.int64)
+    out = [None] * cl.n
+    for i in range(cl.n):
+        g = t[i][t[i] >= 0]
+        out[int(perm[i])] = perm[g].astype(np.int64)
+    return out
+
+
+def _caller_blocks(B, cl, M, size, prec):
+    """{(p, q) caller pair: block} of the library's M (all stored blocks)."""
+    row_ptr, col_idx, perm, _ = cl.pattern()
+    V = B.nbhd_blocks(cl, M, size, prec).cpu().numpy().astype(np.complex128)
+    out = {}
+    for i in range(cl.n):
+        for e in range(int(row_ptr[i]), int(row_ptr[i + 1])):
+            out[(int(perm[i]), int(perm[col_idx[e]]))] = V[e]
+    return out
+
+
+@pytest.mark.parametrize("size", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("which", ["one", "multi"])
+def test_table_and_blocks(B, which, size):
+    cloud = _clouds()[which]
+    prec = B.C64
+    cl = B.build_cloud(cloud)
+    Z, P = B.fill_Z(cl, prec)
+    M = B.nbhd_precond(cl, Z, size, prec)
+    nb_o = precond.neighbourhoods(cloud, size)
+    nb_g = _mapped_table(B, cl, M, size)
+    for p in range(cloud.n):
+        assert np.array_equal(nb_g[p], nb_o[p]), (p, nb_g[p], nb_o[p])
+    Zs, _ = mom.snfc_matrix(cloud)
+    Mo = precond.neighbourhood_inverse(Zs, nb_o).tobsr(blocksize=(NB, NB))
+    ref = {}
+    for p in range(cloud.n):
+        for e in range(Mo.indptr[p], Mo.indptr[p + 1]):
+            ref[(p, int(Mo.indices[e]))] = Mo.data[e]
+    got = _caller_blocks(B, cl, M, size, prec)
+    Zc = Zs.tocsr()
+    kappa = np.zeros(cloud.n)
+    for p, g in enumerate(nb_o):
+        r = (NB * g[:, None] + np.arange(NB)[None, :]).reshape(-1)
+        kappa[p] = np.linalg.cond(Zc[r][:, r].toarray())
+    worst = 0.0
+    for p in range(cloud.n):
+        keys = [k for k in got if k[0] == p]
+        gr = np.concatenate([got[k] for k in keys], axis=1)
+        orow = np.concatenate([ref.get(k, np.zeros((NB, NB))) for k in keys], axis=1)
+        for k in keys:
+            if k not in ref:
+                assert np.all(got[k] == 0), k          # outside every neighbourhood: zero
+        kap = max([kappa[p]] + [kappa[q] for (_, q) in keys if (q, p) in ref or (p, q) in ref])
+        err = np.linalg.norm(gr - orow) / np.linalg.norm(orow)
+        worst = max(worst, err / (3e-5 * kap + 1e-6))
+    # exact symmetry of the stored matrix
+    for (p, q), v in got.items():
+        assert np.array_equal(v, got[(q, p)].T)
+    say(f"[nbhd] {which} size {size}: N={cloud.n}, block rows err / bound max {worst:.3f}")
+    assert worst <= 1.0
+    if size == 1:   # the block-diagonal preconditioner
+        Pg = P.cpu().numpy().astype(np.complex128)
+        row_ptr, col_idx, perm, _ = cl.pattern()
+        for i in range(cl.n):
+            d = got[(int(perm[i]), int(perm[i]))]
+            assert np.linalg.norm(d - Pg[i]) <= (3e-5 * kappa[int(perm[i])] + 1e-6) * np.linalg.norm(Pg[i])
+
+
+def _solve_case(B, cloud, prec, method, size, use_x0=0):
+    inc = W.azimuth_incidences(5)
+    cl = B.build_cloud(cloud)
+    Z, P = B.fill_Z(cl, prec)
+    M = B.nbhd_precond(cl, Z, size, prec)
+    kw = dict(tol=1e-6 if prec == B.C64 else 1e-11, method=method, prec=prec, use_x0=use_x0,
+              restart=500 if method in (B.COCG, B.COCG_RR) else 30,
+              inner_tol=1e-4 if prec == B.C64 else 1e-12, max_cycles=60)
+    X, info = B.solve(cl, Z, M, inc.k_hat, inc.e_hat, B.solve_opts(precond=B.PRECOND_NBHD, **kw))
+    Xb, info_b = B.solve(cl, Z, P, inc.k_hat, inc.e_hat, B.solve_opts(precond=B.PRECOND_BLOCK, **kw))
+    sig = B.rcs(cl, X, -inc.k_hat, inc.e_hat, monostatic=True).cpu().numpy()
+    Zs, _ = mom.snfc_matrix(cloud)
+    u = mom.excitation(cloud, inc.k_hat, inc.e_hat)
+    xo = osolve.sparse_solve(Zs, u)
+    so = mom.monostatic_rcs(cloud, xo, inc.k_hat, inc.e_hat)
+    xg = X.cpu().numpy()
+    cerr = float(np.max(np.linalg.norm(xg - xo, axis=0) / np.linalg.norm(xo, axis=0)))
+    live = so > 0
+    db = float(np.max(np.abs(10 * np.log10(sig[:, live] / so[live])))) if live.any() else 0.0
+    return info, info_b, cerr, db
+
+
+@pytest.mark.parametrize("method", ["cocg", "cocg_rr", "gmres", "gcr"])
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_solves_reach_the_oracle(B, method, prec):
+    cloud = W.random_cloud(31, 400, box_lam=4.0, d_c_lam=1.0)
+    m = {"cocg": B.COCG, "cocg_rr": B.COCG_RR, "gmres": B.GMRES, "gcr": B.GCR}[method]
+    p = B.C64 if prec == "c64" else B.C128
+    info, info_b, cerr, db = _solve_case(B, cloud, p, m, 6)
+    say(f"[nbhd] {method} {prec}: {info['iterations']} steps (block-Jacobi {info_b['iterations']}), "
+        f"residual {info['max_rel_residual']:.1e}, current err {cerr:.2e}, rcs {db:.2e} dB")
+    tol_c = 1e-4 if p == B.C64 else 1e-10
+    assert cerr <= tol_c and db <= (0.1 if p == B.C64 else 1e-6)
+    assert info["iterations"] < info_b["iterations"]
+
+
+def test_multi_cloud_guess_and_compaction(B):
+    # several clouds with an empty one, preconditioner guess, 40 RHS (column compaction)
+    clouds = _clouds()["multi"]
+    inc = W.azimuth_incidences(40)
+    cl = B.build_cloud(clouds)
+    Z, _ = B.fill_Z(cl, B.C64, with_pinv=False)
+    M = B.nbhd_precond(cl, Z, 4, B.C64)
+    X, info = B.solve(cl, Z, M, inc.k_hat, inc.e_hat,
+                      B.solve_opts(tol=1e-6, method=B.COCG, restart=500, inner_tol=1e-4, use_x0=2,
+                                   precond=B.PRECOND_NBHD))
+    Zs, _ = mom.snfc_matrix(clouds)
+    xo = osolve.sparse_solve(Zs, mom.excitation(clouds, inc.k_hat, inc.e_hat))
+    err = np.linalg.norm(X.cpu().numpy() - xo, axis=0) / np.linalg.norm(xo, axis=0)
+    say(f"[nbhd] multi-cloud 40 RHS: {info['iterations']} steps, current err {err.max():.2e}")
+    assert err.max() <= 1e-4
+
+
+def test_other_buffers_are_rejected(B):
+    import torch
+    cloud = W.random_cloud(41, 60, box_lam=2.0, d_c_lam=1.0)
+    inc = W.azimuth_incidences(2)
+    cl = B.build_cloud(cloud)
+    Z, P = B.fill_Z(cl, B.C64)
+    Mc = B.cluster_precond(cl, Z, B.C64)
+    with pytest.raises(B.ChaffError):
+        B.solve(cl, Z, Mc, inc.k_hat, inc.e_hat, B.solve_opts(method=B.COCG, precond=B.PRECOND_NBHD, restart=200))
+    M = B.nbhd_precond(cl, Z, 4, B.C64)
+    Z128, _ = B.fill_Z(cl, B.C128)
+    with pytest.raises(B.ChaffError):   # built for complex64, used with complex128
+        B.solve(cl, Z128, M, inc.k_hat, inc.e_hat,
+                B.solve_opts(method=B.COCG, precond=B.PRECOND_NBHD, prec=B.C128, restart=200))
+    with pytest.raises(B.ChaffError):
+        B.nbhd_precond(cl, Z, 9, B.C64)
+    c20 = W.random_cloud(42, 20, box_lam=2.0, d_c_lam=1.0, n_seg=20)
+    cl20 = B.build_cloud(c20)
+    Z20, _ = B.fill_Z(cl20, B.C64)
+    with pytest.raises(B.ChaffError):
+        B.nbhd_precond(cl20, Z20, 4, B.C64)
+    torch.cuda.synchronize()
