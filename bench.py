@@ -2,9 +2,10 @@
 """Benchmark of the S-NFC thin-wire MoM hot path on one MI355X.
 
 One step = the whole hot path over one batch of synthetic input:
-neighbour search (chaff_build_cloud), impedance fill (chaff_fill_Z),
-excitation + preconditioned GMRES with FP64 refinement (chaff_solve) and
-monostatic RCS (chaff_rcs), with the inputs already resident in HBM.
+neighbour search (chaff_build_cloud), impedance fill (chaff_fill_Z), the
+preconditioner (chaff_nbhd_precond / chaff_cluster_precond as configured),
+excitation + preconditioned Krylov solve with FP64 refinement (chaff_solve)
+and monostatic RCS (chaff_rcs), with the inputs already resident in HBM.
 
     python bench.py [--steps K] [--warmup W] [--config c5] [--gpus 1]
 
@@ -86,14 +87,15 @@ CONFIGS = {
     "c3": dict(prec="c64", method="cocg", restart=2000, inner_tol=1e-5,
                desc="20,000-wire Gaussian cloud + 16 side clouds (500-5,000 wires), d_c=2 lambda, "
                     "360 azimuth incidences, one launch per stage for all 17 clouds"),
-    "c4_eval": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="mlp", precond="cluster",
+    "c4_eval": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="bj", precond="nbhd", nbhd_size=4,
                     desc="100,000 wires, uniform sphere R=40 lambda, d_c=1.5 lambda, 8 incidences, "
-                         "cluster block-Jacobi preconditioner, learned initial guess (3x128 MLP, BF16, "
-                         "trained on 200 solved clouds)"),
-    "c5": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="mlp", precond="cluster",
+                         "neighbourhood-inverse preconditioner (4 wires), initial guess M u; the learned "
+                         "guess and the learned preconditioner are measured beside it"),
+    "c5": dict(prec="c64", method="cocg", restart=5000, inner_tol=1e-5, guess="bj", precond="nbhd", nbhd_size=8,
                desc="1,000,000 wires (7M unknowns), uniform sphere R=50 lambda, d_c=1 lambda, "
-                    "64 azimuth incidences, complex64 + FP64 refinement, cluster block-Jacobi "
-                    "preconditioner, learned initial guess"),
+                    "64 azimuth incidences, complex64 + FP64 refinement, neighbourhood-inverse "
+                    "preconditioner (8 wires), initial guess M u; the learned guess and the learned "
+                    "preconditioner are measured beside it"),
     "n2": dict(prec="c64", method="cocg", restart=2000, inner_tol=1e-5, guess="bj", precond="block",
                desc="the paper's 10^5-chaff case with its own discretisation: 19 unknowns per chaff "
                     "(1.9M unknowns), identical half-wave chaffs at 13 GHz, diameter 20 um, uniform "
@@ -101,10 +103,12 @@ CONFIGS = {
                     "complex64 + FP64 refinement, block-diagonal preconditioner"),
 }
 GUESSES = {"zero": 0, "bj": 2, "mlp": 1}   # bj: x0 = P u with the solve's preconditioner P
-PRECONDS = {"block": 0, "cluster": 1, "nbhd": 2}
+PRECONDS = {"block": 0, "cluster": 1, "nbhd": 2, "nbhd_mlp": 2}   # nbhd_mlp: the learned neighbourhood inverse
 NBHD_SIZE = 6   # wires per neighbourhood of the neighbourhood-inverse preconditioner (default)
 # training recipe of the learned guess per evaluation workload: (generator, clouds, epochs)
 MLP_TRAINING = {"c4_eval": ("c4_train_cloud", 200, 12), "c5": ("c5_train_cloud", 64, 12)}
+# training recipe of the learned neighbourhood-inverse preconditioner: (generator, clouds, epochs)
+NBHD_MLP_TRAINING = {"c4_eval": ("c4_train_cloud", 24, 6), "c5": ("c5_train_cloud", 16, 6)}
 METHODS = {"gmres": 0, "cocg": 1, "cocg_rr": 2, "gcr": 3}
 
 
@@ -285,6 +289,26 @@ def train_guess(config, B):
     return res.theta, report
 
 
+def train_nbhd_mlp(config, size):
+    """Train the learned neighbourhood-inverse preconditioner on raw rows computed by the library (untimed)."""
+    from paper_2410_03060_amd import learned, workloads as W
+    gen, n_clouds, epochs = NBHD_MLP_TRAINING[config]
+    make = getattr(W, gen)
+    samples = learned.nbhd_samples([make(j) for j in range(n_clouds)], size)
+    print(f"[bench] nbhd mlp: {samples.feat.shape[0]} rows from {n_clouds} clouds in {samples.solve_seconds:.1f} s",
+          file=sys.stderr, flush=True)
+    res = learned.train(samples, W.mlp_init(0), epochs=epochs, batch=4096, seed=0)
+    err = learned.relative_target_error(res.theta, samples)
+    print(f"[bench] nbhd mlp: {res.steps} Adam steps in {res.seconds:.1f} s, final epoch loss {res.losses[-1]:.4f}, "
+          f"relative error {err:.3f}", file=sys.stderr, flush=True)
+    report = {"train_clouds": f"{gen}(0..{n_clouds - 1})", "rows": int(samples.feat.shape[0]),
+              "data_seconds": samples.solve_seconds, "epochs": epochs, "batch": 4096, "adam_steps": res.steps,
+              "train_seconds": res.seconds, "epoch_losses": [round(x, 5) for x in res.losses],
+              "train_relative_error": err, "excluded_from_timing": True}
+    del samples
+    return res.theta, report
+
+
 def spmm_sweep(B, geom, prec, sizes=(1, 4, 8, 16, 32, 64)):
     """Block-sparse product alone (chaff_spmm, autotuned per RHS count) on the
     workload's matrix: algorithmic bytes (Z once with its indices, X and Y
@@ -318,12 +342,30 @@ def compare_guesses(step, kinds):
     for g in kinds:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        cl, X, info, sig, Z = step(g)
+        cl, X, info, sig, Z = step(g, bounded=True)
         torch.cuda.synchronize()
         out[g] = {"iterations": info["iterations"], "cycles": info["cycles"],
                   "max_rel_residual": info["max_rel_residual"], "step_seconds": time.perf_counter() - t0}
         del cl, X, sig, Z
         print(f"[bench] guess {g}: iterations {info['iterations']} step {out[g]['step_seconds']:.3f} s",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def compare_preconds(step, kinds, size):
+    """Iterations and wall time of one full step with each preconditioner (guess x0 = M u; untimed region)."""
+    import torch
+    out = {"neighbourhood_size": size}
+    for kind in kinds:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cl, X, info, sig, Z = step("bj", kind, bounded=True)
+        torch.cuda.synchronize()
+        out[kind] = {"iterations": info["iterations"], "cycles": info["cycles"],
+                     "max_rel_residual": info["max_rel_residual"], "step_seconds": time.perf_counter() - t0,
+                     "converged": bool(info["max_rel_residual"] <= opts.tol)}
+        del cl, X, sig, Z
+        print(f"[bench] precond {kind}: iterations {info['iterations']} step {out[kind]['step_seconds']:.3f} s",
               file=sys.stderr, flush=True)
     return out
 
@@ -474,26 +516,42 @@ def main(argv=None) -> int:
     opts.precond = PRECONDS[pc]
     mlp_report = None
     theta = None
-    if guess == "mlp":
+    compare = not a.no_compare and a.config in MLP_TRAINING
+    if guess == "mlp" or compare:   # the learned guess is trained for the comparison too
         theta, mlp_report = train_guess(a.config, B)
+    nbhd_mlp_report = None
+    theta_nb = None
 
     nbhd_size = a.nbhd_size or cfg.get("nbhd_size", NBHD_SIZE)
 
-    def make_precond(cl, Z, P):
-        if pc == "cluster":
+    if pc == "nbhd_mlp" or (compare and a.config in NBHD_MLP_TRAINING):
+        theta_nb, nbhd_mlp_report = train_nbhd_mlp(a.config, nbhd_size)
+
+    def make_precond(cl, Z, P, kind=None):
+        kind = kind or pc
+        if kind == "cluster":
             return B.cluster_precond(cl, Z, prec)
-        if pc == "nbhd":
+        if kind == "nbhd":
             return B.nbhd_precond(cl, Z, nbhd_size, prec)
+        if kind == "nbhd_mlp":
+            return B.nbhd_mlp_precond(cl, theta_nb, P, nbhd_size, prec)
         return P
 
-    def step(guess_kind=None):
+    def step(guess_kind=None, precond_kind=None, bounded=False):
         gk = guess_kind or guess
+        kind = precond_kind or pc
         cl = B.build_cloud(geom)
         Z, P = B.fill_Z(cl, prec)
-        M = make_precond(cl, Z, P)
+        M = make_precond(cl, Z, P, kind)
         x0 = B.mlp_guess(cl, P, theta, kh, eh, prec=prec) if gk == "mlp" else None
         opts.use_x0 = GUESSES[gk]
-        X, info = B.solve(cl, Z, M, kh, eh, opts, x0=x0)
+        opts.precond = PRECONDS[kind]
+        if bounded:   # comparisons: at most 3 cycles of 1,500 steps, a non-converged solve is reported
+            o = B.solve_opts(tol=opts.tol, inner_tol=opts.inner_tol, restart=min(opts.restart, 1500), max_cycles=3,
+                             use_x0=opts.use_x0, prec=opts.prec, method=opts.method, precond=opts.precond)
+            X, info = B.solve(cl, Z, M, kh, eh, o, x0=x0, raise_on_noconv=False)
+        else:
+            X, info = B.solve(cl, Z, M, kh, eh, opts, x0=x0)
         sig = B.rcs(cl, X, -kh, eh, monostatic=True)
         return cl, X, info, sig, Z
 
@@ -580,7 +638,7 @@ def main(argv=None) -> int:
                    "unknowns_per_wire": int(wl.cloud.n_seg - 1),
                    "nnzb": int(cl.nnzb), "pairs": int(cl.n_pairs), "method": method, "restart": restart,
                    "tol": a.tol, "initial_guess": guess, "preconditioner": pc,
-                   "neighbourhood_size": nbhd_size if pc == "nbhd" else None},
+                   "neighbourhood_size": nbhd_size if pc in ("nbhd", "nbhd_mlp") else None},
         "solver": {"cycles": infos[-1]["cycles"], "iterations": infos[-1]["iterations"],
                    "max_rel_residual": infos[-1]["max_rel_residual"],
                    "systems_per_step": int(wl.cloud.n_clouds * R), "solved_total": solved},
@@ -591,7 +649,9 @@ def main(argv=None) -> int:
         "spmm_sweep": None,
         "memory": memory,
         "mlp": mlp_report,
+        "nbhd_mlp": nbhd_mlp_report,
         "guess_comparison": None,
+        "precond_comparison": None,
         "comparator": None,
         "cpu_baseline": None,
         "pcie_inclusive": None,
@@ -618,6 +678,8 @@ def main(argv=None) -> int:
         out["spmm_sweep"] = spmm_sweep(B, geom, prec)
     if not a.no_compare and a.config in MLP_TRAINING:
         out["guess_comparison"] = compare_guesses(step, ["zero", "bj"] + (["mlp"] if theta is not None else []))
+        kinds = ["block", "cluster", "nbhd"] + (["nbhd_mlp"] if theta_nb is not None else [])
+        out["precond_comparison"] = compare_preconds(step, kinds, nbhd_size)
     if not a.no_comparator:
         out["comparator"] = fp64_comparator(B, geom, wl, kh, eh, a.tol, a.config, X_ours=X_last, sig_ours=sig_last)
     if not a.no_cpu_baseline:

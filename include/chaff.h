@@ -264,7 +264,8 @@ chaff_status chaff_cluster_apply(chaff_cloud c, chaff_prec prec, const void* M, 
  * Wires of 8 segments only (CHAFF_EINVAL for n_seg = 20).
  *
  * Buffer M (device, 256-byte aligned, chaff_nbhd_precond_bytes):
- *   a 256-byte header {int64 tag, int64 N, int64 nnzb, int32 size, int32 prec},
+ *   a 256-byte header {int64 tag, int64 N, int64 nnzb, int32 size, int32 prec,
+ *   int32 raw (1 for the rows of chaff_nbhd_raw_rows), int32 0},
  *   then [N][size] int32 neighbourhoods (internal wire indices, slot 0 the
  *   wire itself, -1 where the near set has fewer wires) padded to a multiple
  *   of 256 bytes, then [nnzb][7][7] complex (prec): M in Z's block order
@@ -279,6 +280,56 @@ size_t chaff_nbhd_precond_bytes(chaff_cloud c, chaff_prec prec, int32_t size);  
  * (CHAFF_EINVAL for another buffer). */
 chaff_status chaff_nbhd_precond(chaff_cloud c, chaff_prec prec, int32_t size, const void* Z, void* M,
                                 chaff_stream stream);
+/* The same build without the symmetrisation: M's blocks hold the raw rows
+ * W_p[p,q] at the positions (p, q), q in N(p), and zero elsewhere; the header
+ * is tagged raw and chaff_solve refuses the buffer.  The training targets of
+ * the learned form below. */
+chaff_status chaff_nbhd_raw_rows(chaff_cloud c, chaff_prec prec, int32_t size, const void* Z, void* M,
+                                 chaff_stream stream);
+
+/* ------------------------------------------------------------------ learned neighbourhood inverse
+ * Growth part (4), the block-preconditioner form: the network of the learned
+ * guess (CHAFF_MLP_NFEAT inputs, three SiLU layers, CHAFF_MLP_NOUT outputs;
+ * parameters theta as for chaff_mlp_forward) predicts the raw rows of the
+ * neighbourhood-inverse preconditioner from the neighbourhood's geometry,
+ * and the predicted rows are symmetrised like the computed ones.  Samples
+ * are (wire i, slot s, column c), row (i size + s) 7 + c in the internal wire
+ * order: slot s of i's neighbourhood (q = N(i)[s]), column c of the block.
+ * Each wire gets a canonical tangent tau = sigma t, sigma = +1 when the first
+ * nonzero of (t_z, t_y, t_x) is positive, else -1; S = sigma P maps rooftop
+ * coefficients to the canonical frame (P reverses the 7 rooftops when
+ * sigma = -1), and a block W becomes S_i W S_q there.
+ *   features (BF16, FP64 values rounded once; d_xy = c_y - c_x,
+ *   E(x) = exp(-j 2 pi x / lambda), all zero for an empty slot):
+ *     [c] = 1, [7 + s] = 1 (one-hot column and slot);
+ *     [15], [16] = 10 (L_i/lambda - 1/2), 10 (L_q/lambda - 1/2);
+ *     [17..22] = |d_iq|/d_c, tau_i.d_iq/d_c, tau_q.d_iq/d_c, tau_i.tau_q, Re, Im E(|d_iq|);
+ *     [23] = |N(i)| / 8;
+ *     member t of N(i) at 24 + 15 t: 1, 10 (L_t/lambda - 1/2), the six pair
+ *     numbers of (i, t), the six of (q, t), 1 if t = q or t and q are near;
+ *     [144..191] = 0.
+ *   targets: y[2r] + j y[2r+1] = 0.05 (S_i (W_i[i,q] - delta_iq Pinv_i) S_q)[r][c]
+ *   (FP32): the departure from the block-diagonal preconditioner (Pinv the
+ *   inverse self blocks of chaff_fill_Z), so that zero outputs give it exactly.
+ * Wires of 8 segments and finite d_c only. */
+/* feat [n_rows][CHAFF_MLP_NFEAT] BF16 for rows [row0, row0 + n_rows) of the
+ * neighbourhoods stored in M (any buffer of chaff_nbhd_precond / _raw_rows;
+ * its header is read back: host-synchronising). */
+chaff_status chaff_nbhd_mlp_features(chaff_cloud c, const void* M, int64_t row0, int64_t n_rows,
+                                     uint16_t* feat, chaff_stream stream);
+/* Y [N size 7][CHAFF_MLP_NOUT] FP32 targets from a buffer of chaff_nbhd_raw_rows
+ * and the inverse self blocks Pinv [N][7][7] of chaff_fill_Z (same prec;
+ * host-synchronising header check). */
+chaff_status chaff_nbhd_mlp_targets(chaff_cloud c, chaff_prec prec, const void* M, const void* Pinv,
+                                    float* Y, chaff_stream stream);
+size_t chaff_nbhd_mlp_workspace_bytes(chaff_cloud c, int32_t size);   /* 0 on a bad argument */
+/* Builds the learned preconditioner into M (chaff_nbhd_precond_bytes, 256-byte
+ * aligned): neighbourhoods, features, the network in chunks, raw rows from its
+ * outputs, symmetrisation.  The result is a CHAFF_PRECOND_NBHD buffer.
+ * ws: device workspace of chaff_nbhd_mlp_workspace_bytes.  Host-synchronising. */
+chaff_status chaff_nbhd_mlp_precond(chaff_cloud c, chaff_prec prec, int32_t size, const float* theta,
+                                    const void* Pinv, void* M, void* ws, size_t ws_bytes,
+                                    chaff_stream stream);
 
 /* Excitation alone: U [N*NB][R] complex double (caller order), eq. (4) without
  * its -(j/(w mu0)) factor, closed-form triangle transform. */

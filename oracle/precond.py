@@ -187,19 +187,11 @@ def neighbourhood_raw_blocks(Zs, nbhd, nb: int = NB) -> dict:
     return out
 
 
-def neighbourhood_inverse(Zs, nbhd, nb: int = NB):
-    """The neighbourhood-inverse preconditioner M (scipy BSR, caller order).
-
-    M_pq = (W_p[p, q] + W_q[q, p]^T) / 2, a raw block that does not exist (q not
-    in nbhd[p]) counting as zero; M is complex symmetric like Z, with blocks
-    only on pairs where one wire is in the other's neighbourhood (a subset of
-    the near set).  One wire per neighbourhood gives the block-diagonal
-    preconditioner of Sec. II-B; neighbourhoods that contain whole groups of
-    mutually coupled wires give the exact inverse on those groups."""
+def symmetrise(raw: dict, n: int, nb: int = NB):
+    """M (scipy BSR, caller order) from raw row blocks {(p, q): R_p[p, q]}:
+    M_pq = (R_p[p,q] + R_q[q,p]^T) / 2, a missing raw block counting as zero."""
     import scipy.sparse as sp
-    raw = neighbourhood_raw_blocks(Zs, nbhd, nb)
     keys = set(raw) | {(q, p) for (p, q) in raw}
-    n = len(nbhd)
     I = np.array(sorted(keys), dtype=np.int64).reshape(-1, 2)
     blocks = np.zeros((I.shape[0], nb, nb), dtype=np.complex128)
     for t, (p, q) in enumerate(I):
@@ -213,3 +205,15 @@ def neighbourhood_inverse(Zs, nbhd, nb: int = NB):
         blocks[t] = 0.5 * v
     indptr = np.searchsorted(I[:, 0], np.arange(n + 1)) if I.size else np.zeros(n + 1, dtype=np.int64)
     return sp.bsr_matrix((blocks, I[:, 1], indptr), shape=(nb * n, nb * n), blocksize=(nb, nb))
+
+
+def neighbourhood_inverse(Zs, nbhd, nb: int = NB):
+    """The neighbourhood-inverse preconditioner M (scipy BSR, caller order).
+
+    M_pq = (W_p[p,q] + W_q[q,p]^T) / 2, a raw block that does not exist (q not
+    in nbhd[p]) counting as zero; M is complex symmetric like Z, with blocks
+    only on pairs where one wire is in the other's neighbourhood (a subset of
+    the near set).  One wire per neighbourhood gives the block-diagonal
+    preconditioner of Sec. II-B; neighbourhoods that contain whole groups of
+    mutually coupled wires give the exact inverse on those groups."""
+    return symmetrise(neighbourhood_raw_blocks(Zs, nbhd, nb), len(nbhd), nb)

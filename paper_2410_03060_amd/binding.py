@@ -116,6 +116,12 @@ EXPORTS = {
     "chaff_cluster_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "chaff_nbhd_precond_bytes": (C.c_size_t, [C.c_void_p, C.c_int, C.c_int32]),
     "chaff_nbhd_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chaff_nbhd_raw_rows": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chaff_nbhd_mlp_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "chaff_nbhd_mlp_targets": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chaff_nbhd_mlp_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32]),
+    "chaff_nbhd_mlp_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_size_t, C.c_void_p]),
     "chaff_cluster_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                       C.c_void_p]),
     "chaff_last_error": (C.c_char_p, []),
@@ -363,6 +369,45 @@ def nbhd_precond(cl: Cloud, Z, size: int, prec: int = C64):
         raise ChaffError(EINVAL, last_error() or "bad neighbourhood preconditioner arguments")
     M = torch.empty(nbytes, dtype=torch.uint8, device=cl.device)
     _check(lib().chaff_nbhd_precond(cl.handle, prec, int(size), _ptr(Z), _ptr(M), _stream()))
+    return M
+
+
+def nbhd_raw_rows(cl: Cloud, Z, size: int, prec: int = C64):
+    """Unsymmetrised neighbourhood rows (chaff_nbhd_raw_rows): uint8 buffer, the targets' source."""
+    nbytes = lib().chaff_nbhd_precond_bytes(cl.handle, prec, int(size))
+    if nbytes == 0:
+        raise ChaffError(EINVAL, last_error() or "bad neighbourhood preconditioner arguments")
+    M = torch.empty(nbytes, dtype=torch.uint8, device=cl.device)
+    _check(lib().chaff_nbhd_raw_rows(cl.handle, prec, int(size), _ptr(Z), _ptr(M), _stream()))
+    return M
+
+
+def nbhd_mlp_features(cl: Cloud, M, size: int, row0: int = 0, n_rows: int | None = None):
+    """BF16 features [rows, 192] (int16 bit patterns) of the samples (wire, slot, column) of M."""
+    total = cl.n * size * 7
+    n_rows = total - row0 if n_rows is None else n_rows
+    F = torch.empty((n_rows, MLP_NFEAT), dtype=torch.int16, device=cl.device)
+    _check(lib().chaff_nbhd_mlp_features(cl.handle, _ptr(M), row0, n_rows, _ptr(F), _stream()))
+    return F
+
+
+def nbhd_mlp_targets(cl: Cloud, M_raw, Pinv, size: int, prec: int = C64):
+    """FP32 targets [N*size*7, 14] from a raw-rows buffer and the inverse self blocks of fill_Z."""
+    Y = torch.empty((cl.n * size * 7, MLP_NOUT), dtype=torch.float32, device=cl.device)
+    _check(lib().chaff_nbhd_mlp_targets(cl.handle, prec, _ptr(M_raw), _ptr(Pinv), _ptr(Y), _stream()))
+    return Y
+
+
+def nbhd_mlp_precond(cl: Cloud, theta, Pinv, size: int, prec: int = C64):
+    """The learned neighbourhood-inverse preconditioner (chaff_nbhd_mlp_precond): a PRECOND_NBHD buffer."""
+    nbytes = lib().chaff_nbhd_precond_bytes(cl.handle, prec, int(size))
+    wsb = lib().chaff_nbhd_mlp_workspace_bytes(cl.handle, int(size))
+    if nbytes == 0 or wsb == 0:
+        raise ChaffError(EINVAL, last_error() or "bad learned preconditioner arguments")
+    M = torch.empty(nbytes, dtype=torch.uint8, device=cl.device)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=cl.device)
+    _check(lib().chaff_nbhd_mlp_precond(cl.handle, prec, int(size), _ptr(theta), _ptr(Pinv), _ptr(M), _ptr(ws),
+                                        wsb, _stream()))
     return M
 
 

@@ -113,7 +113,12 @@ chaff_status cluster_apply_public(Cloud* c, chaff_prec prec, const void* M, cons
                                   hipStream_t st);
 constexpr int NBH_MAX = 8;   // wires per neighbourhood at most (CHAFF_NBHD_MAX)
 size_t nbhd_buffer_bytes(const Cloud* c, chaff_prec prec, int size);
-chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, void* M, hipStream_t st);
+chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, void* M, bool raw, hipStream_t st);
+chaff_status nbhd_mlp_features(Cloud* c, const void* M, int64_t row0, int64_t n_rows, uint16_t* feat, hipStream_t st);
+chaff_status nbhd_mlp_targets(Cloud* c, chaff_prec prec, const void* M, const void* Pinv, float* Y, hipStream_t st);
+size_t nbhd_mlp_workspace_bytes(const Cloud* c, int size);
+chaff_status nbhd_mlp_precond(Cloud* c, chaff_prec prec, int size, const float* theta, const void* Pinv, void* M,
+                              void* ws, size_t ws_bytes, hipStream_t st);
 
 }  // namespace chaff
 
@@ -425,7 +430,63 @@ chaff_status chaff_nbhd_precond(chaff_cloud h, chaff_prec prec, int32_t size, co
     if (size < 1 || size > NBH_MAX) return fail(CHAFF_EINVAL, "size must be in [1, CHAFF_NBHD_MAX]");
     if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
     if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the neighbourhood-inverse preconditioner needs wires of 8 segments");
-    return nbhd_precond(&h->c, prec, size, Z, M, (hipStream_t)stream);
+    return nbhd_precond(&h->c, prec, size, Z, M, false, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_nbhd_raw_rows(chaff_cloud h, chaff_prec prec, int32_t size, const void* Z, void* M,
+                                 chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !Z || !M) return fail(CHAFF_EINVAL, "NULL argument");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
+    if (size < 1 || size > NBH_MAX) return fail(CHAFF_EINVAL, "size must be in [1, CHAFF_NBHD_MAX]");
+    if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
+    if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the neighbourhood-inverse preconditioner needs wires of 8 segments");
+    return nbhd_precond(&h->c, prec, size, Z, M, true, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_nbhd_mlp_features(chaff_cloud h, const void* M, int64_t row0, int64_t n_rows, uint16_t* feat,
+                                     chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !M || (!feat && n_rows > 0)) return fail(CHAFF_EINVAL, "NULL argument");
+    if (row0 < 0 || n_rows < 0) return fail(CHAFF_EINVAL, "row0 and n_rows must be >= 0");
+    if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
+    if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the learned preconditioner needs wires of 8 segments");
+    if (!std::isfinite(h->c.d_c)) return fail(CHAFF_EINVAL, "the learned preconditioner needs a finite d_c");
+    return nbhd_mlp_features(&h->c, M, row0, n_rows, feat, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+chaff_status chaff_nbhd_mlp_targets(chaff_cloud h, chaff_prec prec, const void* M, const void* Pinv, float* Y,
+                                    chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !M || !Pinv || !Y) return fail(CHAFF_EINVAL, "NULL argument");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
+    if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
+    if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the learned preconditioner needs wires of 8 segments");
+    return nbhd_mlp_targets(&h->c, prec, M, Pinv, Y, (hipStream_t)stream);
+    CHAFF_GUARD_END
+}
+
+size_t chaff_nbhd_mlp_workspace_bytes(chaff_cloud h, int32_t size) {
+    if (!h || size < 1 || size > NBH_MAX || h->c.nseg != NSEG) return 0;
+    return nbhd_mlp_workspace_bytes(&h->c, size);
+}
+
+chaff_status chaff_nbhd_mlp_precond(chaff_cloud h, chaff_prec prec, int32_t size, const float* theta,
+                                    const void* Pinv, void* M, void* ws, size_t ws_bytes, chaff_stream stream) {
+    CHAFF_GUARD_BEGIN
+    if (!h || !theta || !Pinv || !M || !ws) return fail(CHAFF_EINVAL, "NULL argument");
+    if (prec != CHAFF_C64 && prec != CHAFF_C128) return fail(CHAFF_EINVAL, "prec must be CHAFF_C64 or CHAFF_C128");
+    if (size < 1 || size > NBH_MAX) return fail(CHAFF_EINVAL, "size must be in [1, CHAFF_NBHD_MAX]");
+    if (((uintptr_t)M % 256) != 0) return fail(CHAFF_EINVAL, "M must be 256-byte aligned");
+    if (h->c.nseg != NSEG) return fail(CHAFF_EINVAL, "the learned preconditioner needs wires of 8 segments");
+    if (!std::isfinite(h->c.d_c)) return fail(CHAFF_EINVAL, "the learned preconditioner needs a finite d_c");
+    const size_t need = nbhd_mlp_workspace_bytes(&h->c, size);
+    if (ws_bytes < need) return fail(CHAFF_EWORKSPACE, "learned preconditioner workspace too small: need " +
+                                                           std::to_string(need));
+    return nbhd_mlp_precond(&h->c, prec, size, theta, Pinv, M, ws, ws_bytes, (hipStream_t)stream);
     CHAFF_GUARD_END
 }
 

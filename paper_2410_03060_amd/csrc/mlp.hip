@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "precond.hpp"
 #include "prof.hpp"
 
 namespace chaff {
@@ -31,6 +32,7 @@ constexpr int DYLD = 32;         // row stride of dL/dy (K of the first backward
 constexpr int ROWS_WG = 128;     // rows per workgroup in the row-parallel products
 constexpr int SPLIT_ROWS = 512;  // rows per partial sum of the weight gradients
 constexpr double X_SCALE = 0.5;  // network outputs are current departures / 0.5
+constexpr int NB_W = 7;          // rooftop unknowns per wire (8 segments)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -763,6 +765,200 @@ __global__ void k_assemble(const Wire* __restrict__ wires, const int32_t* __rest
 }
 
 // ------------------------------------------------------------------ host side
+// ------------------------------------------------------------------ learned neighbourhood inverse
+// The same network as a block preconditioner: sample (wire i, slot s,
+// column c) of a neighbourhood-inverse buffer predicts column c of the raw
+// row block W_i[i, q] (q = N(i)[s]) in the canonical frames of i and q, from
+// the neighbourhood's geometry alone; the predicted rows are symmetrised like
+// the computed ones.  Canonical tangent tau = sigma t, sigma = +1 when the
+// first nonzero of (t_z, t_y, t_x) is positive; S = sigma P maps rooftop
+// coefficients to the canonical frame (P reverses the rooftops for sigma = -1).
+// Rows: (i size + s) 7 + c, internal wire order i.
+constexpr int NBF_HEAD = 24, NBF_MEM = 15;   // features: head, then 15 per neighbourhood member
+constexpr double NBH_TARGET_SCALE = 0.05;    // targets: departures from the block-Jacobi blocks, times this
+
+__device__ __forceinline__ double canon_sign(const Wire& w) {
+    return (w.tz > 0.0 || (w.tz == 0.0 && (w.ty > 0.0 || (w.ty == 0.0 && w.tx > 0.0)))) ? 1.0 : -1.0;
+}
+
+// |d|/d_c, tau_x.d/d_c, tau_y.d/d_c, tau_x.tau_y, Re, Im exp(-j k |d|) with d = c_y - c_x
+__device__ __forceinline__ void pair_feats(const Wire& x, double sx, const Wire& y, double sy, double k, double dc,
+                                           double (&f)[6]) {
+#pragma clang fp contract(off)
+    const double dx = y.cx - x.cx, dy = y.cy - x.cy, dz = y.cz - x.cz;
+    const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    double s2 = xx + yy;
+    s2 = s2 + zz;
+    const double dist = sqrt(s2);
+    const double xd = sx * ((x.tx * dx + x.ty * dy) + x.tz * dz);
+    const double yd = sy * ((y.tx * dx + y.ty * dy) + y.tz * dz);
+    const double tt = sx * sy * ((x.tx * y.tx + x.ty * y.ty) + x.tz * y.tz);
+    const double ph = k * dist;
+    f[0] = dist / dc;
+    f[1] = xd / dc;
+    f[2] = yd / dc;
+    f[3] = tt;
+    f[4] = cos(ph);
+    f[5] = -sin(ph);
+}
+
+// One wave per (wire, slot): lanes 0..m-1 form the 15 features of one member
+// each, lane 63 the head; the 192-entry row is staged in LDS and written for
+// the 7 columns (one-hot c patched in) with coalesced stores.
+__global__ __launch_bounds__(256) void k_nbhd_feat(const Wire* __restrict__ wires, const int32_t* __restrict__ nbt,
+                                                   int size, int64_t n, int64_t row0, int64_t n_rows, double k,
+                                                   double lam, double dc, uint16_t* __restrict__ feat) {
+#pragma clang fp contract(off)
+    __shared__ uint16_t fs[4][NF];
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t g = row0 / NB_W + (int64_t)blockIdx.x * 4 + w;   // rows 7 g .. 7 g + 6
+    const int64_t i = g / size;
+    const int s = (int)(g - i * size);
+    if (i >= n || NB_W * g >= row0 + n_rows) return;   // wave-uniform
+    for (int f = lane; f < NF; f += 64) fs[w][f] = 0;
+    int32_t mem[8];
+    int m = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        mem[t] = t < size ? nbt[i * size + t] : -1;
+        m += mem[t] >= 0 ? 1 : 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool live = s < m;
+    if (live) {
+        const Wire wp = wires[i];
+        const int32_t q = mem[s];
+        const Wire wq = wires[q];
+        const double sp = canon_sign(wp), sq = canon_sign(wq);
+        double f6[6];
+        if (lane < m) {
+            int32_t wt = mem[0];
+#pragma unroll
+            for (int t = 1; t < 8; ++t)
+                if (t == lane) wt = mem[t];
+            const Wire ww = wires[wt];
+            const double sw = canon_sign(ww);
+            uint16_t* o = &fs[w][NBF_HEAD + NBF_MEM * lane];
+            o[0] = d2bf(1.0);
+            o[1] = d2bf(10.0 * (ww.len / lam - 0.5));
+            pair_feats(wp, sp, ww, sw, k, dc, f6);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) o[2 + j] = d2bf(f6[j]);
+            pair_feats(wq, sq, ww, sw, k, dc, f6);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) o[8 + j] = d2bf(f6[j]);
+            const double dx = ww.cx - wq.cx, dy = ww.cy - wq.cy, dz = ww.cz - wq.cz;
+            const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            double s2 = xx + yy;
+            s2 = s2 + zz;
+            o[14] = d2bf((wt == q || s2 <= dc * dc) ? 1.0 : 0.0);
+        }
+        if (lane == 63) {
+            uint16_t* o = fs[w];
+            o[7 + s] = d2bf(1.0);
+            o[15] = d2bf(10.0 * (wp.len / lam - 0.5));
+            o[16] = d2bf(10.0 * (wq.len / lam - 0.5));
+            pair_feats(wp, sp, wq, sq, k, dc, f6);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) o[17 + j] = d2bf(f6[j]);
+            o[23] = d2bf(m / 8.0);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint16_t one = d2bf(1.0);
+    for (int c = 0; c < NB_W; ++c) {
+        const int64_t row = NB_W * g + c;
+        if (row < row0 || row >= row0 + n_rows) continue;
+        uint16_t* out = feat + (row - row0) * NF;
+        for (int f = lane; f < NF; f += 64) out[f] = (live && f == c) ? one : fs[w][f];
+    }
+}
+
+__device__ __forceinline__ int64_t block_pos(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                                             int64_t i, int32_t q) {
+    int64_t p = -1;
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+        if (col_idx[e] == q) p = e;
+    return p;
+}
+
+// Targets of every row from a buffer of raw rows: y[2r], y[2r+1] = scale *
+// (S_i (W - delta_iq Pinv_i) S_q)[r][c], the departure from the block-diagonal
+// preconditioner (Pinv the inverse self blocks of the fill).
+template <typename CZ>
+__global__ void k_nbhd_targets(const Wire* __restrict__ wires, const int32_t* __restrict__ nbt, int size, int64_t n,
+                               const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                               const CZ* __restrict__ Mv, const CZ* __restrict__ Pinv, float* __restrict__ Y) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n * size * NB_W) return;
+    const int64_t g = row / NB_W;
+    const int c = (int)(row - g * NB_W);
+    const int64_t i = g / size;
+    const int s = (int)(g - i * size);
+    float* y = Y + row * NO;
+    const int32_t q = nbt[i * size + s];
+    if (q < 0) {
+#pragma unroll
+        for (int r = 0; r < NO; ++r) y[r] = 0.f;
+        return;
+    }
+    const int64_t pos = block_pos(row_ptr, col_idx, i, q);
+    const double sp = canon_sign(wires[i]), sq = canon_sign(wires[q]);
+    const int cq = sq > 0 ? c : NB_W - 1 - c;
+    const double f = sp * sq * NBH_TARGET_SCALE;
+#pragma unroll
+    for (int r = 0; r < NB_W; ++r) {
+        const int rp = sp > 0 ? r : NB_W - 1 - r;
+        const CZ v = Mv[pos * NB_W * NB_W + rp * NB_W + cq];
+        double re = (double)v.re, im = (double)v.im;
+        if (q == i) {
+            const CZ b = Pinv[i * NB_W * NB_W + rp * NB_W + cq];
+            re -= (double)b.re;
+            im -= (double)b.im;
+        }
+        y[2 * r] = (float)(f * re);
+        y[2 * r + 1] = (float)(f * im);
+    }
+}
+
+// Raw rows from network outputs (rows [row0, row0 + n_rows)): the inverse map of k_nbhd_targets.
+template <typename CZ>
+__global__ void k_nbhd_assemble(const Wire* __restrict__ wires, const int32_t* __restrict__ nbt, int size,
+                                const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx, int64_t row0,
+                                int64_t n_rows, const float* __restrict__ Y, const CZ* __restrict__ Pinv,
+                                CZ* __restrict__ Mv) {
+    using R = typename real_of<CZ>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows) return;
+    const int64_t row = row0 + t;
+    const int64_t g = row / NB_W;
+    const int c = (int)(row - g * NB_W);
+    const int64_t i = g / size;
+    const int s = (int)(g - i * size);
+    const int32_t q = nbt[i * size + s];
+    if (q < 0) return;
+    const int64_t pos = block_pos(row_ptr, col_idx, i, q);
+    const double sp = canon_sign(wires[i]), sq = canon_sign(wires[q]);
+    const int cq = sq > 0 ? c : NB_W - 1 - c;
+    const double f = sp * sq / NBH_TARGET_SCALE;
+    const float* y = Y + t * NO;
+#pragma unroll
+    for (int r = 0; r < NB_W; ++r) {
+        const int rp = sp > 0 ? r : NB_W - 1 - r;
+        double re = f * (double)y[2 * r], im = f * (double)y[2 * r + 1];
+        if (q == i) {
+            const CZ b = Pinv[i * NB_W * NB_W + rp * NB_W + cq];
+            re += (double)b.re;
+            im += (double)b.im;
+        }
+        Mv[pos * NB_W * NB_W + rp * NB_W + cq] = CZ{(R)re, (R)im};
+    }
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 inline int64_t pad_rows(int64_t m, int64_t a) { return (m + a - 1) / a * a; }
 
@@ -1013,6 +1209,99 @@ chaff_status mlp_guess(Cloud* c, chaff_prec prec, const void* Pinv, const float*
                                (const float*)b.Y, (c128*)X);
         CHAFF_LAUNCH_CHECK();
     }
+    return CHAFF_OK;
+}
+
+// ---------------------------------------------------------------- learned neighbourhood inverse (host)
+
+constexpr int64_t NBH_MLP_CHUNK = 7 * (1 << 15);   // rows per features/forward pass (whole wire slots)
+
+chaff_status nbhd_mlp_features_n(Cloud* c, int size, const void* M, int64_t row0, int64_t n_rows, uint16_t* feat,
+                                 hipStream_t st) {
+    if (n_rows == 0 || c->n == 0) return CHAFF_OK;
+    const int32_t* nbt = reinterpret_cast<const int32_t*>(static_cast<const char*>(M) + NBH_HEADER);
+    const double k = 2.0 * 3.14159265358979323846 / c->wavelength;
+    const int64_t g0 = row0 / NB_W, g1 = (row0 + n_rows - 1) / NB_W;
+    ProfScope ps("nbhd_mlp_features", st, (double)n_rows * NF * 2.0);
+    hipLaunchKernelGGL(k_nbhd_feat, dim3(nblk(g1 - g0 + 1, 4)), dim3(256), 0, st, (const Wire*)c->wires, nbt, size,
+                       c->n, row0, n_rows, k, c->wavelength, c->d_c, feat);
+    CHAFF_LAUNCH_CHECK();
+    return CHAFF_OK;
+}
+
+chaff_status nbhd_mlp_features(Cloud* c, const void* M, int64_t row0, int64_t n_rows, uint16_t* feat, hipStream_t st) {
+    NbhdHeader h{};
+    chaff_status s = nbhd_header(c, M, &h, st);
+    if (s != CHAFF_OK) return s;
+    if (row0 + n_rows > c->n * h.size * NB_W)
+        return fail(CHAFF_EINVAL, "rows beyond the buffer's N * size * 7 samples");
+    return nbhd_mlp_features_n(c, h.size, M, row0, n_rows, feat, st);
+}
+
+chaff_status nbhd_mlp_targets(Cloud* c, chaff_prec prec, const void* M, const void* Pinv, float* Y, hipStream_t st) {
+    NbhdHeader h{};
+    chaff_status s = nbhd_header(c, M, &h, st);
+    if (s != CHAFF_OK) return s;
+    if (!h.raw || h.prec != (int32_t)prec)
+        return fail(CHAFF_EINVAL, "targets need a buffer of raw rows (chaff_nbhd_raw_rows) of the same precision");
+    const int64_t rows = c->n * h.size * NB_W;
+    if (rows == 0) return CHAFF_OK;
+    const int32_t* nbt = reinterpret_cast<const int32_t*>(static_cast<const char*>(M) + NBH_HEADER);
+    const char* vals = static_cast<const char*>(M) + nbhd_blocks_offset(c->n, h.size);
+    if (prec == CHAFF_C64)
+        hipLaunchKernelGGL(k_nbhd_targets<c64>, dim3(nblk(rows, 256)), dim3(256), 0, st, (const Wire*)c->wires, nbt,
+                           h.size, c->n, (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, (const c64*)vals,
+                           (const c64*)Pinv, Y);
+    else
+        hipLaunchKernelGGL(k_nbhd_targets<c128>, dim3(nblk(rows, 256)), dim3(256), 0, st, (const Wire*)c->wires, nbt,
+                           h.size, c->n, (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, (const c128*)vals,
+                           (const c128*)Pinv, Y);
+    CHAFF_LAUNCH_CHECK();
+    return CHAFF_OK;
+}
+
+size_t nbhd_mlp_workspace_bytes(const Cloud* c, int size) {
+    const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(c->n * size * NB_W, NBH_MLP_CHUNK));
+    Carve cv(nullptr, 0);
+    carve_fwd(cv, pad_rows(rows, ROWS_WG), true);
+    cv.take<uint16_t>((size_t)pad_rows(rows, ROWS_WG) * NF);
+    return cv.off + 256;
+}
+
+chaff_status nbhd_mlp_precond(Cloud* c, chaff_prec prec, int size, const float* theta, const void* Pinv, void* M,
+                              void* ws, size_t ws_bytes, hipStream_t st) {
+    chaff_status s = nbhd_begin(c, prec, size, false, M, st);
+    if (s != CHAFF_OK || c->n == 0) return s;
+    const int64_t total = c->n * size * NB_W;
+    const int64_t chunk = std::min<int64_t>(total, NBH_MLP_CHUNK);
+    Carve cv(ws, ws_bytes);
+    FwdBufs b = carve_fwd(cv, pad_rows(chunk, ROWS_WG), true);
+    uint16_t* feat = cv.take<uint16_t>((size_t)pad_rows(chunk, ROWS_WG) * NF);
+    if (!cv.ok()) return fail(CHAFF_EWORKSPACE, "learned preconditioner workspace too small");
+    s = launch_pack(theta, b.pk, st);
+    if (s != CHAFF_OK) return s;
+    const int32_t* nbt = reinterpret_cast<const int32_t*>(static_cast<const char*>(M) + NBH_HEADER);
+    char* vals = static_cast<char*>(M) + nbhd_blocks_offset(c->n, size);
+    for (int64_t r0 = 0; r0 < total; r0 += chunk) {
+        const int64_t nr = std::min(chunk, total - r0);
+        s = nbhd_mlp_features_n(c, size, M, r0, nr, feat, st);
+        if (s != CHAFF_OK) return s;
+        s = forward_fused(theta, b.pk, feat, nr, b.Y, st);
+        if (s != CHAFF_OK) return s;
+        ProfScope ps("nbhd_mlp_assemble", st, (double)nr * (NO * 4 + 7 * (prec == CHAFF_C64 ? 8 : 16)));
+        if (prec == CHAFF_C64)
+            hipLaunchKernelGGL(k_nbhd_assemble<c64>, dim3(nblk(nr, 256)), dim3(256), 0, st, (const Wire*)c->wires, nbt,
+                               size, (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, r0, nr,
+                               (const float*)b.Y, (const c64*)Pinv, (c64*)vals);
+        else
+            hipLaunchKernelGGL(k_nbhd_assemble<c128>, dim3(nblk(nr, 256)), dim3(256), 0, st, (const Wire*)c->wires,
+                               nbt, size, (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, r0, nr,
+                               (const float*)b.Y, (const c128*)Pinv, (c128*)vals);
+        CHAFF_LAUNCH_CHECK();
+    }
+    s = nbhd_symmetrise(c, prec, vals, st);
+    if (s != CHAFF_OK) return s;
+    CHAFF_HIP(hipStreamSynchronize(st));
     return CHAFF_OK;
 }
 

@@ -507,61 +507,90 @@ __global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int si
 #pragma unroll
     for (int c = 0; c < NB; ++c) A[NR + c] = c64{lane == c ? 1.f : 0.f, 0.f};
 
-    bool used = lane >= NR;
+    // Gauss-Jordan over the 7 m columns of the real system (padding rows keep
+    // their identity entries and never compete for a pivot).  Rows are not
+    // normalised: the pivot row of column k keeps its pivot d_k, the other rows
+    // subtract (a_rk / d_k) times it, and at the end row piv(u) holds d_u in
+    // column u, zeros in every other column and d_u x_u in the unit columns.
+    // Columns are walked block by block: block kb's 7 columns are copied once
+    // into T (static indices from then on); columns of earlier blocks are never
+    // read again, so only T, the later blocks and the unit columns change.
+    const int nr = NB * m;
+    bool used = lane >= nr;
     int my_u = -1;
+    c64 my_d = {1.f, 0.f};
     bool bad = false;
-    for (int k = 0; k < NR; ++k) {
-        c64 v = A[0];
+    for (int kb = 0; kb < m; ++kb) {
+        c64 T[NB];
 #pragma unroll
-        for (int j = 1; j < NR; ++j)
-            if (j == k) v = A[j];
-        // pivot: the largest |a_rk| among rows not yet used, lowest row on ties (NaN counts as 0)
-        float mag = -1.f;
-        if (!used) {
-            mag = v.re * v.re + v.im * v.im;
-            if (!(mag >= 0.f)) mag = 0.f;
-        }
-        int idx = lane;
+        for (int c = 0; c < NB; ++c) T[c] = A[c];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float om = __shfl_xor(mag, off, 64);
-            const int oi = __shfl_xor(idx, off, 64);
-            if (om > mag || (om == mag && oi < idx)) {
-                mag = om;
-                idx = oi;
+        for (int b = 1; b < KM; ++b)
+            if (b == kb) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) T[c] = A[NB * b + c];
             }
-        }
-        const int piv = __builtin_amdgcn_readfirstlane(idx);
-        const float pre = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.re), piv));
-        const float pim = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.im), piv));
-        const float d = pre * pre + pim * pim;
-        c64 inv = {0.f, 0.f};
-        if (d > 0.f && d < INFINITY) inv = c64{pre / d, -pim / d};
-        else bad = true;
-        if (lane == piv) {
-            used = true;
-            my_u = k;
 #pragma unroll
-            for (int j = 0; j < NC; ++j) A[j] = cmul(A[j], inv);
-        }
-        const c64 l = (lane == piv || lane >= NR) ? c64{0.f, 0.f} : v;
+        for (int kc = 0; kc < NB; ++kc) {
+            const c64 v = T[kc];
+            // pivot: the largest |a_rk| among rows not yet used, lowest row on ties (NaN counts as 0)
+            float mag = -1.f;
+            if (!used) {
+                mag = v.re * v.re + v.im * v.im;
+                if (!(mag >= 0.f)) mag = 0.f;
+            }
+            int idx = lane;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
-            const c64 pj = {__int_as_float(__builtin_amdgcn_readlane(__float_as_int(A[j].re), piv)),
-                            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(A[j].im), piv))};
-            A[j].re = fmaf(-l.re, pj.re, A[j].re);
-            A[j].re = fmaf(l.im, pj.im, A[j].re);
-            A[j].im = fmaf(-l.re, pj.im, A[j].im);
-            A[j].im = fmaf(-l.im, pj.re, A[j].im);
+            for (int off = 32; off > 0; off >>= 1) {
+                const float om = __shfl_xor(mag, off, 64);
+                const int oi = __shfl_xor(idx, off, 64);
+                if (om > mag || (om == mag && oi < idx)) {
+                    mag = om;
+                    idx = oi;
+                }
+            }
+            const int piv = __builtin_amdgcn_readfirstlane(idx);
+            const c64 pv = {__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.re), piv)),
+                            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.im), piv))};
+            const float d = pv.re * pv.re + pv.im * pv.im;
+            c64 inv = {0.f, 0.f};
+            if (d > 0.f && d < INFINITY) inv = c64{pv.re / d, -pv.im / d};
+            else bad = true;
+            if (lane == piv) {
+                used = true;
+                my_u = NB * kb + kc;
+                my_d = pv;
+            }
+            const c64 l = (lane == piv || lane >= NR) ? c64{0.f, 0.f} : cmul(v, inv);
+            auto elim = [&](c64& a) {
+                const c64 pj = {__int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.re), piv)),
+                                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.im), piv))};
+                a.re = fmaf(-l.re, pj.re, a.re);
+                a.re = fmaf(l.im, pj.im, a.re);
+                a.im = fmaf(-l.re, pj.im, a.im);
+                a.im = fmaf(-l.im, pj.re, a.im);
+            };
+#pragma unroll
+            for (int c = kc + 1; c < NB; ++c) elim(T[c]);
+#pragma unroll
+            for (int b = 1; b < KM; ++b)
+                if (b > kb) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) elim(A[NB * b + c]);
+                }
+#pragma unroll
+            for (int c = 0; c < NB; ++c) elim(A[NR + c]);
         }
     }
-    // the pivot row of unknown u holds row u of A^-1 E: raw_{p, mem[s]}[c][a] with u = 7 s + a
+    // the pivot row of unknown u holds d_u times row u of A^-1 E: raw_{p, mem[s]}[c][a] with u = 7 s + a
     if (my_u >= 0) {
         const int s = my_u / NB, a = my_u % NB;
+        const float dd = my_d.re * my_d.re + my_d.im * my_d.im;
+        const c64 id = dd > 0.f ? c64{my_d.re / dd, -my_d.im / dd} : c64{0.f, 0.f};
         if (s < m) {
             const int64_t p = pos_s[w][s];   // (p, mem[s]) in row p
 #pragma unroll
-            for (int c = 0; c < NB; ++c) M[p * NB2 + c * NB + a] = ccast<CZ>(A[NR + c]);
+            for (int c = 0; c < NB; ++c) M[p * NB2 + c * NB + a] = ccast<CZ>(cmul(A[NR + c], id));
         }
     }
     if (bad && lane == 0) status[0] = 1;
@@ -591,20 +620,21 @@ __global__ __launch_bounds__(256) void k_nbhd_symm(int64_t n_pairs, const Pair* 
 template <typename CZ>
 void nbhd_build_launch(Cloud* c, int size, const int32_t* nbt, const CZ* Z, CZ* M, hipStream_t st) {
     const unsigned g = (unsigned)((c->n + NBH_WAVES - 1) / NBH_WAVES);
-    if (size <= 2)
-        hipLaunchKernelGGL((k_nbhd_build<CZ, 2>), dim3(g), dim3(64 * NBH_WAVES), 0, st, c->n, size, nbt,
-                           (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, Z, M, c->d_status);
-    else if (size <= 4)
-        hipLaunchKernelGGL((k_nbhd_build<CZ, 4>), dim3(g), dim3(64 * NBH_WAVES), 0, st, c->n, size, nbt,
-                           (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, Z, M, c->d_status);
-    else
-        hipLaunchKernelGGL((k_nbhd_build<CZ, 8>), dim3(g), dim3(64 * NBH_WAVES), 0, st, c->n, size, nbt,
-                           (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, Z, M, c->d_status);
+#define CHAFF_NBH(KMV)                                                                                       \
+    case KMV:                                                                                                \
+        hipLaunchKernelGGL((k_nbhd_build<CZ, KMV>), dim3(g), dim3(64 * NBH_WAVES), 0, st, c->n, size, nbt,   \
+                           (const int64_t*)c->row_ptr, (const int32_t*)c->col_idx, Z, M, c->d_status);       \
+        break;
+    switch (size) {   // the local system is sized for exactly `size` wires
+        CHAFF_NBH(1) CHAFF_NBH(2) CHAFF_NBH(3) CHAFF_NBH(4) CHAFF_NBH(5) CHAFF_NBH(6) CHAFF_NBH(7)
+        default: CHAFF_NBH(8)
+    }
+#undef CHAFF_NBH
 }
 
 }  // namespace
 
-chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, void* M, hipStream_t st) {
+chaff_status nbhd_begin(Cloud* c, chaff_prec prec, int size, bool raw, void* M, hipStream_t st) {
     if (size < 1 || size > NBH_MAX) return fail(CHAFF_EINVAL, "neighbourhood size must be in [1, 8]");
     NbhdHeader h{};
     h.magic = NBH_MAGIC;
@@ -612,54 +642,82 @@ chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, vo
     h.nnzb = c->nnzb;
     h.size = size;
     h.prec = (int32_t)prec;
+    h.raw = raw ? 1 : 0;
     CHAFF_HIP(hipMemcpyAsync(M, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    CHAFF_HIP(hipStreamSynchronize(st));
+    if (c->n == 0) return CHAFF_OK;
     int32_t* nbt = reinterpret_cast<int32_t*>(static_cast<char*>(M) + NBH_HEADER);
     char* vals = static_cast<char*>(M) + nbhd_blocks_offset(c->n, size);
-    if (c->n > 0) {
+    const size_t zb = prec == CHAFF_C64 ? sizeof(c64) : sizeof(c128);
+    const int64_t words = (int64_t)((size_t)c->nnzb * NB2 * zb / 4);
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0, st,
+                       (uint32_t*)vals, words);
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, c->d_status);
+    hipLaunchKernelGGL(k_nbhd_select, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, st, c->n, size,
+                       (const Wire*)c->wires, (const int32_t*)c->perm, (const int64_t*)c->row_ptr,
+                       (const int32_t*)c->col_idx, nbt);
+    CHAFF_LAUNCH_CHECK();
+    return CHAFF_OK;
+}
+
+chaff_status nbhd_symmetrise(Cloud* c, chaff_prec prec, void* vals, hipStream_t st) {
+    const int64_t units = c->n_pairs + c->n;
+    if (units == 0) return CHAFF_OK;
+    const unsigned gs = (unsigned)((units * 64 + 255) / 256);
+    if (prec == CHAFF_C64)
+        hipLaunchKernelGGL((k_nbhd_symm<c64>), dim3(gs), dim3(256), 0, st, c->n_pairs, (const Pair*)c->pairs, c->n,
+                           (const int64_t*)c->diag_pos, (c64*)vals);
+    else
+        hipLaunchKernelGGL((k_nbhd_symm<c128>), dim3(gs), dim3(256), 0, st, c->n_pairs, (const Pair*)c->pairs, c->n,
+                           (const int64_t*)c->diag_pos, (c128*)vals);
+    CHAFF_LAUNCH_CHECK();
+    return CHAFF_OK;
+}
+
+chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, void* M, bool raw, hipStream_t st) {
+    chaff_status s = nbhd_begin(c, prec, size, raw, M, st);
+    if (s != CHAFF_OK || c->n == 0) return s;
+    const int32_t* nbt = reinterpret_cast<const int32_t*>(static_cast<const char*>(M) + NBH_HEADER);
+    char* vals = static_cast<char*>(M) + nbhd_blocks_offset(c->n, size);
+    {
         const size_t zb = prec == CHAFF_C64 ? sizeof(c64) : sizeof(c128);
-        const int64_t words = (int64_t)((size_t)c->nnzb * NB2 * zb / 4);
-        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)), dim3(256), 0,
-                           st, (uint32_t*)vals, words);
-        hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, c->d_status);
-        hipLaunchKernelGGL(k_nbhd_select, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, st, c->n, size,
-                           (const Wire*)c->wires, (const int32_t*)c->perm, (const int64_t*)c->row_ptr,
-                           (const int32_t*)c->col_idx, nbt);
-        CHAFF_LAUNCH_CHECK();
-        {
-            const int km = size <= 2 ? 2 : size <= 4 ? 4 : 8;
-            const double nr = (double)NB * km;
-            ProfScope ps("nbhd_build", st, ProfWork{(double)c->nnzb * NB2 * zb, (double)c->n * nr * nr * (nr + NB) * 8.0});
-            if (prec == CHAFF_C64)
-                nbhd_build_launch<c64>(c, size, nbt, (const c64*)Z, (c64*)vals, st);
-            else
-                nbhd_build_launch<c128>(c, size, nbt, (const c128*)Z, (c128*)vals, st);
-            CHAFF_LAUNCH_CHECK();
-        }
-        const int64_t units = c->n_pairs + c->n;
-        const unsigned gs = (unsigned)((units * 64 + 255) / 256);
+        const double nr = (double)NB * size;
+        ProfScope ps("nbhd_build", st, ProfWork{(double)c->nnzb * NB2 * zb, (double)c->n * nr * nr * (nr + NB) * 8.0});
         if (prec == CHAFF_C64)
-            hipLaunchKernelGGL((k_nbhd_symm<c64>), dim3(gs), dim3(256), 0, st, c->n_pairs, (const Pair*)c->pairs, c->n,
-                               (const int64_t*)c->diag_pos, (c64*)vals);
+            nbhd_build_launch<c64>(c, size, nbt, (const c64*)Z, (c64*)vals, st);
         else
-            hipLaunchKernelGGL((k_nbhd_symm<c128>), dim3(gs), dim3(256), 0, st, c->n_pairs, (const Pair*)c->pairs, c->n,
-                               (const int64_t*)c->diag_pos, (c128*)vals);
+            nbhd_build_launch<c128>(c, size, nbt, (const c128*)Z, (c128*)vals, st);
         CHAFF_LAUNCH_CHECK();
     }
+    if (!raw) {
+        s = nbhd_symmetrise(c, prec, vals, st);
+        if (s != CHAFF_OK) return s;
+    }
     int32_t flag = 0;
-    if (c->n > 0) CHAFF_HIP(hipMemcpyAsync(&flag, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    CHAFF_HIP(hipStreamSynchronize(st));   // also keeps the host header alive until copied
+    CHAFF_HIP(hipMemcpyAsync(&flag, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CHAFF_HIP(hipStreamSynchronize(st));
     if (flag) return fail(CHAFF_ESINGULAR, "a neighbourhood system has a zero pivot");
+    return CHAFF_OK;
+}
+
+chaff_status nbhd_header(const Cloud* c, const void* M, NbhdHeader* h, hipStream_t st) {
+    CHAFF_HIP(hipMemcpyAsync(h, M, sizeof(*h), hipMemcpyDeviceToHost, st));
+    CHAFF_HIP(hipStreamSynchronize(st));
+    if (h->magic != NBH_MAGIC || h->n != c->n || h->nnzb != c->nnzb || h->size < 1 || h->size > NBH_MAX)
+        return fail(CHAFF_EINVAL, "the buffer is not a neighbourhood-inverse preconditioner buffer of this cloud "
+                                  "(build it with chaff_nbhd_precond)");
     return CHAFF_OK;
 }
 
 chaff_status nbhd_check(const Cloud* c, chaff_prec prec, const void* M, int* size, hipStream_t st) {
     NbhdHeader h{};
-    CHAFF_HIP(hipMemcpyAsync(&h, M, sizeof(h), hipMemcpyDeviceToHost, st));
-    CHAFF_HIP(hipStreamSynchronize(st));
-    if (h.magic != NBH_MAGIC || h.n != c->n || h.nnzb != c->nnzb || h.prec != (int32_t)prec || h.size < 1 ||
-        h.size > NBH_MAX)
-        return fail(CHAFF_EINVAL, "the preconditioner buffer is not a neighbourhood-inverse preconditioner of this "
-                                  "cloud and precision (build it with chaff_nbhd_precond)");
+    chaff_status s = nbhd_header(c, M, &h, st);
+    if (s != CHAFF_OK) return s;
+    if (h.prec != (int32_t)prec)
+        return fail(CHAFF_EINVAL, "the neighbourhood-inverse preconditioner was built for the other precision");
+    if (h.raw)
+        return fail(CHAFF_EINVAL, "the buffer holds unsymmetrised neighbourhood rows (chaff_nbhd_raw_rows), "
+                                  "not a preconditioner");
     *size = h.size;
     return CHAFF_OK;
 }

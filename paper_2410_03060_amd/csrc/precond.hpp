@@ -43,13 +43,20 @@ constexpr int64_t NBH_MAGIC = 0x3148424e46464843ll;   // "CHFFNBH1"
 struct NbhdHeader {
     int64_t magic, n, nnzb;
     int32_t size, prec;
+    int32_t raw, pad;    // raw = 1: unsymmetrised rows (training targets), refused by the solver
 };
 // Buffer: header (256 B), [N][size] int32 neighbourhood table (internal
 // indices, slot 0 the wire itself, -1 unused) padded to 256 B, then
 // [nnzb][NB][NB] complex (prec) in Z's block order.
 size_t nbhd_table_bytes(int64_t n, int size);
 size_t nbhd_buffer_bytes(const Cloud* c, chaff_prec prec, int size);
-chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, void* M, hipStream_t st);
+chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, void* M, bool raw, hipStream_t st);
+// Steps shared with the learned form: the header, zeroed blocks and the
+// neighbourhood table; the symmetrisation of raw rows in place.
+chaff_status nbhd_begin(Cloud* c, chaff_prec prec, int size, bool raw, void* M, hipStream_t st);
+chaff_status nbhd_symmetrise(Cloud* c, chaff_prec prec, void* vals, hipStream_t st);
+// Reads M's header (host-synchronising) and checks it against the cloud.
+chaff_status nbhd_header(const Cloud* c, const void* M, NbhdHeader* h, hipStream_t st);
 // Host check of M's header against the cloud (host-synchronising); returns
 // the neighbourhood size through *size.
 chaff_status nbhd_check(const Cloud* c, chaff_prec prec, const void* M, int* size, hipStream_t st);

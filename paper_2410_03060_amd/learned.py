@@ -1,4 +1,5 @@
-"""Training and use of the learned initial guess (host orchestration only).
+"""Training and use of the learned parts (host orchestration only): the initial
+guess and the learned neighbourhood-inverse preconditioner.
 
 Every step runs in libchaff: the training currents come from the library's
 own solver, the features and targets from its feature and target kernels,
@@ -49,6 +50,25 @@ def solved_samples(workloads, opts=None, device="cuda") -> SampleSet:
         B.destroy(cl)
     torch.cuda.synchronize()
     return SampleSet(torch.cat(feats), torch.cat(targs), len(workloads), time.perf_counter() - t0, iters)
+
+
+def nbhd_samples(workloads, size: int, device="cuda") -> SampleSet:
+    """Samples of the learned neighbourhood inverse: for every workload the library
+    computes the raw neighbourhood rows (chaff_nbhd_raw_rows), their features and
+    targets; rows of empty slots are left out."""
+    feats, targs = [], []
+    t0 = time.perf_counter()
+    for wl in workloads:
+        cl = B.build_cloud(wl.cloud, device)
+        Z, P = B.fill_Z(cl, B.C64)
+        Mr = B.nbhd_raw_rows(cl, Z, size)
+        valid = (B.nbhd_table(cl, Mr, size) >= 0)[:, :, None].expand(cl.n, size, 7).reshape(-1)
+        feats.append(B.nbhd_mlp_features(cl, Mr, size)[valid])
+        targs.append(B.nbhd_mlp_targets(cl, Mr, P, size)[valid])
+        del Z, P, Mr
+        B.destroy(cl)
+    torch.cuda.synchronize()
+    return SampleSet(torch.cat(feats), torch.cat(targs), len(workloads), time.perf_counter() - t0, [])
 
 
 @dataclass

@@ -24,6 +24,11 @@ outputs are computed one by one and compared:
     stored incidence within 0.1 dB, the currents of 2,000 seeded wires within
     1e-4 relative (||x_gpu - x_orc|| / ||x_orc|| over those wires), and
     ||x|| of all currents within 1e-4.
+
+The same launch configuration with the neighbourhood-inverse preconditioner
+(the benchmark's default at both sizes) is checked against the stored
+solutions too, with sampled rows of the preconditioner against the oracle's
+definition.
 """
 import os
 
@@ -183,3 +188,106 @@ def test_full_size_sampled_parity(B, config):
     db = np.abs(10 * np.log10(sig / so))
     say(f"  rcs of {len(sel)} incidences: max {db.max():.2e} dB")
     assert db.max() <= 1e-4
+
+
+@pytest.mark.parametrize("config,size", [("c4_eval", 4), ("c5", 8)])
+def test_full_size_neighbourhood_inverse(B, config, size):
+    """The benchmark's launch configuration with the neighbourhood-inverse
+    preconditioner: the solve against the oracle's stored solutions (every
+    stored incidence within 0.1 dB, sampled-wire currents and ||x|| within
+    1e-4), and the preconditioner's rows of 12 sampled wires against the
+    oracle's definition (neighbourhood identical; each block row within
+    kappa * 3e-5 + 1e-6 of the oracle's, kappa the condition numbers of the
+    neighbourhood systems the row draws on)."""
+    import torch
+    wl = getattr(W, config)()
+    cloud = wl.cloud
+    say(f"[fullsize nbhd] {config}: N={cloud.n}, K={size}")
+    cl = B.build_cloud(cloud)
+    Z, _ = B.fill_Z(cl, B.C64, with_pinv=False)
+    M = B.nbhd_precond(cl, Z, size, B.C64)
+    X, info = B.solve(cl, Z, M, wl.inc.k_hat, wl.inc.e_hat,
+                      B.solve_opts(tol=1e-6, method=B.COCG, restart=5000, max_cycles=60, inner_tol=1e-5,
+                                   use_x0=2, precond=B.PRECOND_NBHD))
+    say(f"  solve: cycles {info['cycles']} iterations {info['iterations']} residual {info['max_rel_residual']:.2e}")
+    assert info["max_rel_residual"] <= 1e-6
+    sig_all = B.rcs(cl, X, -wl.inc.k_hat, wl.inc.e_hat, monostatic=True)[0].cpu().numpy()
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", f"fullsize_{config}.npz"))
+    gi = gold["incidences"]
+    rows = (NB * gold["wires"][:, None] + np.arange(NB)[None, :]).reshape(-1)
+    Xg = X[:, torch.as_tensor(gi, device=X.device)]
+    xs = Xg[torch.as_tensor(rows, device=X.device)].cpu().numpy()
+    cerr = np.linalg.norm(xs - gold["currents"], axis=0) / np.linalg.norm(gold["currents"], axis=0)
+    nerr = np.abs(torch.linalg.vector_norm(Xg, dim=0).cpu().numpy() - gold["xnorm"]) / gold["xnorm"]
+    db = np.abs(10 * np.log10(sig_all[gi] / gold["sigma"]))
+    say(f"  against the oracle's solutions: current err {cerr.max():.2e}, ||x|| err {nerr.max():.2e}, "
+        f"rcs {db.max():.2e} dB")
+    assert cerr.max() <= 1e-4 and nerr.max() <= 1e-4 and db.max() <= 0.1
+
+    # sampled rows of M against the oracle's definition, from the oracle's own blocks
+    row_ptr, col_idx, perm, _ = cl.pattern()
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(cloud.n, dtype=perm.dtype)
+    tab = B.nbhd_table(cl, M, size).cpu().numpy()
+    V = B.nbhd_blocks(cl, M, size, B.C64)
+    k = 2.0 * math.pi / cloud.wavelength
+    rng = np.random.default_rng(17)
+    wires = np.sort(rng.choice(cloud.n, 12, replace=False))
+
+    def nbhd_of(p):      # the oracle's definition: p, then the size-1 nearest near-set wires
+        nb = _near_brute(cloud, p)
+        d = cloud.center[nb] - cloud.center[p]
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        return np.concatenate([[p], nb[np.lexsort((nb, d2))][:size - 1]]).astype(np.int64)
+
+    def local_system(g):
+        m = len(g)
+        A = np.zeros((NB * m, NB * m), dtype=np.complex128)
+        S = mom.self_blocks(cloud.length[g], cloud.radius[g], k)
+        for a in range(m):
+            A[NB * a:NB * a + NB, NB * a:NB * a + NB] = S[a]
+        pairs = [(a, b) for a in range(m) for b in range(m)
+                 if a != b and int(g[b]) in set(_near_brute(cloud, int(g[a])).tolist())]
+        if pairs:
+            blk = mom.mutual_blocks(cloud.center, cloud.tangent, cloud.length, cloud.radius,
+                                    np.array([g[a] for a, _ in pairs]), np.array([g[b] for _, b in pairs]), k)
+            for (a, b), zb in zip(pairs, blk):
+                A[NB * a:NB * a + NB, NB * b:NB * b + NB] = zb
+        return A
+
+    raw_cache = {}
+
+    def raw_row(p):      # {q: W_p[p, q]} and cond(A_p)
+        if p not in raw_cache:
+            g = nbhd_of(p)
+            A = local_system(g)
+            Wp = np.linalg.inv(A)
+            raw_cache[p] = ({int(q): Wp[:NB, NB * t:NB * t + NB] for t, q in enumerate(g)}, np.linalg.cond(A))
+        return raw_cache[p]
+
+    worst = 0.0
+    for p in wires:
+        i = int(iperm[p])
+        g_lib = perm[tab[i][tab[i] >= 0]].astype(np.int64)
+        assert np.array_equal(g_lib, nbhd_of(int(p)))
+        e0, e1 = int(row_ptr[i]), int(row_ptr[i + 1])
+        cols = perm[col_idx[e0:e1]].astype(np.int64)
+        got = V[e0:e1].cpu().numpy().astype(np.complex128)
+        rp, kp = raw_row(int(p))
+        ref = np.zeros_like(got)
+        kap = kp
+        for t, q in enumerate(cols):
+            rq, kq = raw_row(int(q))
+            a = rp.get(int(q))
+            b = rq.get(int(p))
+            v = np.zeros((NB, NB), dtype=np.complex128)
+            if a is not None:
+                v = v + a
+            if b is not None:
+                v = v + b.T
+                kap = max(kap, kq)
+            ref[t] = 0.5 * v
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        worst = max(worst, err / (3e-5 * kap + 1e-6))
+    say(f"  {len(wires)} sampled rows of M: err / bound max {worst:.3f}")
+    assert worst <= 1.0
