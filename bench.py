@@ -352,7 +352,7 @@ def compare_guesses(step, kinds):
     return out
 
 
-def compare_preconds(step, kinds, size):
+def compare_preconds(step, kinds, size, tol):
     """Iterations and wall time of one full step with each preconditioner (guess x0 = M u; untimed region)."""
     import torch
     out = {"neighbourhood_size": size}
@@ -363,7 +363,7 @@ def compare_preconds(step, kinds, size):
         torch.cuda.synchronize()
         out[kind] = {"iterations": info["iterations"], "cycles": info["cycles"],
                      "max_rel_residual": info["max_rel_residual"], "step_seconds": time.perf_counter() - t0,
-                     "converged": bool(info["max_rel_residual"] <= opts.tol)}
+                     "converged": bool(info["max_rel_residual"] <= tol)}
         del cl, X, sig, Z
         print(f"[bench] precond {kind}: iterations {info['iterations']} step {out[kind]['step_seconds']:.3f} s",
               file=sys.stderr, flush=True)
@@ -679,7 +679,7 @@ def main(argv=None) -> int:
     if not a.no_compare and a.config in MLP_TRAINING:
         out["guess_comparison"] = compare_guesses(step, ["zero", "bj"] + (["mlp"] if theta is not None else []))
         kinds = ["block", "cluster", "nbhd"] + (["nbhd_mlp"] if theta_nb is not None else [])
-        out["precond_comparison"] = compare_preconds(step, kinds, nbhd_size)
+        out["precond_comparison"] = compare_preconds(step, kinds, nbhd_size, a.tol)
     if not a.no_comparator:
         out["comparator"] = fp64_comparator(B, geom, wl, kh, eh, a.tol, a.config, X_ours=X_last, sig_ours=sig_last)
     if not a.no_cpu_baseline:

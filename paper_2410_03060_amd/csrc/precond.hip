@@ -452,6 +452,29 @@ __global__ __launch_bounds__(256) void k_nbhd_select(int64_t n, int size, const 
         if (t + 1 < size) out[t + 1] = bj[t];
 }
 
+// Wave arg-max of a non-negative magnitude over the lanes still competing:
+// each lane forms the key (magnitude bits with the low 6 cleared) | (63 - lane)
+// (float bits order like the magnitudes; the lowest lane wins a tie), the
+// keys are reduced with DPP moves inside each row of 16 lanes and the four
+// row maxima read back to the scalar unit.  The magnitudes compared keep 17
+// of their 23 fraction bits, so the pivot is the largest to 2^-17 — still a
+// partial pivot.
+__device__ __forceinline__ int pivot_lane(bool used, float mag, int lane) {
+    if (!(mag >= 0.f)) mag = 0.f;
+    uint32_t key = used ? 0u : ((__float_as_uint(mag) & ~63u) | (uint32_t)(63 - lane));
+    // quad_perm [1,0,3,2] (lane ^ 1), quad_perm [2,3,0,1] (lane ^ 2), row_half_mirror, row_mirror
+    key = max(key, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0xB1, 0xF, 0xF, false));
+    key = max(key, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x4E, 0xF, 0xF, false));
+    key = max(key, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x141, 0xF, 0xF, false));
+    key = max(key, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x140, 0xF, 0xF, false));
+    const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, 0);
+    const uint32_t k1 = (uint32_t)__builtin_amdgcn_readlane((int)key, 16);
+    const uint32_t k2 = (uint32_t)__builtin_amdgcn_readlane((int)key, 32);
+    const uint32_t k3 = (uint32_t)__builtin_amdgcn_readlane((int)key, 48);
+    const uint32_t best = max(max(k0, k1), max(k2, k3));
+    return 63 - (int)(best & 63u);
+}
+
 template <typename CZ, int KM>
 __global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int size, const int32_t* __restrict__ nbt,
                                                                const int64_t* __restrict__ row_ptr,
@@ -533,23 +556,8 @@ __global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int si
 #pragma unroll
         for (int kc = 0; kc < NB; ++kc) {
             const c64 v = T[kc];
-            // pivot: the largest |a_rk| among rows not yet used, lowest row on ties (NaN counts as 0)
-            float mag = -1.f;
-            if (!used) {
-                mag = v.re * v.re + v.im * v.im;
-                if (!(mag >= 0.f)) mag = 0.f;
-            }
-            int idx = lane;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const float om = __shfl_xor(mag, off, 64);
-                const int oi = __shfl_xor(idx, off, 64);
-                if (om > mag || (om == mag && oi < idx)) {
-                    mag = om;
-                    idx = oi;
-                }
-            }
-            const int piv = __builtin_amdgcn_readfirstlane(idx);
+            // pivot: the largest |a_rk| among rows not yet used (NaN counts as 0)
+            const int piv = pivot_lane(used, v.re * v.re + v.im * v.im, lane);
             const c64 pv = {__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.re), piv)),
                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.im), piv))};
             const float d = pv.re * pv.re + pv.im * pv.im;
