@@ -388,7 +388,11 @@ static chaff_status spmm_launch(const int64_t* row_ptr, const int32_t* col_idx, 
         const int t = (!DIAG && MODE == 0 && std::is_same<CZ, CX>::value && std::is_same<CX, CY>::value)
                           ? tuned_variant(NB, n, nnzb, s, std::is_same<CZ, c64>::value ? CHAFF_C64 : CHAFF_C128)
                           : -1;
-        variant = t >= 0 ? t : (DIAG ? (s == 1 ? 0 : 1) : default_variant(s));
+        // wide products of mixed precision (the FP64 residual, the FP64 guess) are not in the
+        // tuning table: one wave per block row with the block staged in LDS, as the tuned
+        // complex64 product at these widths
+        const bool wide = !DIAG && NB2 <= 64 && s >= 32;
+        variant = t >= 0 ? t : (DIAG ? (s == 1 ? 0 : 1) : wide ? 7 : default_variant(s));
     }
     if (variant == 0) {
         dim3 grid((unsigned)((n * NB + 255) / 256), (unsigned)s);
@@ -872,21 +876,28 @@ __global__ void k_cg_alpha(int64_t nsys, const c128* __restrict__ pq, CgState* _
     cg[t] = S;
 }
 
-// x64[:, colmap[c]] += scale(system) * xc[:, c] for the s_cur current columns,
-// then xc = 0 (the correction restarts from zero).
+
+// Compaction flush: x64 += scale * (xc + alpha p), i.e. the deferred x update of
+// the last step followed by the flush of the accumulated correction, in one
+// pass (the same roundings as applying them one after the other).
 template <typename C>
-__global__ void k_add_scaled(const int32_t* __restrict__ wire_cloud, const double* __restrict__ scale,
-                             const int32_t* __restrict__ colmap, int64_t n_rows, int64_t s_cur, int64_t s_full,
-                             C* __restrict__ xc, c128* __restrict__ x) {
+__global__ void k_cg_flush(const int32_t* __restrict__ wire_cloud, const CgState* __restrict__ cg,
+                           const double* __restrict__ scale, const int32_t* __restrict__ colmap, int64_t n_rows,
+                           int64_t s_cur, int64_t s_full, const C* __restrict__ p, const C* __restrict__ xc,
+                           c128* __restrict__ x) {
+    using R = typename real_of<C>::type;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_rows * s_cur) return;
     const int64_t row = t / s_cur, rr = t - (t / s_cur) * s_cur;
+    const int64_t cl = wire_cloud[row / NB];
+    const CgState& S = cg[cl * s_cur + rr];
+    cplx<R> xv = xc[t];
+    cfma(xv, cplx<R>{(R)S.alpha_re, (R)S.alpha_im}, p[t]);
     const int64_t col = colmap[rr];
-    const double f = scale[(int64_t)wire_cloud[row / NB] * s_full + col];
-    const c128 v = ccast<c128>(xc[t]);
+    const double f = scale[cl * s_full + col];
+    const c128 v = ccast<c128>(xv);
     c128& xo = x[row * s_full + col];
     xo = c128{xo.re + f * v.re, xo.im + f * v.im};
-    xc[t] = C{0, 0};
 }
 
 // dst[row][j] = src[row][keep[j]] (column compaction of a row-major [rows][s] block)
@@ -1107,19 +1118,6 @@ __global__ __launch_bounds__(RB) void k_cg_pdir(const Chunk* __restrict__ chunks
     }
 }
 
-// x += alpha p (the deferred update of the last step, before a flush)
-template <typename C>
-__global__ void k_cg_xpend(const int32_t* __restrict__ wire_cloud, const CgState* __restrict__ cg, int64_t n_rows,
-                           int64_t s, const C* __restrict__ p, C* __restrict__ x) {
-    using R = typename real_of<C>::type;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_rows * s) return;
-    const int64_t row = t / s, rr = t - (t / s) * s;
-    const CgState& S = cg[(int64_t)wire_cloud[row / NB] * s + rr];
-    cplx<R> xv = x[t];
-    cfma(xv, cplx<R>{(R)S.alpha_re, (R)S.alpha_im}, p[t]);
-    x[t] = xv;
-}
 
 // r -= alpha q ; z = P_i r (not stored) ; partial r^T z and ||r||^2
 template <typename CZ, typename C, int ST>
@@ -1714,28 +1712,42 @@ static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& 
 template <typename C>
 static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc, const SolveLayout& L,
                                  std::vector<int32_t>& colmap, const std::vector<int32_t>& keep, int64_t s_full,
-                                 C* xc, C* r, C* p, C* q, bool q_live, hipStream_t st) {
+                                 C*& xc, C*& r, C*& p, C*& q, bool q_live, hipStream_t st) {
     const int64_t rows = cs.rows, s_old = cs.s, s_new = (int64_t)keep.size();
-    ProfScope ps("cocg_compact", st, (double)rows * s_old * sizeof(C) * 5 + 2.0 * rows * s_new * sizeof(C) * 3);
-    hipLaunchKernelGGL((k_cg_xpend<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
-                       (const int32_t*)c->wire_cloud, (const CgState*)L.cg, rows, s_old, (const C*)p, xc);
-    CHAFF_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_add_scaled<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
-                       (const int32_t*)c->wire_cloud, (const double*)L.rn, (const int32_t*)L.colmap, rows, s_old,
-                       s_full, xc, L.x);
+    ProfScope ps("cocg_compact", st,
+                 (double)rows * s_old * (2.0 * sizeof(C) + 2.0 * sizeof(c128)) +
+                     (double)rows * (s_old + s_new) * sizeof(C) * (q_live ? 3 : 2) + (double)rows * s_new * sizeof(C));
+    // flush every column's correction (with the deferred update of the last step) into the FP64 solution
+    hipLaunchKernelGGL((k_cg_flush<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
+                       (const int32_t*)c->wire_cloud, (const CgState*)L.cg, (const double*)L.rn,
+                       (const int32_t*)L.colmap, rows, s_old, s_full, (const C*)p, (const C*)xc, L.x);
     CHAFF_LAUNCH_CHECK();
     CHAFF_HIP(hipMemcpyAsync(L.keep, keep.data(), s_new * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    // xc was flushed and zeroed above: it is the staging buffer of the gathers
-    // and is cleared again afterwards.
-    for (C* v : {r, p, q}) {
-        if (v == q && !q_live) continue;   // q is rebuilt by the next product
-        hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)v, rows,
-                           s_old, (const int32_t*)L.keep, s_new, xc);
+    // the live columns move into the buffer freed before them (xc, then r, then p): no copies back
+    C* const bx = xc;
+    C* const br = r;
+    C* const bp = p;
+    C* const bq = q;
+    hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)br, rows, s_old,
+                       (const int32_t*)L.keep, s_new, bx);
+    CHAFF_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)bp, rows, s_old,
+                       (const int32_t*)L.keep, s_new, br);
+    CHAFF_LAUNCH_CHECK();
+    r = bx;
+    p = br;
+    if (q_live) {   // z kept in q between the update and the direction pass
+        hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)bq, rows,
+                           s_old, (const int32_t*)L.keep, s_new, bp);
         CHAFF_LAUNCH_CHECK();
-        CHAFF_HIP(hipMemcpyAsync(v, xc, (size_t)rows * s_new * sizeof(C), hipMemcpyDeviceToDevice, st));
+        q = bp;
+        xc = bq;
+    } else {        // q is rebuilt by the next product
+        q = bp;
+        xc = bq;
     }
-    {
-        const int64_t words = rows * s_old * (int64_t)sizeof(C) / 4;
+    {   // the new correction starts at zero
+        const int64_t words = rows * s_new * (int64_t)sizeof(C) / 4;
         hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(words)), dim3(256), 0, st, (uint32_t*)xc, words);
         CHAFF_LAUNCH_CHECK();
     }
@@ -1980,13 +1992,10 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
                            L.cg);
         CHAFF_LAUNCH_CHECK();
     }
-    // the deferred x update of the last step, then x64 += scale * xc
-    hipLaunchKernelGGL((k_cg_xpend<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
-                       (const int32_t*)c->wire_cloud, (const CgState*)L.cg, rows, cs.s, (const C*)p, xc);
-    CHAFF_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_add_scaled<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
-                       (const int32_t*)c->wire_cloud, (const double*)L.rn, (const int32_t*)L.colmap, rows, cs.s, s,
-                       xc, L.x);
+    // the deferred x update of the last step, then x64 += scale * xc (one pass)
+    hipLaunchKernelGGL((k_cg_flush<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
+                       (const int32_t*)c->wire_cloud, (const CgState*)L.cg, (const double*)L.rn,
+                       (const int32_t*)L.colmap, rows, cs.s, s, (const C*)p, (const C*)xc, L.x);
     CHAFF_LAUNCH_CHECK();
     return CHAFF_OK;
 }
