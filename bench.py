@@ -76,6 +76,22 @@ def measured_traffic(config: str, kernel: str):
         return None
     return ent["hbm_bytes_per_launch"]
 
+MFMA_FILE = os.path.join(ROOT, "profiles", "mfma_counters.json")
+
+
+def measured_mfma(config: str, kernel: str):
+    """MFMA busy fraction and counted MFMA flop per launch from the committed counter run,
+    or None unless the record matches this workload and the kernel source is unchanged."""
+    try:
+        with open(MFMA_FILE) as f:
+            ent = json.load(f).get(config, {}).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not ent or "source" not in ent or ent.get("source_sha256_16") != source_hash(ent["source"]):
+        return None
+    return ent
+
+
 CONFIGS = {
     # prec: Krylov/fill precision; method: Krylov method per refinement cycle;
     # restart: GMRES cycle length or COCG step cap; inner_tol: reduction per cycle
@@ -600,6 +616,10 @@ def main(argv=None) -> int:
         mfma = {"spmm", "spmm_narrow", "nbhd_apply", "nbhd_apply_narrow"} | ({"k_cg_update"} if pc == "cluster" else set())
         roof = roofline_of(k, prec == B.C64 and name in mfma)
         roof["traffic"] = measured_traffic(a.config, name)
+        mc = measured_mfma(a.config, name)
+        if mc is not None:   # matrix-core counters of the same kernel (profiles/mfma_counters.json)
+            roof["mfma_busy"] = mc["mfma_busy_fraction"]
+            roof["mfma_flop_counted_per_launch"] = mc["mfma_flop"]
         symbols = dict(KERNEL_SYMBOLS)
         if pc == "cluster":   # the cluster path runs its own update and direction kernels
             symbols.update({"k_cg_update": ("chaff::kr7::k_cg_update_cl", KERNEL_SYMBOLS["k_cg_update"][1]),

@@ -891,7 +891,7 @@ __global__ void k_cg_flush(const int32_t* __restrict__ wire_cloud, const CgState
     const int64_t row = t / s_cur, rr = t - (t / s_cur) * s_cur;
     const int64_t cl = wire_cloud[row / NB];
     const CgState& S = cg[cl * s_cur + rr];
-    cplx<R> xv = xc[t];
+    cplx<R> xv = xc ? xc[t] : cplx<R>{0, 0};   // no xc: nothing accumulated yet this cycle
     cfma(xv, cplx<R>{(R)S.alpha_re, (R)S.alpha_im}, p[t]);
     const int64_t col = colmap[rr];
     const double f = scale[cl * s_full + col];
@@ -908,6 +908,30 @@ __global__ void k_gather_cols(const C* __restrict__ src, int64_t n_rows, int64_t
     if (t >= n_rows * s_dst) return;
     const int64_t row = t / s_dst, j = t - (t / s_dst) * s_dst;
     dst[t] = src[row * s_src + keep[j]];
+}
+
+// dst[row][keep[j]] = src[row][j] (the inverse of k_gather_cols; other columns untouched)
+template <typename C>
+__global__ void k_scatter_cols(const C* __restrict__ src, int64_t n_rows, int64_t s_src,
+                               const int32_t* __restrict__ keep, int64_t s_dst, C* __restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s_src) return;
+    const int64_t row = t / s_src, j = t - (t / s_src) * s_src;
+    dst[row * s_dst + keep[j]] = src[t];
+}
+
+// V0[row][j] = Rv[row][keep[j]] * inv_rn[cloud][keep[j]]: the start vector of a
+// COCG cycle restricted to the columns that still hold a live system
+template <typename C>
+__global__ void k_start_vector_cols(const c128* __restrict__ Rv, const int32_t* __restrict__ wire_cloud,
+                                    const double* __restrict__ inv_rn, int64_t n_rows, int64_t s_full,
+                                    const int32_t* __restrict__ keep, int64_t s_new, C* __restrict__ V0) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows * s_new) return;
+    const int64_t row = t / s_new, j = t - (t / s_new) * s_new;
+    const int64_t col = keep[j];
+    const int c = wire_cloud[row / NB];
+    V0[t] = ccast<C>(cscale(Rv[row * s_full + col], inv_rn[(int64_t)c * s_full + col]));
 }
 
 template <typename T>
@@ -931,20 +955,23 @@ __global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_
 // HBM latency of the Z stream overlaps the arithmetic; lane (group g, column
 // c) applies block columns k = g, g + G, ... (G = 64/S) to RHS column c, and
 // the G partial sums are combined with cross-lane adds.  sigma = p^T q is
-// reduced per tile in FP64 (tpart[tile][r]), with the row's own p taken from
-// the registers that gathered its diagonal block (no second read of p); two
-// fixed-order passes then sum
+// reduced per tile in FP64 (tpart[tile][r]); a row's blocks are applied in
+// rotated order, from the one after the diagonal block round to the diagonal
+// block itself, so the row's own p is still in the registers that gathered
+// that last slab (no second read of p).  Two fixed-order passes then sum
 // tiles per group and groups per cloud.  The gathers of p are latency bound:
 // complex64 tiles ask the compiler for at least six waves per SIMD (the
 // 64-column MFMA tile fits 60 registers: eight waves); complex128 tiles would
-// spill under that bound.
+// spill under that bound.  Gathering the next block's slab during the current
+// block's MFMAs measured no faster at C5 (it costs one wave per SIMD).
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 constexpr int COCG_TILE_ROWS = RB / 64;
 template <typename CZ, typename C, int S>
 __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(sizeof(C) == sizeof(c64) && NB == 7 ? 6 : 1)))
 void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles, int xcd_order,
-                 const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx, const CZ* __restrict__ Z,
-                 const C* __restrict__ P, C* __restrict__ Q, int64_t s, c128* __restrict__ tpart) {
+                 const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                 const int64_t* __restrict__ diag_pos, const CZ* __restrict__ Z, const C* __restrict__ P,
+                 C* __restrict__ Q, int64_t s, c128* __restrict__ tpart) {
     using R = typename real_of<C>::type;
     constexpr int G = 64 / S;
     constexpr int KK = (NB + G - 1) / G;
@@ -988,38 +1015,36 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
         for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
         f32x4_t mr[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         f32x4_t mi[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-        // the row's own p slab, kept from the gather of the diagonal block for p^T q
-        // (the lane writing row q holds p_q there: q % G == g, at kk = q / G)
-        cplx<R> xd[KK];
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) xd[kk] = {0, 0};
+        // blocks in rotated order, the diagonal block last: its slab (the row's
+        // own p, for p^T q) is then still in the registers after the loop
         const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+        const int64_t ne = e1 - e0, ed = diag_pos[i];
+        int64_t e = ed + 1 < e1 ? ed + 1 : e0;
         // lane l stages entries l, l + 64, ... of each block (ZPL per lane)
         CZ zn[ZPL];
+        cplx<R> x[KK];
 #pragma unroll
         for (int u = 0; u < ZPL; ++u)
-            zn[u] = (lane + 64 * u < NB2 && e0 < e1) ? Z[e0 * NB2 + lane + 64 * u] : CZ{0, 0};
-        for (int64_t e = e0; e < e1; ++e) {
-            const int buf = (int)((e - e0) & 1);
+            zn[u] = (lane + 64 * u < NB2 && ne > 0) ? Z[e * NB2 + lane + 64 * u] : CZ{0, 0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) x[kk] = {0, 0};
+        for (int64_t j = 0; j < ne; ++j) {
+            const int buf = (int)(j & 1);
 #pragma unroll
             for (int u = 0; u < ZPL; ++u)
                 if (lane + 64 * u < NB2) zs[w][buf][lane + 64 * u] = zn[u];
-            if (e + 1 < e1) {
+            const int64_t ce = col_idx[e];
+            e = e + 1 < e1 ? e + 1 : e0;
+            if (j + 1 < ne) {
 #pragma unroll
                 for (int u = 0; u < ZPL; ++u)
-                    if (lane + 64 * u < NB2) zn[u] = Z[(e + 1) * NB2 + lane + 64 * u];
+                    if (lane + 64 * u < NB2) zn[u] = Z[e * NB2 + lane + 64 * u];
             }
-            const int64_t ce = col_idx[e];
             const C* xb = P + ce * NB * s + rc;
-            cplx<R> x[KK];
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 const int k = g + kk * G;
                 x[kk] = k < NB ? ccast<cplx<R>>(xb[k * s]) : cplx<R>{0, 0};
-            }
-            if (ce == i) {   // wave-uniform: the diagonal block
-#pragma unroll
-                for (int kk = 0; kk < KK; ++kk) xd[kk] = x[kk];
             }
             // the block written above by this wave's lanes is visible to all of its lanes
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1067,7 +1092,7 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
                 if (q % G != g) continue;
                 const int64_t o = (i * NB + q) * s + r;
                 Q[o] = ccast<C>(acc[q]);
-                cfma(dot, ccast<c128>(xd[q / G]), ccast<c128>(acc[q]));
+                cfma(dot, ccast<c128>(x[q / G]), ccast<c128>(acc[q]));
             }
         }
     }
@@ -1166,10 +1191,12 @@ __global__ __launch_bounds__(RB) void k_cg_update(const Chunk* __restrict__ chun
 
 // r -= alpha q ; partial ||r||^2 (slot0).  The neighbourhood-inverse
 // preconditioner forms z = M r and r^T z in a block-sparse product of its own.
+// first: the first step of a cycle (alpha = 0), where only the norm is formed
+// and q, which holds nothing yet, is not read.
 template <typename C, int ST>
 __global__ __launch_bounds__(RB) void k_cg_rupd(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
                                                 const C* __restrict__ q, C* __restrict__ rv, int64_t s,
-                                                c128* __restrict__ part, int nslot, int slot0) {
+                                                c128* __restrict__ part, int nslot, int slot0, int first) {
     using R = typename real_of<C>::type;
     __shared__ c128 red[RB];
     const Chunk ch = chunks[blockIdx.x];
@@ -1185,12 +1212,14 @@ __global__ __launch_bounds__(RB) void k_cg_rupd(const Chunk* __restrict__ chunks
             for (int k = 0; k < NB; ++k) {   // issue all loads before any arithmetic
                 const int64_t o = (i * NB + k) * s + r;
                 res[k] = rv[o];
-                qv[k] = q[o];
+                if (!first) qv[k] = q[o];
             }
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
-                cfma(res[k], na, qv[k]);
-                rv[(i * NB + k) * s + r] = res[k];
+                if (!first) {
+                    cfma(res[k], na, qv[k]);
+                    rv[(i * NB + k) * s + r] = res[k];
+                }
                 rr.re += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
             }
         }
@@ -1383,12 +1412,15 @@ void k_cg_update_cl(const Chunk* __restrict__ chunks, const CgState* __restrict_
     }
 }
 
-// Cluster preconditioner form of k_cg_pdir: z was stored by k_cg_update_cl.
-//   x += alpha p_old (deferred; skipped with pend = 0), p = z + beta p_old.
+// Form of k_cg_pdir where z was stored by the update (cluster) or by its own
+// product (neighbourhood inverse):
+//   x += alpha p_old (deferred; skipped with pend = 0; with pend = 2 x holds
+//   nothing yet and is written as alpha p_old), p = z + beta p_old (with
+//   pfirst, the first step of a cycle, p = z: p_old holds nothing yet).
 template <typename C, int ST>
 __global__ __launch_bounds__(RB) void k_cg_pdir_z(const Chunk* __restrict__ chunks, const CgState* __restrict__ cg,
                                                   const C* __restrict__ z, C* __restrict__ p, C* __restrict__ x,
-                                                  int64_t s, int pend) {
+                                                  int64_t s, int pend, int pfirst) {
     using R = typename real_of<C>::type;
     const Chunk ch = chunks[blockIdx.x];
     const int rsub = ST == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / ST);
@@ -1397,12 +1429,16 @@ __global__ __launch_bounds__(RB) void k_cg_pdir_z(const Chunk* __restrict__ chun
     const CgState& S = cg[(int64_t)ch.cloud * s + r];
     const cplx<R> a = {pend ? (R)S.alpha_re : (R)0, pend ? (R)S.alpha_im : (R)0};
     const cplx<R> b = {(R)S.beta_re, (R)S.beta_im};
+    if (pfirst) {
+        for (int64_t row = ch.w0 * NB + rsub; row < ch.w1 * NB; row += RB / ST) p[row * s + r] = z[row * s + r];
+        return;
+    }
     for (int64_t row = ch.w0 * NB + rsub; row < ch.w1 * NB; row += RB / ST) {
         const int64_t o = row * s + r;
         const cplx<R> pv = p[o];
         cplx<R> zv = z[o];
         if (pend) {
-            cplx<R> xv = x[o];
+            cplx<R> xv = pend == 2 ? cplx<R>{0, 0} : x[o];
             cfma(xv, a, pv);
             x[o] = xv;
         }
@@ -1671,10 +1707,10 @@ static void launch_cg_pdir(const SolveShape& sh, SolveLayout& L, const CZ* Pinv,
                        Pinv, r, p, x, sh.s, pend);
 }
 template <typename C, int ST>
-static void launch_cg_rupd(const SolveShape& sh, SolveLayout& L, const C* q, C* r, hipStream_t st) {
+static void launch_cg_rupd(const SolveShape& sh, SolveLayout& L, const C* q, C* r, bool first, hipStream_t st) {
     const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
     hipLaunchKernelGGL((k_cg_rupd<C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const CgState*)L.cg, q, r,
-                       sh.s, L.part, sh.nslot, 1);
+                       sh.s, L.part, sh.nslot, 1, first ? 1 : 0);
 }
 template <typename CZ, typename C, int ST>
 static void launch_cg_update_cl(const SolveShape& sh, SolveLayout& L, const CZ* Mb, C* qz, C* r, hipStream_t st) {
@@ -1685,11 +1721,11 @@ static void launch_cg_update_cl(const SolveShape& sh, SolveLayout& L, const CZ* 
     }
 }
 template <typename C, int ST>
-static void launch_cg_pdir_z(const SolveShape& sh, SolveLayout& L, const C* z, C* p, C* x, int pend,
+static void launch_cg_pdir_z(const SolveShape& sh, SolveLayout& L, const C* z, C* p, C* x, int pend, bool pfirst,
                              hipStream_t st) {
     const dim3 grid(sh.n_chunks, (unsigned)((sh.s + ST - 1) / ST));
     hipLaunchKernelGGL((k_cg_pdir_z<C, ST>), grid, dim3(RB), 0, st, (const Chunk*)L.chunks, (const CgState*)L.cg,
-                       z, p, x, sh.s, pend);
+                       z, p, x, sh.s, pend, pfirst ? 1 : 0);
 }
 template <typename CZ, typename C, int ST>
 static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& L, const CZ* Z, const C* p, C* q,
@@ -1699,8 +1735,12 @@ static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& 
     const int64_t nblk = sh.cocg_xcd ? per_xcd * NXCD * ct : sh.n_tiles * ct;
     hipLaunchKernelGGL((k_cocg_spmm<CZ, C, ST>), dim3((unsigned)nblk), dim3(RB), 0, st,
                        (const Chunk*)L.tiles, sh.n_tiles, ct, sh.cocg_xcd, (const int64_t*)c->row_ptr,
-                       (const int32_t*)c->col_idx, Z, p, q, sh.s, L.tpart);
+                       (const int32_t*)c->col_idx, (const int64_t*)c->diag_pos, Z, p, q, sh.s, L.tpart);
 }
+
+static chaff_status cocg_narrow_shape(const Cloud* c, SolveShape& cs, SolveLayout& Lc, const SolveLayout& L,
+                                      std::vector<int32_t>& colmap, const std::vector<int32_t>& keep,
+                                      hipStream_t st);
 
 // Column compaction inside a COCG cycle: once at most half of the current
 // RHS tile width still has a system above its checkpoint, the finished
@@ -1712,16 +1752,21 @@ static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& 
 template <typename C>
 static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc, const SolveLayout& L,
                                  std::vector<int32_t>& colmap, const std::vector<int32_t>& keep, int64_t s_full,
-                                 C*& xc, C*& r, C*& p, C*& q, bool q_live, hipStream_t st) {
+                                 C*& xc, C*& r, C*& p, C*& q, bool q_live, bool xc_valid, bool p_valid,
+                                 hipStream_t st) {
     const int64_t rows = cs.rows, s_old = cs.s, s_new = (int64_t)keep.size();
     ProfScope ps("cocg_compact", st,
                  (double)rows * s_old * (2.0 * sizeof(C) + 2.0 * sizeof(c128)) +
                      (double)rows * (s_old + s_new) * sizeof(C) * (q_live ? 3 : 2) + (double)rows * s_new * sizeof(C));
-    // flush every column's correction (with the deferred update of the last step) into the FP64 solution
-    hipLaunchKernelGGL((k_cg_flush<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
-                       (const int32_t*)c->wire_cloud, (const CgState*)L.cg, (const double*)L.rn,
-                       (const int32_t*)L.colmap, rows, s_old, s_full, (const C*)p, (const C*)xc, L.x);
-    CHAFF_LAUNCH_CHECK();
+    // flush every column's correction (with the deferred update of the last step) into the FP64 solution;
+    // before the first search direction there is nothing to flush (alpha is still 0)
+    if (p_valid) {
+        hipLaunchKernelGGL((k_cg_flush<C>), dim3(blocks_for(rows * s_old)), dim3(256), 0, st,
+                           (const int32_t*)c->wire_cloud, (const CgState*)L.cg, (const double*)L.rn,
+                           (const int32_t*)L.colmap, rows, s_old, s_full, (const C*)p,
+                           xc_valid ? (const C*)xc : (const C*)nullptr, L.x);
+        CHAFF_LAUNCH_CHECK();
+    }
     CHAFF_HIP(hipMemcpyAsync(L.keep, keep.data(), s_new * sizeof(int32_t), hipMemcpyHostToDevice, st));
     // the live columns move into the buffer freed before them (xc, then r, then p): no copies back
     C* const bx = xc;
@@ -1731,9 +1776,11 @@ static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc
     hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)br, rows, s_old,
                        (const int32_t*)L.keep, s_new, bx);
     CHAFF_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)bp, rows, s_old,
-                       (const int32_t*)L.keep, s_new, br);
-    CHAFF_LAUNCH_CHECK();
+    if (p_valid) {
+        hipLaunchKernelGGL((k_gather_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st, (const C*)bp, rows,
+                           s_old, (const int32_t*)L.keep, s_new, br);
+        CHAFF_LAUNCH_CHECK();
+    }
     r = bx;
     p = br;
     if (q_live) {   // z kept in q between the update and the direction pass
@@ -1751,6 +1798,15 @@ static chaff_status cocg_compact(const Cloud* c, SolveShape& cs, SolveLayout& Lc
         hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(words)), dim3(256), 0, st, (uint32_t*)xc, words);
         CHAFF_LAUNCH_CHECK();
     }
+    return cocg_narrow_shape(c, cs, Lc, L, colmap, keep, st);
+}
+
+// The recurrence states, the column map and the tile set of a COCG cycle
+// switch to the columns in keep (uploaded to L.keep by the caller).
+static chaff_status cocg_narrow_shape(const Cloud* c, SolveShape& cs, SolveLayout& Lc, const SolveLayout& L,
+                                      std::vector<int32_t>& colmap, const std::vector<int32_t>& keep,
+                                      hipStream_t st) {
+    const int64_t s_old = cs.s, s_new = (int64_t)keep.size();
     hipLaunchKernelGGL((k_gather_sys<CgState>), dim3(blocks_for((int64_t)cs.n_clouds * s_new, 64)), dim3(64), 0, st,
                        (const CgState*)L.cg, cs.n_clouds, s_old, (const int32_t*)L.keep, s_new, L.cg2);
     CHAFF_LAUNCH_CHECK();
@@ -1819,15 +1875,53 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     hipLaunchKernelGGL(k_cg_cycle_start, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, (const double*)L.target,
                        (const double*)L.h2, (const int32_t*)L.active, first ? 1 : 0, L.cg);
     CHAFF_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_start_vector<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.r,
-                       (const int32_t*)c->wire_cloud, (const double*)L.inv_rn, sh.n_clouds, rows, s, r);
-    CHAFF_LAUNCH_CHECK();
-    const int64_t words = vs * (int64_t)sizeof(C) / 4;
-    hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(words)), dim3(256), 0, st, (uint32_t*)xc, words);
-    CHAFF_LAUNCH_CHECK();
-    if (first || !use_rr) {   // p and q enter the first step multiplied by zero: they must be finite
-        hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(2 * words)), dim3(256), 0, st, (uint32_t*)p, 2 * words);
+    // With the neighbourhood inverse a fresh recurrence skips the passes that
+    // only carry zeros: x_c, p and q are not cleared, the first step forms
+    // ||r||^2 without the update r -= 0 q, sets p = z without reading p, and
+    // the first correction is written as alpha p rather than added to x_c.
+    const bool lazy = nbhd && !use_rr;   // (COCG_RR carries p and q into the next cycle)
+    bool xc_valid = !lazy, p_valid = !lazy;
+    // columns that hold a live system: with at most half a tile of them the
+    // cycle starts compacted (the rule of the compaction inside the cycle)
+    std::vector<int32_t> live;
+    for (int64_t j = 0; j < s; ++j) {
+        bool lv = false;
+        for (int cl = 0; cl < sh.n_clouds && !lv; ++cl) lv = act[(size_t)cl * s + j] != 0;
+        if (lv) live.push_back((int32_t)j);
+    }
+    if (compact && !live.empty() && (int64_t)live.size() <= spmm_tile_width(s) / 2) {
+        const int64_t s_new = (int64_t)live.size();
+        CHAFF_HIP(hipMemcpyAsync(L.keep, live.data(), s_new * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL((k_start_vector_cols<C>), dim3(blocks_for(rows * s_new)), dim3(256), 0, st,
+                           (const c128*)L.r, (const int32_t*)c->wire_cloud, (const double*)L.inv_rn, rows, s,
+                           (const int32_t*)L.keep, s_new, r);
         CHAFF_LAUNCH_CHECK();
+        if (!lazy) {
+            const int64_t words = rows * s_new * (int64_t)sizeof(C) / 4;
+            hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(words)), dim3(256), 0, st, (uint32_t*)xc, words);
+            CHAFF_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(words)), dim3(256), 0, st, (uint32_t*)p, words);
+            CHAFF_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(words)), dim3(256), 0, st, (uint32_t*)q, words);
+            CHAFF_LAUNCH_CHECK();
+        }
+        chaff_status cst = cocg_narrow_shape(c, cs, Lc, L, colmap, live, st);
+        if (cst != CHAFF_OK) return cst;
+        if (g_verbose)
+            std::fprintf(stderr, "[chaff] cocg cycle starts on %lld columns\n", (long long)cs.s);
+    } else {
+        hipLaunchKernelGGL((k_start_vector<C>), dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.r,
+                           (const int32_t*)c->wire_cloud, (const double*)L.inv_rn, sh.n_clouds, rows, s, r);
+        CHAFF_LAUNCH_CHECK();
+        const int64_t words = vs * (int64_t)sizeof(C) / 4;
+        if (!lazy) {
+            hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(words)), dim3(256), 0, st, (uint32_t*)xc, words);
+            CHAFF_LAUNCH_CHECK();
+        }
+        if ((first || !use_rr) && !lazy) {   // p and q enter the first step multiplied by zero: they must be finite
+            hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(2 * words)), dim3(256), 0, st, (uint32_t*)p, 2 * words);
+            CHAFF_LAUNCH_CHECK();
+        }
     }
     CHAFF_HIP(hipStreamSynchronize(st));   // host staging vectors may leave scope
     int mode = (first || !use_rr) ? 0 : 2;
@@ -1836,17 +1930,19 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
     std::vector<int32_t> flags;
     for (int k = 0; k <= o->restart; ++k) {
         const int wst = spmm_tile_width(cs.s);
+        const bool first_step = lazy && k == 0;   // alpha = 0 and q holds nothing yet
         if (nbhd) {   // r -= alpha q, ||r||^2; then z = M r (over q) with per-tile r^T z
             {
-                ProfScope pu(wst == 64 ? "k_cg_rupd" : "k_cg_rupd_narrow", st, (3.0 * rows * cs.s) * sizeof(C));
+                ProfScope pu(wst == 64 ? "k_cg_rupd" : "k_cg_rupd_narrow", st,
+                             ((first_step ? 1.0 : 3.0) * rows * cs.s) * sizeof(C));
                 switch (wst) {
-                    case 1: launch_cg_rupd<C, 1>(cs, Lc, q, r, st); break;
-                    case 2: launch_cg_rupd<C, 2>(cs, Lc, q, r, st); break;
-                    case 4: launch_cg_rupd<C, 4>(cs, Lc, q, r, st); break;
-                    case 8: launch_cg_rupd<C, 8>(cs, Lc, q, r, st); break;
-                    case 16: launch_cg_rupd<C, 16>(cs, Lc, q, r, st); break;
-                    case 32: launch_cg_rupd<C, 32>(cs, Lc, q, r, st); break;
-                    default: launch_cg_rupd<C, 64>(cs, Lc, q, r, st); break;
+                    case 1: launch_cg_rupd<C, 1>(cs, Lc, q, r, first_step, st); break;
+                    case 2: launch_cg_rupd<C, 2>(cs, Lc, q, r, first_step, st); break;
+                    case 4: launch_cg_rupd<C, 4>(cs, Lc, q, r, first_step, st); break;
+                    case 8: launch_cg_rupd<C, 8>(cs, Lc, q, r, first_step, st); break;
+                    case 16: launch_cg_rupd<C, 16>(cs, Lc, q, r, first_step, st); break;
+                    case 32: launch_cg_rupd<C, 32>(cs, Lc, q, r, first_step, st); break;
+                    default: launch_cg_rupd<C, 64>(cs, Lc, q, r, first_step, st); break;
                 }
             }
             CHAFF_LAUNCH_CHECK();
@@ -1925,9 +2021,11 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
                 if (live) keep.push_back((int32_t)j);
             }
             if (!keep.empty() && (int64_t)keep.size() <= wst / 2) {
-                chaff_status cst = cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, p, q, zq, st);
+                chaff_status cst =
+                    cocg_compact<C>(c, cs, Lc, L, colmap, keep, s, xc, r, p, q, zq, xc_valid, p_valid, st);
                 if (cst != CHAFF_OK) return cst;
                 pending_applied = true;
+                xc_valid = true;   // the compaction clears the new x_c
                 if (g_verbose)
                     std::fprintf(stderr, "[chaff] cocg step %d: compacted to %lld columns\n", k, (long long)cs.s);
             }
@@ -1935,19 +2033,22 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         mode = 1;
         ++iters;
         if (zq) {   // x += alpha p_old (deferred), p = z + beta p_old
-            const int pend = pending_applied ? 0 : 1;
+            const bool pfirst = !p_valid;   // the first direction: p = z, nothing to add to x
+            const int pend = (pending_applied || pfirst) ? 0 : (xc_valid ? 1 : 2);
             pending_applied = false;
+            p_valid = true;
+            if (pend == 2) xc_valid = true;
             ProfScope pp(spmm_tile_width(cs.s) == 64 ? "k_cg_p" : "k_cg_p_narrow", st,
-                         (3.0 + 2.0 * pend) * rows * cs.s * sizeof(C));
+                         (pfirst ? 2.0 : 3.0 + (pend == 2 ? 1.0 : 2.0 * pend)) * rows * cs.s * sizeof(C));
             const C* zc = q;
             switch (spmm_tile_width(cs.s)) {
-                case 1: launch_cg_pdir_z<C, 1>(cs, Lc, zc, p, xc, pend, st); break;
-                case 2: launch_cg_pdir_z<C, 2>(cs, Lc, zc, p, xc, pend, st); break;
-                case 4: launch_cg_pdir_z<C, 4>(cs, Lc, zc, p, xc, pend, st); break;
-                case 8: launch_cg_pdir_z<C, 8>(cs, Lc, zc, p, xc, pend, st); break;
-                case 16: launch_cg_pdir_z<C, 16>(cs, Lc, zc, p, xc, pend, st); break;
-                case 32: launch_cg_pdir_z<C, 32>(cs, Lc, zc, p, xc, pend, st); break;
-                default: launch_cg_pdir_z<C, 64>(cs, Lc, zc, p, xc, pend, st); break;
+                case 1: launch_cg_pdir_z<C, 1>(cs, Lc, zc, p, xc, pend, pfirst, st); break;
+                case 2: launch_cg_pdir_z<C, 2>(cs, Lc, zc, p, xc, pend, pfirst, st); break;
+                case 4: launch_cg_pdir_z<C, 4>(cs, Lc, zc, p, xc, pend, pfirst, st); break;
+                case 8: launch_cg_pdir_z<C, 8>(cs, Lc, zc, p, xc, pend, pfirst, st); break;
+                case 16: launch_cg_pdir_z<C, 16>(cs, Lc, zc, p, xc, pend, pfirst, st); break;
+                case 32: launch_cg_pdir_z<C, 32>(cs, Lc, zc, p, xc, pend, pfirst, st); break;
+                default: launch_cg_pdir_z<C, 64>(cs, Lc, zc, p, xc, pend, pfirst, st); break;
             }
         } else {   // x += alpha p_old (deferred), p = P r + beta p_old
             const int pend = pending_applied ? 0 : 1;
@@ -1993,10 +2094,13 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         CHAFF_LAUNCH_CHECK();
     }
     // the deferred x update of the last step, then x64 += scale * xc (one pass)
-    hipLaunchKernelGGL((k_cg_flush<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
-                       (const int32_t*)c->wire_cloud, (const CgState*)L.cg, (const double*)L.rn,
-                       (const int32_t*)L.colmap, rows, cs.s, s, (const C*)p, (const C*)xc, L.x);
-    CHAFF_LAUNCH_CHECK();
+    if (p_valid) {
+        hipLaunchKernelGGL((k_cg_flush<C>), dim3(blocks_for(rows * cs.s)), dim3(256), 0, st,
+                           (const int32_t*)c->wire_cloud, (const CgState*)L.cg, (const double*)L.rn,
+                           (const int32_t*)L.colmap, rows, cs.s, s, (const C*)p,
+                           xc_valid ? (const C*)xc : (const C*)nullptr, L.x);
+        CHAFF_LAUNCH_CHECK();
+    }
     return CHAFF_OK;
 }
 
@@ -2278,20 +2382,56 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     bool converged = false;
     std::vector<double> hinv(nsys), hrn(nsys), cocg_scale;
     std::vector<SysState> hsys(nsys);
+    // columns the last COCG cycle worked on: only their solutions changed
+    std::vector<int32_t> last_live;
     for (;;) {
         // true residual r = b - Z x (FP64 accumulation over the stored Z)
+        const int64_t u = (int64_t)last_live.size();
         if (cycles == 0 && o->use_x0 == 0) {
             hipLaunchKernelGGL(k_copy_c128, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.b, vs, L.r);
             CHAFF_LAUNCH_CHECK();
+        } else if (u > 0 && u <= s / 2) {
+            // the changed columns alone, packed into the (idle) Krylov vectors:
+            // x and b gathered, r = b - Z x, r scattered back into L.r; the other
+            // systems keep the residuals of the last evaluation (their x is unchanged)
+            c128* xn = reinterpret_cast<c128*>(V);
+            c128* bn = reinterpret_cast<c128*>(V + vs);
+            c128* rn = reinterpret_cast<c128*>(V + 2 * vs);
+            CHAFF_HIP(hipMemcpyAsync(L.keep, last_live.data(), u * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL((k_gather_cols<c128>), dim3(blocks_for(rows * u)), dim3(256), 0, st, (const c128*)L.x,
+                               rows, s, (const int32_t*)L.keep, u, xn);
+            CHAFF_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_gather_cols<c128>), dim3(blocks_for(rows * u)), dim3(256), 0, st, (const c128*)L.b,
+                               rows, s, (const int32_t*)L.keep, u, bn);
+            CHAFF_LAUNCH_CHECK();
+            sst = spmm_launch<CZ, c128, c128, 1, false>(c->row_ptr, c->col_idx, Z, xn, bn, rn, c->n, c->nnzb, u, -1, st,
+                                                        "spmm_residual_fp64");
+            if (sst != CHAFF_OK) return sst;
+            hipLaunchKernelGGL((k_scatter_cols<c128>), dim3(blocks_for(rows * u)), dim3(256), 0, st, (const c128*)rn,
+                               rows, u, (const int32_t*)L.keep, s, L.r);
+            CHAFF_LAUNCH_CHECK();
+            SolveShape shn = sh;
+            shn.s = u;
+            shn.nsys = (int64_t)sh.n_clouds * u;
+            sst = norms_to<c128>(shn, L, rn, L.red, st);
+            if (sst != CHAFF_OK) return sst;
+            std::vector<c128> hn((size_t)shn.nsys);
+            CHAFF_HIP(hipMemcpyAsync(hn.data(), L.red, shn.nsys * sizeof(c128), hipMemcpyDeviceToHost, st));
+            CHAFF_HIP(hipStreamSynchronize(st));
+            for (int cl = 0; cl < sh.n_clouds; ++cl)
+                for (int64_t j = 0; j < u; ++j) hr[(size_t)cl * s + last_live[j]] = hn[(size_t)cl * u + j];
         } else {
             sst = spmm_launch<CZ, c128, c128, 1, false>(c->row_ptr, c->col_idx, Z, L.x, L.b, L.r, c->n, c->nnzb, s, -1, st,
                                                         "spmm_residual_fp64");
             if (sst != CHAFF_OK) return sst;
         }
-        sst = norms_to<c128>(sh, L, L.r, L.red, st);
-        if (sst != CHAFF_OK) return sst;
-        CHAFF_HIP(hipMemcpyAsync(hr.data(), L.red, nsys * sizeof(c128), hipMemcpyDeviceToHost, st));
-        CHAFF_HIP(hipStreamSynchronize(st));
+        if (!(u > 0 && u <= s / 2) || (cycles == 0 && o->use_x0 == 0)) {
+            sst = norms_to<c128>(sh, L, L.r, L.red, st);
+            if (sst != CHAFF_OK) return sst;
+            CHAFF_HIP(hipMemcpyAsync(hr.data(), L.red, nsys * sizeof(c128), hipMemcpyDeviceToHost, st));
+            CHAFF_HIP(hipStreamSynchronize(st));
+        }
+        last_live.clear();
         double worst = 0.0;
         int64_t active = 0;
         for (int64_t i = 0; i < nsys; ++i) {
@@ -2339,6 +2479,12 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
             CHAFF_HIP(hipMemcpyAsync(L.inv_rn, sc_inv.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
             sst = cocg_cycle<C, CZ>(c, o, sh, L, Z, Pinv, tg, ck, act, first, iters, st);
             if (sst != CHAFF_OK) return sst;
+            if (sh.method == CHAFF_COCG)   // COCG_RR keeps p and q in the Krylov vectors across cycles
+                for (int64_t j = 0; j < s; ++j) {
+                    bool lv = false;
+                    for (int cl = 0; cl < sh.n_clouds && !lv; ++cl) lv = act[(size_t)cl * s + j] != 0;
+                    if (lv) last_live.push_back((int32_t)j);
+                }
             continue;
         }
         CHAFF_HIP(hipMemcpyAsync(L.sys, hsys.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, st));

@@ -379,7 +379,9 @@ chaff_status cluster_apply_public(Cloud* c, chaff_prec prec, const void* M, cons
 //    7 KM rows with the identity, E the wire's own 7 unit columns) in FP32
 //    registers; Gauss-Jordan with partial pivoting: the pivot row is chosen
 //    by a wave reduction over the unused rows, normalised by its lane, and
-//    broadcast column by column with readlane, so no row is ever moved.  The
+//    broadcast column by column with readlane, so no row is ever moved
+//    (an LDS broadcast of the pivot row measured slower: 40.6 against 30.9 ms
+//    at C5, eight wires, as its extra registers leave two waves per SIMD).  The
 //    pivot row of unknown u ends holding row u of A^-1 E, i.e. column u of
 //    p's row block of A^-1 (A is complex symmetric), which is written at the
 //    block position of (p, member) in Z's pattern;
@@ -689,8 +691,13 @@ chaff_status nbhd_precond(Cloud* c, chaff_prec prec, int size, const void* Z, vo
     char* vals = static_cast<char*>(M) + nbhd_blocks_offset(c->n, size);
     {
         const size_t zb = prec == CHAFF_C64 ? sizeof(c64) : sizeof(c128);
-        const double nr = (double)NB * size;
-        ProfScope ps("nbhd_build", st, ProfWork{(double)c->nnzb * NB2 * zb, (double)c->n * nr * nr * (nr + NB) * 8.0});
+        // algorithmic work of the elimination: at every pivot each of the nr rows
+        // updates the columns still live (the rest of the pivot's block, the later
+        // blocks and the wire's unit columns): m NB (NB - 1) / 2 + NB^2 m (m - 1) / 2
+        // + NB^2 m complex multiply-adds per row for m wires
+        const double nr = (double)NB * size, m = size;
+        const double cma = m * NB * (NB - 1) / 2.0 + (double)NB2 * m * (m - 1.0) / 2.0 + (double)NB2 * m;
+        ProfScope ps("nbhd_build", st, ProfWork{(double)c->nnzb * NB2 * zb, (double)c->n * nr * cma * 8.0});
         if (prec == CHAFF_C64)
             nbhd_build_launch<c64>(c, size, nbt, (const c64*)Z, (c64*)vals, st);
         else
