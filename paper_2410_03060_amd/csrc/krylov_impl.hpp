@@ -910,16 +910,6 @@ __global__ void k_gather_cols(const C* __restrict__ src, int64_t n_rows, int64_t
     dst[t] = src[row * s_src + keep[j]];
 }
 
-// dst[row][keep[j]] = src[row][j] (the inverse of k_gather_cols; other columns untouched)
-template <typename C>
-__global__ void k_scatter_cols(const C* __restrict__ src, int64_t n_rows, int64_t s_src,
-                               const int32_t* __restrict__ keep, int64_t s_dst, C* __restrict__ dst) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_rows * s_src) return;
-    const int64_t row = t / s_src, j = t - (t / s_src) * s_src;
-    dst[row * s_dst + keep[j]] = src[t];
-}
-
 // V0[row][j] = Rv[row][keep[j]] * inv_rn[cloud][keep[j]]: the start vector of a
 // COCG cycle restricted to the columns that still hold a live system
 template <typename C>
@@ -2382,56 +2372,20 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     bool converged = false;
     std::vector<double> hinv(nsys), hrn(nsys), cocg_scale;
     std::vector<SysState> hsys(nsys);
-    // columns the last COCG cycle worked on: only their solutions changed
-    std::vector<int32_t> last_live;
     for (;;) {
         // true residual r = b - Z x (FP64 accumulation over the stored Z)
-        const int64_t u = (int64_t)last_live.size();
         if (cycles == 0 && o->use_x0 == 0) {
             hipLaunchKernelGGL(k_copy_c128, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.b, vs, L.r);
             CHAFF_LAUNCH_CHECK();
-        } else if (u > 0 && u <= s / 2) {
-            // the changed columns alone, packed into the (idle) Krylov vectors:
-            // x and b gathered, r = b - Z x, r scattered back into L.r; the other
-            // systems keep the residuals of the last evaluation (their x is unchanged)
-            c128* xn = reinterpret_cast<c128*>(V);
-            c128* bn = reinterpret_cast<c128*>(V + vs);
-            c128* rn = reinterpret_cast<c128*>(V + 2 * vs);
-            CHAFF_HIP(hipMemcpyAsync(L.keep, last_live.data(), u * sizeof(int32_t), hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL((k_gather_cols<c128>), dim3(blocks_for(rows * u)), dim3(256), 0, st, (const c128*)L.x,
-                               rows, s, (const int32_t*)L.keep, u, xn);
-            CHAFF_LAUNCH_CHECK();
-            hipLaunchKernelGGL((k_gather_cols<c128>), dim3(blocks_for(rows * u)), dim3(256), 0, st, (const c128*)L.b,
-                               rows, s, (const int32_t*)L.keep, u, bn);
-            CHAFF_LAUNCH_CHECK();
-            sst = spmm_launch<CZ, c128, c128, 1, false>(c->row_ptr, c->col_idx, Z, xn, bn, rn, c->n, c->nnzb, u, -1, st,
-                                                        "spmm_residual_fp64");
-            if (sst != CHAFF_OK) return sst;
-            hipLaunchKernelGGL((k_scatter_cols<c128>), dim3(blocks_for(rows * u)), dim3(256), 0, st, (const c128*)rn,
-                               rows, u, (const int32_t*)L.keep, s, L.r);
-            CHAFF_LAUNCH_CHECK();
-            SolveShape shn = sh;
-            shn.s = u;
-            shn.nsys = (int64_t)sh.n_clouds * u;
-            sst = norms_to<c128>(shn, L, rn, L.red, st);
-            if (sst != CHAFF_OK) return sst;
-            std::vector<c128> hn((size_t)shn.nsys);
-            CHAFF_HIP(hipMemcpyAsync(hn.data(), L.red, shn.nsys * sizeof(c128), hipMemcpyDeviceToHost, st));
-            CHAFF_HIP(hipStreamSynchronize(st));
-            for (int cl = 0; cl < sh.n_clouds; ++cl)
-                for (int64_t j = 0; j < u; ++j) hr[(size_t)cl * s + last_live[j]] = hn[(size_t)cl * u + j];
         } else {
             sst = spmm_launch<CZ, c128, c128, 1, false>(c->row_ptr, c->col_idx, Z, L.x, L.b, L.r, c->n, c->nnzb, s, -1, st,
                                                         "spmm_residual_fp64");
             if (sst != CHAFF_OK) return sst;
         }
-        if (!(u > 0 && u <= s / 2) || (cycles == 0 && o->use_x0 == 0)) {
-            sst = norms_to<c128>(sh, L, L.r, L.red, st);
-            if (sst != CHAFF_OK) return sst;
-            CHAFF_HIP(hipMemcpyAsync(hr.data(), L.red, nsys * sizeof(c128), hipMemcpyDeviceToHost, st));
-            CHAFF_HIP(hipStreamSynchronize(st));
-        }
-        last_live.clear();
+        sst = norms_to<c128>(sh, L, L.r, L.red, st);
+        if (sst != CHAFF_OK) return sst;
+        CHAFF_HIP(hipMemcpyAsync(hr.data(), L.red, nsys * sizeof(c128), hipMemcpyDeviceToHost, st));
+        CHAFF_HIP(hipStreamSynchronize(st));
         double worst = 0.0;
         int64_t active = 0;
         for (int64_t i = 0; i < nsys; ++i) {
@@ -2479,12 +2433,6 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
             CHAFF_HIP(hipMemcpyAsync(L.inv_rn, sc_inv.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
             sst = cocg_cycle<C, CZ>(c, o, sh, L, Z, Pinv, tg, ck, act, first, iters, st);
             if (sst != CHAFF_OK) return sst;
-            if (sh.method == CHAFF_COCG)   // COCG_RR keeps p and q in the Krylov vectors across cycles
-                for (int64_t j = 0; j < s; ++j) {
-                    bool lv = false;
-                    for (int cl = 0; cl < sh.n_clouds && !lv; ++cl) lv = act[(size_t)cl * s + j] != 0;
-                    if (lv) last_live.push_back((int32_t)j);
-                }
             continue;
         }
         CHAFF_HIP(hipMemcpyAsync(L.sys, hsys.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, st));
