@@ -490,13 +490,18 @@ __global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int si
     const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const int64_t i = (int64_t)blockIdx.x * NBH_WAVES + w;
     if (i >= n) return;   // wave-uniform; the waves of a workgroup never wait for each other
-    int32_t mem[KM];
+    // members in the order of the local system: the neighbours first, the wire
+    // itself last (its unit columns then stay untouched until its own block)
+    int32_t raw[KM], mem[KM];
     int m = 0;
 #pragma unroll
     for (int s = 0; s < KM; ++s) {
-        mem[s] = s < size ? nbt[i * size + s] : -1;
-        m += mem[s] >= 0 ? 1 : 0;
+        raw[s] = s < size ? nbt[i * size + s] : -1;
+        m += raw[s] >= 0 ? 1 : 0;
     }
+#pragma unroll
+    for (int s = 0; s < KM; ++s) mem[s] = s + 1 < m ? raw[s + 1] : (s + 1 == m ? raw[0] : -1);
+    const int own = NB * (m - 1);   // first row of the wire's own block
     // block position of (member a, member b) in Z's pattern, -1 if the pair is not near
     if (lane < KM * KM) {
         const int a = lane / KM, b = lane % KM;
@@ -530,7 +535,7 @@ __global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int si
         }
     }
 #pragma unroll
-    for (int c = 0; c < NB; ++c) A[NR + c] = c64{lane == c ? 1.f : 0.f, 0.f};
+    for (int c = 0; c < NB; ++c) A[NR + c] = c64{lane == own + c ? 1.f : 0.f, 0.f};
 
     // Gauss-Jordan over the 7 m columns of the real system (padding rows keep
     // their identity entries and never compete for a pivot).  Rows are not
@@ -540,6 +545,10 @@ __global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int si
     // Columns are walked block by block: block kb's 7 columns are copied once
     // into T (static indices from then on); columns of earlier blocks are never
     // read again, so only T, the later blocks and the unit columns change.
+    // The pivots of the neighbours' columns are taken among the neighbours'
+    // rows only (partial pivoting on the leading block, whose Schur complement
+    // is the wire's own block): every pivot row then has zero unit columns
+    // until the last block, so those columns are left alone until then.
     const int nr = NB * m;
     bool used = lane >= nr;
     int my_u = -1;
@@ -559,7 +568,8 @@ __global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int si
         for (int kc = 0; kc < NB; ++kc) {
             const c64 v = T[kc];
             // pivot: the largest |a_rk| among rows not yet used (NaN counts as 0)
-            const int piv = pivot_lane(used, v.re * v.re + v.im * v.im, lane);
+            const bool own_block = kb == m - 1;   // wave-uniform
+            const int piv = pivot_lane(used || (!own_block && lane >= own), v.re * v.re + v.im * v.im, lane);
             const c64 pv = {__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.re), piv)),
                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.im), piv))};
             const float d = pv.re * pv.re + pv.im * pv.im;
@@ -588,8 +598,10 @@ __global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int si
 #pragma unroll
                     for (int c = 0; c < NB; ++c) elim(A[NB * b + c]);
                 }
+            if (own_block) {
 #pragma unroll
-            for (int c = 0; c < NB; ++c) elim(A[NR + c]);
+                for (int c = 0; c < NB; ++c) elim(A[NR + c]);
+            }
         }
     }
     // the pivot row of unknown u holds d_u times row u of A^-1 E: raw_{p, mem[s]}[c][a] with u = 7 s + a
@@ -598,7 +610,7 @@ __global__ __launch_bounds__(64 * NBH_WAVES) void k_nbhd_build(int64_t n, int si
         const float dd = my_d.re * my_d.re + my_d.im * my_d.im;
         const c64 id = dd > 0.f ? c64{my_d.re / dd, -my_d.im / dd} : c64{0.f, 0.f};
         if (s < m) {
-            const int64_t p = pos_s[w][s];   // (p, mem[s]) in row p
+            const int64_t p = pos_s[w][(m - 1) * KM + s];   // (p, mem[s]) in row p
 #pragma unroll
             for (int c = 0; c < NB; ++c) M[p * NB2 + c * NB + a] = ccast<CZ>(cmul(A[NR + c], id));
         }
