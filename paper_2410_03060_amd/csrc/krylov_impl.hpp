@@ -182,9 +182,10 @@ __global__ __launch_bounds__(64) void k_spmm_wave_row(const int64_t* __restrict_
                                                       const CY* __restrict__ B, CY* __restrict__ Y,
                                                       int64_t n, int64_t s) {
     using R = typename real_of<CY>::type;
+    using ZT = cplx<R>;   // blocks are staged in the accumulation type: converted once per entry
     constexpr int G = 64 / (S * NR);
     constexpr int KK = (NB + G - 1) / G;
-    __shared__ CZ zs[2][NR][NB2];
+    __shared__ ZT zs[2][NR][NB2];
     const int lane = threadIdx.x;
     const int sub = lane / (S * G), g = (lane / S) % G, c = lane % S;
     int64_t grp = blockIdx.x;
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(64) void k_spmm_wave_row(const int64_t* __restrict_
         const int buf = (int)(t & 1);
         if (lane < NB2) {
 #pragma unroll
-            for (int u = 0; u < NR; ++u) zs[buf][u][lane] = zn[u];
+            for (int u = 0; u < NR; ++u) zs[buf][u][lane] = ccast<ZT>(zn[u]);
         }
         if (t + 1 < len && lane < NB2) {
 #pragma unroll
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(64) void k_spmm_wave_row(const int64_t* __restrict_
                 const int k = g + kk * G;
                 if (k < NB) {
 #pragma unroll
-                    for (int q = 0; q < NB; ++q) cfma(acc[q], ccast<cplx<R>>(zs[buf][sub][q * NB + k]), x[kk]);
+                    for (int q = 0; q < NB; ++q) cfma(acc[q], zs[buf][sub][q * NB + k], x[kk]);
                 }
             }
         }
