@@ -951,14 +951,15 @@ __global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_
 // block itself, so the row's own p is still in the registers that gathered
 // that last slab (no second read of p).  Two fixed-order passes then sum
 // tiles per group and groups per cloud.  The gathers of p are latency bound:
-// complex64 tiles ask the compiler for at least six waves per SIMD (the
-// 64-column MFMA tile fits 60 registers: eight waves); complex128 tiles would
-// spill under that bound.  Gathering the next block's slab during the current
-// block's MFMAs measured no faster at C5 (it costs one wave per SIMD).
+// complex64 tiles ask the compiler for at least seven waves per SIMD (the
+// 64-column three-product MFMA tile fits 72 registers; the four-product form
+// fitted 60, eight waves, and ran 4 % slower); complex128 tiles would spill
+// under that bound.  Gathering the next block's slab during the current block's
+// MFMAs measured no faster at C5 (it costs one wave per SIMD).
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 constexpr int COCG_TILE_ROWS = RB / 64;
 template <typename CZ, typename C, int S>
-__global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(sizeof(C) == sizeof(c64) && NB == 7 ? 6 : 1)))
+__global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(sizeof(C) == sizeof(c64) && NB == 7 ? 7 : 1)))
 void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles, int xcd_order,
                  const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
                  const int64_t* __restrict__ diag_pos, const CZ* __restrict__ Z, const C* __restrict__ P,
@@ -995,9 +996,12 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
     // l % S of depth group l / S; the 4 lanes of an MFMA block share their
     // group, so each block forms its group's partial sums for 4 columns, and
     // the groups are added by the cross-lane sums below.  Rows 0-3 and 4-7 of
-    // the block are two 4-row tiles, row 7 zero; four MFMAs per depth step for
-    // the real form of the complex product, in the order of cfma, so the
-    // result rounds exactly as the vector form's)
+    // the block are two 4-row tiles, row 7 zero.  Three real products per
+    // complex one (Gauss's form): the sums a.re x.re, a.im x.im and
+    // (a.re + a.im)(x.re + x.im) are accumulated apart and combined at the
+    // end, so a depth step takes three MFMAs per tile instead of four; its
+    // rounding differs from the four-product form by a few units of the
+    // largest partial sum, within the FP32 accuracy the refinement corrects)
     constexpr bool PMFMA = sizeof(C) == sizeof(c64) && sizeof(CZ) == sizeof(c64) && NB == 7;
     static_assert(!PMFMA || S % 4 == 0, "an MFMA block of 4 lanes stays inside one depth group");
     if (i < tl.w1) {   // wave-uniform
@@ -1006,6 +1010,7 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
         for (int q = 0; q < NB; ++q) acc[q] = {0, 0};
         f32x4_t mr[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         f32x4_t mi[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        f32x4_t ms[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         // blocks in rotated order, the diagonal block last: its slab (the row's
         // own p, for p^T q) is then still in the registers after the loop
         const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
@@ -1045,14 +1050,16 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
 #pragma unroll
                 for (int kk = 0; kk < KK; ++kk) {
                     const int k = g + kk * G;
+                    const float xs = (float)x[kk].re + (float)x[kk].im;
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
                         const int row = 4 * t + (lane & 3);
                         const c64 a = (row < NB && k < NB) ? ccast<c64>(zs[w][buf][row * NB + k]) : c64{0.f, 0.f};
+                        // three real products per complex one: re = a.re x.re - a.im x.im,
+                        // im = (a.re + a.im)(x.re + x.im) - a.re x.re - a.im x.im
                         mr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, (float)x[kk].re, mr[t], 0, 0, 0);
-                        mr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(-a.im, (float)x[kk].im, mr[t], 0, 0, 0);
-                        mi[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, (float)x[kk].im, mi[t], 0, 0, 0);
-                        mi[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.im, (float)x[kk].re, mi[t], 0, 0, 0);
+                        mi[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.im, (float)x[kk].im, mi[t], 0, 0, 0);
+                        ms[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re + a.im, xs, ms[t], 0, 0, 0);
                     }
                 }
             } else {
@@ -1068,7 +1075,10 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
         }
         if constexpr (PMFMA) {
 #pragma unroll
-            for (int q = 0; q < NB; ++q) acc[q] = cplx<R>{(R)mr[q >> 2][q & 3], (R)mi[q >> 2][q & 3]};
+            for (int q = 0; q < NB; ++q) {
+                const float pr = mr[q >> 2][q & 3], pi = mi[q >> 2][q & 3], ps = ms[q >> 2][q & 3];
+                acc[q] = cplx<R>{(R)(pr - pi), (R)(ps - pr - pi)};
+            }
         }
 #pragma unroll
         for (int off = S; off < 64; off <<= 1)
