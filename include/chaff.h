@@ -55,7 +55,9 @@ typedef enum {
     CHAFF_EWORKSPACE = -2,   /* workspace too small / pattern capacity exceeded */
     CHAFF_EHIP = -3,         /* a HIP runtime call failed */
     CHAFF_ESINGULAR = -4,    /* a self block could not be inverted */
-    CHAFF_ENOCONV = -5       /* solver hit its iteration cap; X holds the last iterate */
+    CHAFF_ENOCONV = -5       /* solver hit its iteration cap, or a recurrence broke down and left a
+                                system's solution non-finite (its relative residual reads +inf);
+                                X holds the last iterate */
 } chaff_status;
 
 typedef enum { CHAFF_C64 = 0, CHAFF_C128 = 1 } chaff_prec;

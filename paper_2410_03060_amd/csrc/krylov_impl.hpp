@@ -2380,7 +2380,7 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
 
     const bool refine = std::is_same<C, c64>::value;
     int cycles = 0, iters = 0;
-    bool converged = false;
+    bool converged = false, broken = false;
     std::vector<double> hinv(nsys), hrn(nsys), cocg_scale;
     std::vector<SysState> hsys(nsys);
     for (;;) {
@@ -2399,9 +2399,14 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         CHAFF_HIP(hipStreamSynchronize(st));
         double worst = 0.0;
         int64_t active = 0;
+        broken = false;
         for (int64_t i = 0; i < nsys; ++i) {
             double rn = std::sqrt(std::max(hr[i].re, 0.0));
             rel[i] = bnorm[i] > 0 ? rn / bnorm[i] : 0.0;
+            if (!std::isfinite(hr[i].re)) {   // a recurrence broke down and left x non-finite
+                rel[i] = INFINITY;
+                broken = true;
+            }
             worst = std::max(worst, rel[i]);
             bool act = rel[i] > o->tol && std::isfinite(rel[i]);
             active += act;
@@ -2420,7 +2425,7 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         if (g_verbose)
             std::fprintf(stderr, "[chaff] cycle %d: active %lld max rel residual %.3e (iterations so far %d)\n",
                          cycles, (long long)active, worst, iters);
-        if (active == 0) { converged = true; break; }
+        if (active == 0) { converged = !broken; break; }
         if (cycles >= o->max_cycles) break;
         ++cycles;
         CHAFF_HIP(hipMemcpyAsync(L.rn, hrn.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
@@ -2571,8 +2576,9 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     }
     if (!converged)
-        return fail(CHAFF_ENOCONV, "no convergence after " + std::to_string(cycles) +
-                                       " cycles; max relative residual " + std::to_string(worst));
+        return fail(CHAFF_ENOCONV, (broken ? "breakdown (non-finite solution) after " : "no convergence after ") +
+                                       std::to_string(cycles) + " cycles; max relative residual " +
+                                       std::to_string(worst));
     return CHAFF_OK;
 }
 

@@ -127,7 +127,11 @@ def _solve_case(B, cloud, prec, method, size, use_x0=0):
               restart=500 if method in (B.COCG, B.COCG_RR) else 30,
               inner_tol=1e-4 if prec == B.C64 else 1e-12, max_cycles=60)
     X, info = B.solve(cl, Z, M, inc.k_hat, inc.e_hat, B.solve_opts(precond=B.PRECOND_NBHD, **kw))
-    Xb, info_b = B.solve(cl, Z, P, inc.k_hat, inc.e_hat, B.solve_opts(precond=B.PRECOND_BLOCK, **kw))
+    # the block-Jacobi baseline may fail: with COCG_RR in complex64 its recurrence stagnates at the
+    # 500-step cap cycle after cycle and overflows on this cloud (reported as CHAFF_ENOCONV, relative
+    # residual +inf); its step count then only bounds the neighbourhood solve's from above
+    Xb, info_b = B.solve(cl, Z, P, inc.k_hat, inc.e_hat, B.solve_opts(precond=B.PRECOND_BLOCK, **kw),
+                         raise_on_noconv=False)
     sig = B.rcs(cl, X, -inc.k_hat, inc.e_hat, monostatic=True).cpu().numpy()
     Zs, _ = mom.snfc_matrix(cloud)
     u = mom.excitation(cloud, inc.k_hat, inc.e_hat)
@@ -147,8 +151,10 @@ def test_solves_reach_the_oracle(B, method, prec):
     m = {"cocg": B.COCG, "cocg_rr": B.COCG_RR, "gmres": B.GMRES, "gcr": B.GCR}[method]
     p = B.C64 if prec == "c64" else B.C128
     info, info_b, cerr, db = _solve_case(B, cloud, p, m, 6)
-    say(f"[nbhd] {method} {prec}: {info['iterations']} steps (block-Jacobi {info_b['iterations']}), "
-        f"residual {info['max_rel_residual']:.1e}, current err {cerr:.2e}, rcs {db:.2e} dB")
+    say(f"[nbhd] {method} {prec}: {info['iterations']} steps (block-Jacobi {info_b['iterations']}, "
+        f"residual {info_b['max_rel_residual']:.1e}), residual {info['max_rel_residual']:.1e}, "
+        f"current err {cerr:.2e}, rcs {db:.2e} dB")
+    assert info["max_rel_residual"] <= (1e-6 if p == B.C64 else 1e-11)
     tol_c = 1e-4 if p == B.C64 else 1e-10
     assert cerr <= tol_c and db <= (0.1 if p == B.C64 else 1e-6)
     assert info["iterations"] < info_b["iterations"]
