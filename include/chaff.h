@@ -183,7 +183,9 @@ typedef enum { CHAFF_PRECOND_BLOCK = 0, CHAFF_PRECOND_CLUSTER = 1, CHAFF_PRECOND
  * Z and its block-diagonal inverse are complex symmetric (bilinear a^T b),
  * with four vectors and no restart inside a cycle.  CHAFF_COCG restarts the
  * recurrence at every refinement checkpoint; CHAFF_COCG_RR keeps the search
- * direction and only replaces the recursive residual by the FP64 true one.
+ * direction and only replaces the recursive residual by the FP64 true one
+ * (after a cycle that ended at its `restart` step cap it restarts the
+ * recurrence as CHAFF_COCG does).
  * CHAFF_GCR is the generalized conjugate residual method of Sec. II-B,
  * restarted every `restart` (= m <= 200) steps and right-preconditioned:
  * it keeps the m preconditioned directions and their images under Z

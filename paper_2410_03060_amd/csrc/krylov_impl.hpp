@@ -946,11 +946,13 @@ __global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_
 // HBM latency of the Z stream overlaps the arithmetic; lane (group g, column
 // c) applies block columns k = g, g + G, ... (G = 64/S) to RHS column c, and
 // the G partial sums are combined with cross-lane adds.  sigma = p^T q is
-// reduced per tile in FP64 (tpart[tile][r]); a row's blocks are applied in
-// rotated order, from the one after the diagonal block round to the diagonal
-// block itself, so the row's own p is still in the registers that gathered
-// that last slab (no second read of p).  Two fixed-order passes then sum
-// tiles per group and groups per cloud.  The gathers of p are latency bound:
+// reduced per tile in FP64 (tpart[tile][r]); the row's own p is stashed in
+// LDS when its diagonal block's slab is gathered (no second read of p, no
+// registers held across the loop).  Blocks are applied in ascending column
+// order: the rows in flight on an XCD then gather their neighbours' slabs in
+// step, and L2 serves them (10.2 GB fetched per C5 launch; starting each row
+// after its diagonal, so that the own slab came last, fetched 12.9 GB).  Two
+// fixed-order passes then sum tiles per group and groups per cloud.  The gathers of p are latency bound:
 // complex64 tiles ask the compiler for at least seven waves per SIMD (the
 // 64-column three-product MFMA tile fits 72 registers; the four-product form
 // fitted 60, eight waves, and ran 4 % slower); complex128 tiles would spill
@@ -961,14 +963,14 @@ constexpr int COCG_TILE_ROWS = RB / 64;
 template <typename CZ, typename C, int S>
 __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(sizeof(C) == sizeof(c64) && NB == 7 ? 7 : 1)))
 void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles, int xcd_order,
-                 const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                 const int64_t* __restrict__ diag_pos, const CZ* __restrict__ Z, const C* __restrict__ P,
-                 C* __restrict__ Q, int64_t s, c128* __restrict__ tpart) {
+                 const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx, const CZ* __restrict__ Z,
+                 const C* __restrict__ P, C* __restrict__ Q, int64_t s, c128* __restrict__ tpart) {
     using R = typename real_of<C>::type;
     constexpr int G = 64 / S;
     constexpr int KK = (NB + G - 1) / G;
     constexpr int ZPL = (NB2 + 63) / 64;
     __shared__ CZ zs[COCG_TILE_ROWS][2][NB2];
+    __shared__ cplx<typename real_of<C>::type> pown[COCG_TILE_ROWS][(NB + 64 / S - 1) / (64 / S)][64];
     __shared__ c128 red[RB];
     const int64_t id = blockIdx.x;
     int64_t t, ctile_l;
@@ -1011,36 +1013,38 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
         f32x4_t mr[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         f32x4_t mi[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         f32x4_t ms[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-        // blocks in rotated order, the diagonal block last: its slab (the row's
-        // own p, for p^T q) is then still in the registers after the loop
+        // blocks in ascending column order; the row's own p slab is stashed in
+        // LDS when its diagonal block is gathered (each lane reads back only
+        // what it wrote, so no barrier) for p^T q after the loop
         const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
-        const int64_t ne = e1 - e0, ed = diag_pos[i];
-        int64_t e = ed + 1 < e1 ? ed + 1 : e0;
         // lane l stages entries l, l + 64, ... of each block (ZPL per lane)
         CZ zn[ZPL];
         cplx<R> x[KK];
 #pragma unroll
         for (int u = 0; u < ZPL; ++u)
-            zn[u] = (lane + 64 * u < NB2 && ne > 0) ? Z[e * NB2 + lane + 64 * u] : CZ{0, 0};
+            zn[u] = (lane + 64 * u < NB2 && e0 < e1) ? Z[e0 * NB2 + lane + 64 * u] : CZ{0, 0};
 #pragma unroll
-        for (int kk = 0; kk < KK; ++kk) x[kk] = {0, 0};
-        for (int64_t j = 0; j < ne; ++j) {
-            const int buf = (int)(j & 1);
+        for (int kk = 0; kk < KK; ++kk) pown[w][kk][lane] = cplx<R>{0, 0};
+        for (int64_t e = e0; e < e1; ++e) {
+            const int buf = (int)((e - e0) & 1);
 #pragma unroll
             for (int u = 0; u < ZPL; ++u)
                 if (lane + 64 * u < NB2) zs[w][buf][lane + 64 * u] = zn[u];
-            const int64_t ce = col_idx[e];
-            e = e + 1 < e1 ? e + 1 : e0;
-            if (j + 1 < ne) {
+            if (e + 1 < e1) {
 #pragma unroll
                 for (int u = 0; u < ZPL; ++u)
-                    if (lane + 64 * u < NB2) zn[u] = Z[e * NB2 + lane + 64 * u];
+                    if (lane + 64 * u < NB2) zn[u] = Z[(e + 1) * NB2 + lane + 64 * u];
             }
+            const int64_t ce = col_idx[e];
             const C* xb = P + ce * NB * s + rc;
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 const int k = g + kk * G;
                 x[kk] = k < NB ? ccast<cplx<R>>(xb[k * s]) : cplx<R>{0, 0};
+            }
+            if (ce == i) {   // wave-uniform: the diagonal block
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) pown[w][kk][lane] = x[kk];
             }
             // the block written above by this wave's lanes is visible to all of its lanes
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1093,7 +1097,7 @@ void k_cocg_spmm(const Chunk* __restrict__ tiles, int64_t n_tiles, int col_tiles
                 if (q % G != g) continue;
                 const int64_t o = (i * NB + q) * s + r;
                 Q[o] = ccast<C>(acc[q]);
-                cfma(dot, ccast<c128>(x[q / G]), ccast<c128>(acc[q]));
+                cfma(dot, ccast<c128>(pown[w][q / G][lane]), ccast<c128>(acc[q]));
             }
         }
     }
@@ -1736,7 +1740,7 @@ static void launch_cocg_spmm(const Cloud* c, const SolveShape& sh, SolveLayout& 
     const int64_t nblk = sh.cocg_xcd ? per_xcd * NXCD * ct : sh.n_tiles * ct;
     hipLaunchKernelGGL((k_cocg_spmm<CZ, C, ST>), dim3((unsigned)nblk), dim3(RB), 0, st,
                        (const Chunk*)L.tiles, sh.n_tiles, ct, sh.cocg_xcd, (const int64_t*)c->row_ptr,
-                       (const int32_t*)c->col_idx, (const int64_t*)c->diag_pos, Z, p, q, sh.s, L.tpart);
+                       (const int32_t*)c->col_idx, Z, p, q, sh.s, L.tpart);
 }
 
 static chaff_status cocg_narrow_shape(const Cloud* c, SolveShape& cs, SolveLayout& Lc, const SolveLayout& L,
@@ -1848,7 +1852,8 @@ template <typename C, typename CZ>
 static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveShape& sh, SolveLayout& L,
                                const CZ* Z, const CZ* Pinv, const std::vector<double>& target,
                                const std::vector<double>& ckpt, const std::vector<int32_t>& act, bool first,
-                               int& iters, hipStream_t st) {
+                               int& iters, bool& capped, hipStream_t st) {
+    capped = false;
     const int64_t rows = sh.rows, s = sh.s, vs = rows * s, nsys = sh.nsys;
     C* V = static_cast<C*>(L.V);   // [x_c | r | p | q], each with room for [rows][s]
     C* xc = V;
@@ -2009,7 +2014,11 @@ static chaff_status cocg_cycle(Cloud* c, const chaff_solve_opts* o, const SolveS
         if (g_verbose && k % 50 == 0)
             std::fprintf(stderr, "[chaff] cocg step %d: %d of %lld systems above their checkpoint (%lld columns)\n",
                          k, n_act, (long long)cs.nsys, (long long)cs.s);
-        if (n_act == 0 || k == o->restart) break;
+        if (n_act == 0) break;
+        if (k == o->restart) {   // the step cap with systems still above their checkpoint
+            capped = true;
+            break;
+        }
         if (compact && cs.s > 1 && n_act != last_checked && n_act <= (int64_t)cs.n_clouds * (wst / 2)) {
             last_checked = n_act;
             flags.resize(cs.nsys);
@@ -2380,7 +2389,7 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
 
     const bool refine = std::is_same<C, c64>::value;
     int cycles = 0, iters = 0;
-    bool converged = false, broken = false;
+    bool converged = false, broken = false, rr_restart = false;
     std::vector<double> hinv(nsys), hrn(nsys), cocg_scale;
     std::vector<SysState> hsys(nsys);
     for (;;) {
@@ -2447,8 +2456,13 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
             }
             CHAFF_HIP(hipMemcpyAsync(L.rn, sc.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
             CHAFF_HIP(hipMemcpyAsync(L.inv_rn, sc_inv.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st));
-            sst = cocg_cycle<C, CZ>(c, o, sh, L, Z, Pinv, tg, ck, act, first, iters, st);
+            // COCG_RR carries p and r^T z into the next cycle; after a cycle that
+            // stalled at its step cap the recurrence restarts from the true residual
+            // instead (a stagnating FP32 recurrence carried on can overflow)
+            bool capped = false;
+            sst = cocg_cycle<C, CZ>(c, o, sh, L, Z, Pinv, tg, ck, act, first || rr_restart, iters, capped, st);
             if (sst != CHAFF_OK) return sst;
+            rr_restart = capped;
             continue;
         }
         CHAFF_HIP(hipMemcpyAsync(L.sys, hsys.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, st));
