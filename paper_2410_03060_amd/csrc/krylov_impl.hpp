@@ -952,12 +952,12 @@ __global__ void k_gather_sys(const T* __restrict__ src, int n_clouds, int64_t s_
 // order: the rows in flight on an XCD then gather their neighbours' slabs in
 // step, and L2 serves them (10.2 GB fetched per C5 launch; starting each row
 // after its diagonal, so that the own slab came last, fetched 12.9 GB).  Two
-// fixed-order passes then sum tiles per group and groups per cloud.  The gathers of p are latency bound:
-// complex64 tiles ask the compiler for at least seven waves per SIMD (the
-// 64-column three-product MFMA tile fits 72 registers; the four-product form
-// fitted 60, eight waves, and ran 4 % slower); complex128 tiles would spill
-// under that bound.  Gathering the next block's slab during the current block's
-// MFMAs measured no faster at C5 (it costs one wave per SIMD).
+// fixed-order passes then sum tiles per group and groups per cloud.  The
+// gathers of p bound the kernel: complex64 tiles ask the compiler for at
+// least seven waves per SIMD (the 64-column three-product MFMA tile fits 66
+// registers; eight waves spill); complex128 tiles would spill under that
+// bound.  Gathering the next block's slab during the current block's MFMAs
+// measured no faster at C5 (it costs one wave per SIMD).
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 constexpr int COCG_TILE_ROWS = RB / 64;
 template <typename CZ, typename C, int S>
