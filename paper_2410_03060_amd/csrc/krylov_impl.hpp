@@ -506,7 +506,7 @@ __device__ __forceinline__ double sinc(double x) {
 // U[i*7+q][r] (internal wire i) or, with `perm`, at caller row perm[i].
 __global__ void k_excitation(const Wire* __restrict__ wires, const int32_t* __restrict__ perm, int64_t n,
                              const double* __restrict__ k_hat, const double* __restrict__ e_hat,
-                             int64_t s, double k, c128* __restrict__ U) {
+                             int64_t s, double k, c128* __restrict__ U, c64* __restrict__ U32) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * s) return;
     const int64_t i = t / s, r = t - (t / s) * s;
@@ -525,7 +525,14 @@ __global__ void k_excitation(const Wire* __restrict__ wires, const int32_t* __re
         double sn, cs;
         sincos(ph0 + beta * sq, &sn, &cs);
         U[(row * NB + q) * s + r] = c128{env * cs, -env * sn};
+        if (U32) U32[(row * NB + q) * s + r] = c64{(float)(env * cs), (float)(-env * sn)};
     }
+}
+
+// x (FP64) = x32 (FP32), exactly
+__global__ void k_widen(const c64* __restrict__ x32, int64_t n, c128* __restrict__ x) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = c128{(double)x32[t].re, (double)x32[t].im};
 }
 
 // ------------------------------------------------------------------ row-chunk reductions
@@ -2352,10 +2359,22 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
     // --- excitation and initial guess (internal order, FP64)
     chaff_status sst0 = CHAFF_OK;
     const double k = 2.0 * PI_K / c->wavelength;
+    // complex64 with the neighbourhood inverse: the guess x0 = M u is formed in
+    // FP32 from an FP32 copy of u (a guess needs no more), and x0's FP32 values,
+    // widened exactly into the FP64 solution, give the first residual through
+    // FP32 slabs (half the gathered bytes of FP64 ones) with FP64 accumulation
+    const bool guess32 = std::is_same<C, c64>::value && o->use_x0 == 2 && o->precond == CHAFF_PRECOND_NBHD;
+    c64* const u32 = guess32 ? reinterpret_cast<c64*>(V + vs) : nullptr;   // idle Krylov vectors
+    c64* const x32 = guess32 ? reinterpret_cast<c64*>(V) : nullptr;
     hipLaunchKernelGGL(k_excitation, dim3(blocks_for(c->n * s)), dim3(256), 0, st, (const Wire*)c->wires,
-                       (const int32_t*)nullptr, c->n, k_hat, e_hat, s, k, L.b);
+                       (const int32_t*)nullptr, c->n, k_hat, e_hat, s, k, L.b, u32);
     CHAFF_LAUNCH_CHECK();
-    if (o->use_x0 == 1) {
+    if (guess32) {
+        sst0 = spmm_launch<CZ, c64, c64, 0, false>(c->row_ptr, c->col_idx, Pinv, (const c64*)u32, (const c64*)nullptr,
+                                                   x32, c->n, c->nnzb, s, -1, st, "guess_nbhd");
+        if (sst0 != CHAFF_OK) return sst0;
+        hipLaunchKernelGGL(k_widen, dim3(blocks_for(vs)), dim3(256), 0, st, (const c64*)x32, vs, L.x);
+    } else if (o->use_x0 == 1) {
         hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)Xout,
                            (const int32_t*)c->perm, c->n, s, L.x, 0);
     } else if (o->use_x0 == 2 && o->precond == CHAFF_PRECOND_NBHD) {
@@ -2397,6 +2416,10 @@ static chaff_status solve_impl(Cloud* c, const chaff_solve_opts* o, const CZ* Z,
         if (cycles == 0 && o->use_x0 == 0) {
             hipLaunchKernelGGL(k_copy_c128, dim3(blocks_for(vs)), dim3(256), 0, st, (const c128*)L.b, vs, L.r);
             CHAFF_LAUNCH_CHECK();
+        } else if (cycles == 0 && guess32) {   // x = x32 exactly: the FP32 slabs give the same residual
+            sst = spmm_launch<CZ, c64, c128, 1, false>(c->row_ptr, c->col_idx, Z, (const c64*)x32, L.b, L.r, c->n,
+                                                       c->nnzb, s, -1, st, "spmm_residual_fp64");
+            if (sst != CHAFF_OK) return sst;
         } else {
             sst = spmm_launch<CZ, c128, c128, 1, false>(c->row_ptr, c->col_idx, Z, L.x, L.b, L.r, c->n, c->nnzb, s, -1, st,
                                                         "spmm_residual_fp64");
@@ -2652,7 +2675,7 @@ chaff_status autotune(Cloud* c, chaff_prec prec, const void* Z, void* X, void* Y
 chaff_status excitation(Cloud* c, const double* k_hat, const double* e_hat, int64_t s, void* U, hipStream_t st) {
     const double k = 2.0 * PI_K / c->wavelength;
     hipLaunchKernelGGL(k_excitation, dim3(blocks_for(c->n * s)), dim3(256), 0, st, (const Wire*)c->wires,
-                       (const int32_t*)c->perm, c->n, k_hat, e_hat, s, k, (c128*)U);
+                       (const int32_t*)c->perm, c->n, k_hat, e_hat, s, k, (c128*)U, (c64*)nullptr);
     CHAFF_LAUNCH_CHECK();
     return CHAFF_OK;
 }
