@@ -341,6 +341,28 @@ def test_determinism_bitwise(B):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("method", ["cocg", "gmres"])
+def test_non_finite_solution_is_reported_as_breakdown(B, method):
+    """A NaN entry in Z makes the FP64 residual of the systems that touch it
+    non-finite: the solve ends with CHAFF_ENOCONV and a relative residual of
+    +inf, never with convergence."""
+    import torch
+    cloud = W.random_cloud(43, 60, box_lam=2.0, d_c_lam=1.0)
+    inc = W.azimuth_incidences(3)
+    say(f"[breakdown] {method}: NaN entry in one block, 60 wires, 3 RHS")
+    cl = B.build_cloud(cloud)
+    Z, P = B.fill_Z(cl, B.C64)
+    Z[0, 0, 0] = complex(float("nan"), 0.0)
+    torch.cuda.synchronize()
+    opts = B.solve_opts(tol=1e-6, method=B.COCG if method == "cocg" else B.GMRES, restart=50, max_cycles=3)
+    with pytest.raises(B.ChaffError) as err:
+        B.solve(cl, Z, P, inc.k_hat, inc.e_hat, opts)
+    assert err.value.status == B.ENOCONV and "breakdown" in str(err.value)
+    _, info = B.solve(cl, Z, P, inc.k_hat, inc.e_hat, opts, raise_on_noconv=False)
+    assert math.isinf(info["max_rel_residual"])
+    B.destroy(cl)
+
+
 def test_tangent_validation_on_device(B):
     bad = W.random_cloud(9, 20, box_lam=3.0, d_c_lam=1.0)
     bad.tangent[3] *= 1.01
