@@ -1,6 +1,6 @@
 """FP64 CPU oracle for the sparsified thin-wire MoM method (TEST INFRASTRUCTURE).
 
-This package is the independent reference that every GPU result is judged
+This package is the independent reference that every GPU result is checked
 against.  It is test infrastructure only: the product path never imports it;
 only the tests, the package smoke check and the benchmark's CPU-baseline leg
 may call it.  It shares no code with the HIP path (no kernels, headers,
